@@ -1,0 +1,161 @@
+"""The five benchmark/test problems, as plain input data.
+
+Each ``make_problem(name)`` call returns a dict of numpy arrays and scalars.
+Every value is either a constant stated by the problem definition or drawn
+from a seeded numpy PCG64 stream; no solver arithmetic happens here.
+
+Ionic parameter vectors (fixed order, shared by every consumer):
+
+* FHN  ``[k, a, eps, gamma]``       (FitzHugh-Nagumo, section 2.2)
+* AP   ``[k, a, eps0]``             (Aliev-Panfilov with mu1 = 0)
+* BO   ``BO_PARAM_NAMES`` below      (Bueno-Orovio, section 2.2 and the
+  appendix parameter table, time constants converted from s to ms)
+"""
+import numpy as np
+
+from .meshes import structured_mesh, cell_centroids, dof_nodes
+
+BO_PARAM_NAMES = [
+    "tau_o1", "tau_o2", "tau_so1", "tau_so2", "tau_si", "tau_fi",
+    "tau_1p", "tau_1m1", "tau_1m2", "tau_2m1", "tau_2m2", "tau_3m1", "tau_3m2",
+    "tau_2p", "tau_2inf", "k_2", "k_3", "k_so", "w_inf_star",
+    "V_1", "V_1m", "V_2", "V_2m", "V_3", "V_hat", "V_o", "V_so", "u_o",
+]
+
+# Appendix table of Bueno-Orovio parameters.  Time constants are printed in
+# seconds; the 3D workloads run in milliseconds, so every tau is multiplied by
+# 1e3 except tau_2inf, which divides a potential and is dimensionless.  Rows
+# duplicated in the printed table are taken once.  u_o = 0 makes the paper's
+# initial state (u = 0, w = (1, 1, 0)) a rest state of the so-current.
+BO_EPI = {
+    "tau_o1": 6.0, "tau_o2": 6.0, "tau_so1": 43.0, "tau_so2": 0.2,
+    "tau_si": 2.8723, "tau_fi": 0.11, "tau_1p": 1.4506, "tau_1m1": 60.0,
+    "tau_1m2": 1150.0, "tau_2m1": 70.0, "tau_2m2": 20.0, "tau_3m1": 2.7342,
+    "tau_3m2": 3.0, "tau_2p": 280.0, "tau_2inf": 0.07, "k_2": 65.0,
+    "k_3": 2.0994, "k_so": 2.0, "w_inf_star": 0.94, "V_1": 0.3,
+    "V_1m": 0.015, "V_2": 0.015, "V_2m": 0.03, "V_3": 0.9087, "V_hat": 1.58,
+    "V_o": 0.006, "V_so": 0.65, "u_o": 0.0,
+}
+
+MODEL_IDS = {"fhn": 0, "ap": 1, "bo": 2}
+N_GATES = {"fhn": 1, "ap": 1, "bo": 3}
+
+CONFIGS = {
+    # 32x32 Q1 unit square, FitzHugh-Nagumo, fixed penalty 10 p^2 / h
+    "c1": dict(dim=2, n=32, p=1, jitter=0.0, seed=None, group=[4],
+               sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=10,
+               model="fhn", params=[19.5, 0.13, 0.01, 0.5],
+               penalty=("fixed", 10.0 * 1 ** 2 * 32), ic="corner_disc",
+               stim=None, tol=1e-10),
+    # 256x256 jittered Q2, Aliev-Panfilov, three levels (4x4 grouping twice)
+    "c2": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
+               sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=100,
+               model="ap", params=[8.0, 0.15, 0.002],
+               penalty=("paper",), ic="corner_disc", stim=None, tol=1e-8),
+    # 64^3 Q2 cube, rotating fibres, Bueno-Orovio (ms), four levels (2x2x2)
+    "c3": dict(dim=3, n=64, p=2, jitter=0.0, seed=None, group=[2, 2, 2],
+               sigma=("fibre_z", 1.2e-3, 2.5e-4), chi=1.0, Cm=1.0, dt=5e-2,
+               steps=50, model="bo",
+               params=[BO_EPI[k] for k in BO_PARAM_NAMES],
+               penalty=("paper",), ic="rest", stim=("corner_block", 0.125, 0.3, 3.0),
+               tol=1e-8),
+    # adjoint problem: mesh and physics of c2, 50 steps
+    "c5": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
+               sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=50,
+               model="ap", params=[8.0, 0.15, 0.002],
+               penalty=("paper",), ic="corner_disc", stim=None, tol=1e-8,
+               sensors=(64, 2605), target_seed=2606),
+}
+
+
+def _conductivity(spec, centroids, dim):
+    """Per-cell symmetric conductivity, packed (xx, xy, yy) in 2D and
+    (xx, xy, xz, yy, yz, zz) in 3D."""
+    nc = centroids.shape[0]
+    if spec[0] == "iso":
+        s = spec[1]
+        if dim == 2:
+            return np.tile(np.array([s, 0.0, s]), (nc, 1))
+        return np.tile(np.array([s, 0.0, 0.0, s, 0.0, s]), (nc, 1))
+    if spec[0] == "fibre_z":
+        # D = sigma_t I + (sigma_l - sigma_t) f f^T, fibre angle rotating
+        # linearly from -60 to +60 degrees along z (sigma_n = sigma_t).
+        sl, st = spec[1], spec[2]
+        th = np.deg2rad(-60.0 + 120.0 * centroids[:, 2])
+        f = np.stack([np.cos(th), np.sin(th), np.zeros_like(th)], axis=1)
+        D = st * np.eye(3)[None] + (sl - st) * f[:, :, None] * f[:, None, :]
+        return np.stack([D[:, 0, 0], D[:, 0, 1], D[:, 0, 2],
+                         D[:, 1, 1], D[:, 1, 2], D[:, 2, 2]], axis=1)
+    raise ValueError(spec)
+
+
+def make_problem(name, n=None, steps=None, **overrides):
+    """Build the input arrays of a named problem.
+
+    ``n`` overrides the number of cells per axis (small variants for tests);
+    other keyword overrides replace config entries verbatim.
+    """
+    cfg = dict(CONFIGS[name])
+    cfg.update(overrides)
+    if n is not None:
+        if cfg["penalty"][0] == "fixed":
+            # keep "10 p^2 / h" meaningful when the mesh is resized
+            cfg["penalty"] = ("fixed", 10.0 * cfg["p"] ** 2 * n)
+        cfg["n"] = n
+        if "group" not in overrides:
+            # keep only the grouping factors the smaller grid can take
+            g, m = [], n
+            for f in cfg["group"]:
+                if m % f or m // f < 1:
+                    break
+                g.append(f)
+                m //= f
+            cfg["group"] = g
+    if steps is not None:
+        cfg["steps"] = steps
+    dim, p = cfg["dim"], cfg["p"]
+    xyz, cells = structured_mesh(dim, cfg["n"], cfg["jitter"], cfg["seed"])
+    cen = cell_centroids(xyz, cells)
+    nc = cells.shape[0]
+    b = (p + 1) ** dim
+    N = nc * b
+    S = N_GATES[cfg["model"]]
+    nodes = dof_nodes(xyz, cells, p).reshape(N, dim)
+    U0 = np.zeros(N)
+    W0 = np.zeros((S, N))
+    if cfg["ic"] == "corner_disc":
+        U0[np.linalg.norm(nodes, axis=1) < 0.1] = 1.0
+    elif cfg["ic"] == "rest":
+        if cfg["model"] == "bo":
+            W0[0] = 1.0
+            W0[1] = 1.0
+    stim_mask = np.zeros(nc, dtype=bool)
+    stim_amp, stim_tend = 0.0, 0.0
+    if cfg["stim"] is not None and cfg["stim"][0] == "corner_block":
+        _, edge, stim_amp, stim_tend = cfg["stim"]
+        stim_mask = np.all(cen < edge, axis=1)
+    prob = dict(cfg)
+    prob.update(name=name, xyz=xyz, cell_vtx=cells, n_cells=nc, b=b, N=N,
+                S=S, D_cell=_conductivity(cfg["sigma"], cen, dim),
+                U0=U0, W0=W0, stim_mask=stim_mask, stim_amp=stim_amp,
+                stim_tend=stim_tend, model_id=MODEL_IDS[cfg["model"]],
+                params=np.asarray(cfg["params"], dtype=np.float64),
+                node_xyz=nodes)
+    if "sensors" in cfg:
+        ns, seed = cfg["sensors"]
+        rng = np.random.default_rng(seed)
+        prob["sensor_cell"] = rng.integers(0, nc, size=ns).astype(np.int64)
+        prob["sensor_ref"] = rng.uniform(0.0, 1.0, size=(ns, dim))
+        rng2 = np.random.default_rng(cfg["target_seed"])
+        prob["s_true"] = np.exp(np.log(1.3) * rng2.standard_normal(nc))
+    return prob
+
+
+def iapp_nodal(prob, t):
+    """Applied current at DoF nodes at time t (piecewise constant per cell,
+    switched on while t <= t_end)."""
+    out = np.zeros(prob["N"])
+    if prob["stim_amp"] and t <= prob["stim_tend"] + 1e-12:
+        m = np.repeat(prob["stim_mask"], prob["b"])
+        out[m] = prob["stim_amp"]
+    return out
