@@ -1,0 +1,163 @@
+"""Benchmark: DoFs/s per semi-implicit time step of the SIPDG monodomain
+solver (ionic update + load vector + PCG with one agglomerated-multigrid
+V-cycle per iteration, to relative residual 1e-8) on one MI355X.
+
+Workload: [0,1]^2, 256x256 quadrilaterals with seeded +-0.2h nodal jitter,
+DG Q2 (589,824 DoFs), Aliev-Panfilov ionic model, three agglomerated levels
+(4x4 grouping twice), dt = 1e-2.  The headline value is the mixed-precision
+solver (FP32 V-cycle, FP64 outer PCG); the FP64 solver is reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoFs/s per time step (PCG+V-cycle to 1e-8), mixed vs FP64; iters; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def _stats(v):
+    import numpy as np
+    a = np.asarray(v, dtype=float)
+    return dict(mean=float(a.mean()), std=float(a.std()), min=int(a.min()), max=int(a.max()))
+
+
+def cheb_step_bytes(info, prec_bytes):
+    """Algorithmic bytes of one fused Chebyshev step on level 0: every cell
+    and face block once, the adjacency lists, and the vector streams
+    (gather d, x r/w, r r/w, D^-1, new d)."""
+    b = info["b"]
+    n, nf = info["n_cells"][0], info["n_faces"][0]
+    N = n * b
+    blocks = (n + nf) * b * b * prec_bytes
+    adjacency = 4 * (n + 1) + 2 * 2 * 4 * nf
+    vectors = 7 * prec_bytes * N
+    return blocks + adjacency + vectors
+
+
+def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None):
+    import numpy as np
+    import torch
+    from paper_2602_16312_amd import api, problem
+
+    t0 = time.perf_counter()
+    h, s = problem.build(pr, precision=precision)
+    setup_s = time.perf_counter() - t0
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()),
+                   dev(pr["W0"].ravel()),
+                   torch.empty(pr["N"], dtype=torch.float64, device="cuda"))
+    k = 0
+    for _ in range(warmup):
+        k += 1
+        api.time_step(s, st, k * pr["dt"], tol=tol)
+    torch.cuda.synchronize()
+    if profile_kind:
+        api.profile_begin(s, profile_kind, 0)
+    its = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        k += 1
+        r = api.time_step(s, st, k * pr["dt"], tol=tol)
+        its.append(r["its"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = api.profile_end(s) if profile_kind else None
+    return dict(wall=wall, its=its, setup_s=setup_s, info=s.info(), prof=prof,
+                U=st.U.cpu().numpy())
+
+
+def cpu_baseline(pr, tol, nsteps):
+    from oracle.stepper import Simulation
+    sim = Simulation(pr)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    _, _, stats = sim.run(nsteps, tol, record=False)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return dict(value=pr["N"] / (wall / nsteps), unit="DoFs/s", cores=max(1, round(cpu / wall)),
+                kind="oracle",
+                sample=f"first {nsteps} time steps of the same workload (scipy CSR PCG + "
+                       f"V-cycle, FP64, tol {tol}); oracle setup excluded; "
+                       f"its={[s['its'] for s in stats]}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "launches": 5}))
+        return
+
+    from workloads import make_problem
+    pr = make_problem("c2")
+    res = run_gpu(pr, "mixed", args.steps, args.warmup, args.tol, profile_kind="cheb_step")
+    ms = res["wall"] / args.steps * 1e3
+    value = pr["N"] / (res["wall"] / args.steps)
+    info = res["info"]
+    n_launch, kms = res["prof"]
+    per_launch_s = kms / max(1, n_launch) / 1e3
+    alg = cheb_step_bytes(info, 4)
+    achieved = alg / per_launch_s / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "DoFs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "256x256 jittered Q2 SIPDG monodomain, Aliev-Panfilov, "
+                               "3-level agglomerated V-cycle PCG to rel. residual 1e-8",
+                   "n_dofs": int(pr["N"]), "cells_per_level": info["n_cells"],
+                   "precision": "mixed: FP32 V-cycle, FP64 PCG and coarse solve",
+                   "dt": pr["dt"], "tol": args.tol},
+        "iters": _stats(res["its"]),
+        "setup_s": res["setup_s"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cheb_step<float,9> (level 0)",
+                     "alg_bytes_per_launch": alg, "avg_launch_us": per_launch_s * 1e6,
+                     "launches": n_launch},
+    }
+    if not args.no_fp64:
+        r64 = run_gpu(pr, "fp64", args.steps, args.warmup, args.tol)
+        out["fp64"] = {"value": pr["N"] / (r64["wall"] / args.steps),
+                       "ms_per_step": r64["wall"] / args.steps * 1e3,
+                       "iters": _stats(r64["its"])}
+        out["mixed_vs_fp64_rel_diff"] = float(np.abs(res["U"] - r64["U"]).max()
+                                              / np.abs(r64["U"]).max())
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, args.tol, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,252 @@
+/*
+ * dgmg.h -- C ABI of the MI355X agglomerated-multigrid PCG solver for the
+ * SIPDG-discretised monodomain equations (arXiv 2602.16312).
+ *
+ * The library solves, at every semi-implicit time step,
+ *     (3 chi C_m / (2 dt) M + A) U_{n+1} = I_app - chi M g + chi C_m/(2 dt) M (4 U_n - U_{n-1})
+ * (section 3.1, eq. fully_discrete, with ionic current interpolation) by PCG
+ * preconditioned with one V-cycle over a nested hierarchy of agglomerated
+ * polytopic levels (sections 4 and 5.1; section 6 for the smoother and the
+ * V-cycle settings).  All per-step work runs in hand-written gfx950 HIP
+ * kernels; setup (assembly, agglomeration, Galerkin products, eigenvalue
+ * estimates, coarse factorisation) runs in host C++.
+ *
+ * Conventions for every entry point:
+ *  - Return value: DGMG_OK (0), DGMG_NOT_CONVERGED (+1, outputs and stats
+ *    valid) or a negative error code; dgmg_last_error() then returns a
+ *    thread-local message.  No C++ exception crosses this boundary.
+ *  - "host" pointers are read during the call only; the library copies what
+ *    it keeps.  "device" pointers are HIP device memory owned by the caller
+ *    (e.g. torch tensors), contiguous, float64, and must stay valid until the
+ *    work enqueued on `stream` has completed.
+ *  - DG vectors are cell-major: DoF (K, i) lives at K*b + i, b = (p+1)^d, with
+ *    the local index i = i0 + (p+1) i1 + (p+1)^2 i2 of the tensor Lagrange
+ *    basis on Gauss-Lobatto nodes (x fastest).
+ *  - Opaque handles are owned by the library and freed with dgmg_destroy_*.
+ *    A solver is not thread-safe; calls that share a solver must be
+ *    serialised by the caller.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *    it; dgmg_pcg_solve and dgmg_time_step synchronise it once per PCG
+ *    iteration to read the residual norm for the stopping test.
+ */
+#ifndef DGMG_H
+#define DGMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGMG_OK 0
+#define DGMG_NOT_CONVERGED 1
+#define DGMG_EINVAL (-1)
+#define DGMG_ENOTSPD (-2)
+#define DGMG_ENAN (-3)
+#define DGMG_EHIP (-4)
+#define DGMG_ENOMEM (-5)
+#define DGMG_EUNSUPPORTED (-6)
+
+#define DGMG_MAX_LEVELS 8
+
+typedef struct dgmg_hierarchy dgmg_hierarchy;
+typedef struct dgmg_solver dgmg_solver;
+
+/* Quadrilateral (dim 2) or hexahedral (dim 3) mesh (section 3: shape-regular
+ * quad/hex triangulation).  host xyz: n_vert x dim row-major.  host
+ * cell_vtx: n_cells x 2^dim vertex ids, corner c = c0 + 2 c1 + 4 c2 at
+ * reference point (c0, c1, c2).  Face neighbours must share their face with
+ * identical tangential orientation (checked; DGMG_EUNSUPPORTED otherwise). */
+typedef struct {
+    int32_t dim;
+    int64_t n_vert;
+    const double* xyz;
+    int64_t n_cells;
+    const int64_t* cell_vtx;
+} dgmg_mesh;
+
+enum { DGMG_AGGLO_GRID = 0, DGMG_AGGLO_RTREE_STR = 1, DGMG_AGGLO_USER = 2 };
+
+/* Agglomeration options (section 4).  n_levels counts the fine mesh too.
+ *  GRID:       level l >= 1 groups the fine cells whose centroids (vertex
+ *              averages) fall in the same bin of a grid_bins[l][0..dim-1]
+ *              grid over the mesh bounding box; bins must nest across levels.
+ *  RTREE_STR:  bulk-loaded (sort-tile-recursive) R-tree of fanout
+ *              rtree_fanout over the cells' bounding boxes; level l gathers the
+ *              leaves below each tree node l levels above the leaves
+ *              (Algorithms 1 and 2).
+ *  USER:       host user_parents[l-1][e] = level-l id of level-(l-1) entity e. */
+typedef struct {
+    int32_t n_levels;
+    int32_t method;
+    int32_t grid_bins[DGMG_MAX_LEVELS][3];
+    int32_t rtree_fanout;
+    const int64_t* const* user_parents;
+} dgmg_agglo_opts;
+
+/* Builds the nested agglomerated hierarchy {T_l} (host only, no device work).
+ * Errors: DGMG_EINVAL for bad sizes, empty agglomerates or a non-nested
+ * partition; DGMG_ENOMEM. */
+int dgmg_build_hierarchy(const dgmg_mesh* mesh, const dgmg_agglo_opts* opts,
+                         dgmg_hierarchy** out);
+/* Number of levels, and the number of entities on `level`. */
+int dgmg_hierarchy_info(const dgmg_hierarchy* h, int32_t level, int32_t* n_levels,
+                        int64_t* n_entities);
+/* host out: n_entities(level) parent ids on level+1. */
+int dgmg_hierarchy_parents(const dgmg_hierarchy* h, int32_t level, int64_t* out);
+void dgmg_destroy_hierarchy(dgmg_hierarchy* h);
+
+enum { DGMG_PENALTY_PAPER = 0, DGMG_PENALTY_FIXED = 1 };
+/* Discretisation (section 3): tensor Q_p, 1 <= p <= 3.  Penalty on an
+ * interior face: sigma = eta_F * mean(n^T D+ n, n^T D- n) with
+ * eta_F = c p(p+1) mean(|F|/|K+|, |F|/|K-|) (PAPER; c = `eta` if > 0, else
+ * the paper's c = 1) or eta_F = `eta` (FIXED). */
+typedef struct {
+    int32_t p;
+    int32_t penalty_mode;
+    double eta;
+} dgmg_disc;
+
+enum { DGMG_MODEL_FHN = 0, DGMG_MODEL_AP = 1, DGMG_MODEL_BO = 2 };
+/* Physics (section 2): chi_m, C_m, time step, BDF order (2, or 1 for
+ * backward Euler), host D_cell: n_cells x d(d+1)/2 packed symmetric
+ * conductivity (xx,xy,yy | xx,xy,xz,yy,yz,zz), host cell_scale: n_cells
+ * multipliers of D_K or NULL, ionic model id and its parameter vector
+ * (FHN [k,a,eps,Gamma]; AP [k,a,eps0]; BO 28 values in the order documented
+ * with the Python binding). */
+typedef struct {
+    double chi, Cm, dt;
+    int32_t bdf;
+    const double* D_cell;
+    const double* cell_scale;
+    int32_t model;
+    int32_t n_params;
+    const double* params;
+} dgmg_physics;
+
+enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
+/* Multigrid options (section 6): Chebyshev-Jacobi degree and number of
+ * pre/post sweeps, Lanczos steps, lambda_hi = lam_safety * theta_max,
+ * lambda_lo = lambda_hi / smooth_range; host lam_override (NULL or 2 values
+ * (lo, hi) per smoothed level) replaces the estimate.  precision MIXED runs
+ * the V-cycle in FP32 with the coarse solve and the outer PCG in FP64.
+ * device_setup = 0 stops after the host setup (inspection on machines
+ * without a GPU; solve calls then fail with DGMG_EINVAL). */
+typedef struct {
+    int32_t cheb_degree;
+    int32_t cheb_sweeps;
+    int32_t lanczos_steps;
+    double lam_safety;
+    double smooth_range;
+    const double* lam_override;
+    int32_t precision;
+    int32_t device_setup;
+} dgmg_mg_opts;
+
+/* Assembles A_0 = 3 chi C_m/(2 dt) M + A (eq. fully_discrete; bdf = 1 uses
+ * chi C_m/dt), the prolongations, the Galerkin operators A_{l+1} = P^T A_l P
+ * (eq. inherited_matrices, Algorithm 3), the smoother data and the dense
+ * Cholesky factor of the coarsest operator, and uploads them.  Errors:
+ * DGMG_EINVAL (non-positive Jacobian, bad options), DGMG_ENOTSPD (coarse
+ * pivot <= 0), DGMG_EUNSUPPORTED (dim, p), DGMG_EHIP, DGMG_ENOMEM. */
+int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc,
+                      const dgmg_physics* phys, const dgmg_mg_opts* mg,
+                      dgmg_solver** out);
+void dgmg_destroy_solver(dgmg_solver* s);
+
+/* Solver description.  host out arrays sized DGMG_MAX_LEVELS. */
+typedef struct {
+    int32_t dim, p, b, n_levels, precision, model, n_gates;
+    int64_t n_dofs;
+    int64_t n_cells[DGMG_MAX_LEVELS];
+    int64_t n_faces[DGMG_MAX_LEVELS];
+    double lam_lo[DGMG_MAX_LEVELS], lam_hi[DGMG_MAX_LEVELS];
+    double op_complexity;
+    double t_assembly, t_hierarchy, t_transfer, t_galerkin, t_smoother, t_coarse, t_upload;
+    int64_t device_bytes;
+} dgmg_solver_info;
+int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info);
+
+enum { DGMG_TOL_REL_R0 = 0, DGMG_TOL_REL_B = 1, DGMG_TOL_ABS = 2 };
+typedef struct {
+    double tol;
+    int32_t tol_mode;
+    int32_t max_it;
+    int32_t flexible; /* 1: beta = (r_new, z_new - z_old)/(r_old, z_old) */
+} dgmg_pcg_opts;
+typedef struct {
+    int32_t its;      /* A_0 applications inside the loop */
+    int32_t converged;
+    double r0, rfin;  /* ||b - A x||_2 at start and end */
+} dgmg_pcg_stats;
+
+/* PCG on A_0 x = b with one V-cycle per iteration (section 6; section 3.1).
+ * device b (N), device x (N; in: initial guess, out: solution).  Stops when
+ * ||r_k|| <= tol * ||r_0|| (REL_R0), tol * ||b|| (REL_B) or tol (ABS).
+ * Errors: DGMG_ENOTSPD on (p, A p) <= 0 or (r, z) <= 0, DGMG_ENAN on a
+ * non-finite residual, DGMG_NOT_CONVERGED after max_it. */
+int dgmg_pcg_solve(dgmg_solver* s, const double* b, double* x,
+                   const dgmg_pcg_opts* opts, dgmg_pcg_stats* stats, void* stream);
+
+/* Ionic update at every DoF (section 3.1; models of section 2.2): with
+ * U* = 2 U - Uprev (BDF2) or U (bdf 1), writes the BDF2 gate update
+ * Wnext = (4 W - Wprev + 2 dt c0(U*)) / (3 - 2 dt c1(U*)) for dw/dt = c1 w + c0
+ * and g = I_ion(U*, Wnext).  device U, Uprev, g: N; W, Wprev, Wnext: S x N
+ * (gate-major).  Wnext may alias Wprev. */
+int dgmg_ionic_step(dgmg_solver* s, const double* U, const double* Uprev,
+                    const double* W, const double* Wprev, double* Wnext,
+                    double* g, void* stream);
+
+/* Caller-owned state of the two-step scheme (device buffers). */
+typedef struct {
+    double* U;      /* U_n,     N     */
+    double* Uprev;  /* U_{n-1}, N     */
+    double* W;      /* W_n,     S x N */
+    double* Wprev;  /* W_{n-1}, S x N */
+    double* g;      /* workspace, N   */
+} dgmg_state;
+
+/* One time step t_n -> t_next (section 3.1): ionic update, load vector
+ * M f with f = chi C_m/(2 dt)(4 U_n - U_{n-1}) + I_app - chi g (ICI), PCG
+ * warm-started from U_n.  device iapp: N nodal applied current or NULL.  On
+ * return the pointer pairs of *state are rotated: U holds U_{n+1}, Uprev
+ * U_n, W holds W_{n+1}, Wprev W_n (no data is copied).  Errors as for
+ * dgmg_pcg_solve. */
+int dgmg_time_step(dgmg_solver* s, dgmg_state* state, double t_next,
+                   const double* iapp, const dgmg_pcg_opts* opts,
+                   dgmg_pcg_stats* stats, void* stream);
+
+/* ---- operator-level entry points (parity tests, adjoint driver) ---- */
+
+/* y = A_level x.  prec selects the stored FP64 or FP32 copy of the level
+ * (FP32 exists for every level in MIXED mode); device x, y: N_level float64. */
+int dgmg_apply(dgmg_solver* s, int32_t level, int32_t prec, const double* x,
+               double* y, void* stream);
+/* z = B r, one V-cycle in the solver's precision mode; device r, z: N. */
+int dgmg_vcycle(dgmg_solver* s, const double* r, double* z, void* stream);
+/* b = M f per cell (the ICI load vector); device f, b: N. */
+int dgmg_mass_apply(dgmg_solver* s, const double* f, double* b, void* stream);
+
+/* Host copies of a level's FP64 operator: diag (n_cells x b x b, row-major
+ * blocks), faces as (plus, minus) cell pairs and blocks A(plus rows, minus
+ * cols), prolongation blocks to this level from level+1 (n_cells x b x b) and
+ * parents.  Any out pointer may be NULL; sizes from dgmg_get_info. */
+int dgmg_export_level(const dgmg_solver* s, int32_t level, double* diag,
+                      int64_t* face_cells, double* face_blocks, double* prolong,
+                      int64_t* parents);
+
+/* Kernel timing with HIP events recorded on the caller's stream around every
+ * launch of one kernel kind on one level, between begin and end: kind 0 the
+ * fused Chebyshev step, 1 the fused residual, 2 the plain/dot apply, 3 the
+ * restriction (level = fine level), 4 the prolongation (level = fine level),
+ * 5 the coarse solve (level ignored).  end waits for the recorded events and
+ * returns the number of launches and their summed duration in ms. */
+int dgmg_profile_begin(dgmg_solver* s, int32_t kind, int32_t level);
+int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms);
+
+const char* dgmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGMG_H */

@@ -5,9 +5,11 @@ eq. (matrices); penalty definition right after a_h).
 Readings of the paper used here (listed in the design notes):
 * the penalty term enters a_h with a plus sign (standard symmetric interior
   penalty); the printed form puts it under the minus, which is indefinite;
-* on an interior face F between K+ and K-, alpha = p(p+1) * mean(|F|/|K+|,
-  |F|/|K-|) and sigma = alpha * mean(n^T D+ n, n^T D- n), evaluated at every
-  face quadrature point; a fixed eta replaces alpha when requested;
+* on an interior face F between K+ and K-, alpha = c * p(p+1) *
+  mean(|F|/|K+|, |F|/|K-|) and sigma = alpha * mean(n^T D+ n, n^T D- n),
+  evaluated at every face quadrature point; c = 1 is the paper's value, a
+  larger c is a safety factor for strongly distorted meshes; a fixed eta
+  replaces alpha when requested;
 * boundary faces contribute nothing (homogeneous Neumann);
 * D is constant per cell (input), optionally scaled per cell by s_K; each
   side of a face uses its own scaled tensor;
@@ -140,7 +142,8 @@ def face_matrices(Xp, Xm, Dp, Dm, axis, volp, volm, p, penalty):
     nDn = 0.5 * (np.einsum("fqa,fab,fqb->fq", n, Dp, n)
                  + np.einsum("fqa,fab,fqb->fq", n, Dm, n))
     if penalty[0] == "paper":
-        eta = p * (p + 1) * 0.5 * (area / volp + area / volm)
+        c = float(penalty[1]) if len(penalty) > 1 else 1.0
+        eta = c * p * (p + 1) * 0.5 * (area / volp + area / volm)
     else:
         eta = np.full(Xp.shape[0], float(penalty[1]))
     sig = eta[:, None] * nDn                              # [nf, nq]

@@ -1,0 +1,869 @@
+// Device solver: level upload, V-cycle, PCG, time step and the C ABI.
+//
+// V-cycle (section 6: one V-cycle per PCG iteration, Chebyshev-accelerated
+// Jacobi of degree k with s pre- and post-smoothing sweeps; section 5.1:
+// prolongation by the natural embedding, restriction by its transpose,
+// Galerkin level operators): on level l < L-1
+//   x = Cheb(b, 0); r = b - A x; e = V(P^T r); x += P e; x = Cheb(b, x)
+// and the coarsest level is solved exactly with the FP64 inverse of its
+// Cholesky-factorised operator.  Chebyshev (Saad's preconditioned Chebyshev
+// acceleration, D = diag(A_l)) restarts s times from the true residual; the
+// last "x += d" of a sweep is carried as a pending correction and fused into
+// the next kernel that reads x.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <vector>
+
+#include "internal.hpp"
+#include "ionic.hpp"
+#include "kernels.hpp"
+
+namespace dgmg {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& m) { g_last_error = m; }
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            fail(DGMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+#define DISPATCH_B(bval, ...)                                                          \
+    switch (bval) {                                                                    \
+        case 4: { constexpr int BV = 4; __VA_ARGS__; } break;                          \
+        case 8: { constexpr int BV = 8; __VA_ARGS__; } break;                          \
+        case 9: { constexpr int BV = 9; __VA_ARGS__; } break;                          \
+        case 16: { constexpr int BV = 16; __VA_ARGS__; } break;                        \
+        case 27: { constexpr int BV = 27; __VA_ARGS__; } break;                        \
+        case 64: { constexpr int BV = 64; __VA_ARGS__; } break;                        \
+        default: fail(DGMG_EUNSUPPORTED, "unsupported block size");                    \
+    }
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kWG - 1) / kWG); }
+
+struct DevLevel {
+    int32_t n = 0, nf = 0;
+    int64_t N = 0;
+    int32_t *nbr_ptr = nullptr, *nbr_cell = nullptr, *nbr_code = nullptr;
+    int32_t *child_ptr = nullptr, *child_list = nullptr;  // children on level l-1
+    int32_t* parent = nullptr;                             // parent on level l+1
+    double *diag64 = nullptr, *fblk64 = nullptr, *dinv64 = nullptr, *P64 = nullptr;
+    float *diag32 = nullptr, *fblk32 = nullptr, *dinv32 = nullptr, *P32 = nullptr;
+    void *vb = nullptr, *vx = nullptr, *vx2 = nullptr, *vr = nullptr, *vd = nullptr, *vd2 = nullptr;
+    double lam_lo = 0, lam_hi = 0;
+};
+
+}  // namespace dgmg
+
+using namespace dgmg;
+
+struct dgmg_hierarchy : public Hierarchy {};
+
+struct dgmg_solver {
+    int dim = 0, p = 0, b = 0, L = 0, prec = 0, S = 1, bdf = 2;
+    int cheb_k = 3, cheb_s = 3;
+    int64_t N = 0;
+    bool on_device = false;
+    std::vector<DevLevel> lv;
+    // coarse
+    int64_t nc_dofs = 0;
+    double* Ainv = nullptr;
+    double* cpart = nullptr;
+    int nchunk = 1, rows_per_chunk = 1;
+    // outer PCG work
+    double *r = nullptr, *z = nullptr, *zold = nullptr, *pv = nullptr, *q = nullptr, *bwork = nullptr;
+    double *tmp64a = nullptr, *tmp64b = nullptr;
+    double* partial = nullptr;
+    double* sc = nullptr;
+    double* sc_host = nullptr;
+    double* mass = nullptr;
+    IonicParams ip{};
+    double cU = 0.0;
+    std::vector<void*> allocs;
+    int64_t dev_bytes = 0;
+    // host copies
+    std::vector<BlockOp> ops;
+    std::vector<std::vector<double>> Ph;
+    std::vector<std::vector<int64_t>> parents;
+    std::vector<double> mass_h;
+    dgmg_solver_info info{};
+    // kernel timing with HIP events (one kernel kind on one level at a time)
+    int prof_kind = -1, prof_level = -1;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    size_t prof_used = 0;
+
+    template <typename T>
+    T* dalloc(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) fail(DGMG_ENOMEM, "hipMalloc failed");
+        allocs.push_back(p);
+        dev_bytes += (int64_t)(count * sizeof(T));
+        return (T*)p;
+    }
+    template <typename T>
+    T* upload(const std::vector<T>& h) {
+        T* d = dalloc<T>(h.size());
+        HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+        return d;
+    }
+    ~dgmg_solver() {
+        for (auto& e : prof_ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        for (void* p : allocs) (void)hipFree(p);
+        if (sc_host) (void)hipHostFree(sc_host);
+    }
+};
+
+namespace dgmg {
+
+// row-major b x b blocks -> column-major, optionally converted
+template <typename T>
+static std::vector<T> to_colmajor(const std::vector<double>& a, int b) {
+    const size_t bb = (size_t)b * b, nblk = a.size() / bb;
+    std::vector<T> out(a.size());
+    for (size_t k = 0; k < nblk; ++k)
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j) out[k * bb + (size_t)j * b + i] = (T)a[k * bb + (size_t)i * b + j];
+    return out;
+}
+
+template <typename T>
+static LevelArgs<T> largs(const DevLevel& L);
+template <>
+LevelArgs<double> largs<double>(const DevLevel& L) {
+    return {L.diag64, L.fblk64, L.dinv64, L.nbr_ptr, L.nbr_cell, L.nbr_code, L.n};
+}
+template <>
+LevelArgs<float> largs<float>(const DevLevel& L) {
+    return {L.diag32, L.fblk32, L.dinv32, L.nbr_ptr, L.nbr_cell, L.nbr_code, L.n};
+}
+template <typename T>
+static const T* Pof(const DevLevel& L);
+template <>
+const double* Pof<double>(const DevLevel& L) { return L.P64; }
+template <>
+const float* Pof<float>(const DevLevel& L) { return L.P32; }
+
+// Brackets one launch with a pair of events when that kernel kind/level is
+// being timed (see dgmg_profile_begin).
+struct ProfScope {
+    dgmg_solver* s;
+    hipStream_t st;
+    bool on = false;
+    size_t idx = 0;
+    ProfScope(dgmg_solver* s_, int kind, int level, hipStream_t st_) : s(s_), st(st_) {
+        if (s->prof_kind != kind || s->prof_level != level) return;
+        if (s->prof_used == s->prof_ev.size()) {
+            hipEvent_t a, b;
+            HIPCHK(hipEventCreate(&a));
+            HIPCHK(hipEventCreate(&b));
+            s->prof_ev.push_back({a, b});
+        }
+        idx = s->prof_used++;
+        on = true;
+        HIPCHK(hipEventRecord(s->prof_ev[idx].first, st));
+    }
+    ~ProfScope() {
+        if (on) (void)hipEventRecord(s->prof_ev[idx].second, st);
+    }
+};
+enum { PK_CHEB_STEP = 0, PK_RESIDUAL = 1, PK_APPLY = 2, PK_RESTRICT = 3, PK_PROLONG = 4,
+       PK_COARSE = 5 };
+
+static int level_index(const dgmg_solver* s, const DevLevel& L) { return (int)(&L - s->lv.data()); }
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, T* y,
+                         const T* w, double* partial, hipStream_t st) {
+    ProfScope ps(s, PK_APPLY, level_index(s, L), st);
+    DISPATCH_B(s->b, k_apply<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(largs<T>(L), va, vb, y, w, partial));
+}
+template <typename T>
+static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, const T* rhs,
+                            T* r, T* d, T c1, T* xout, double* partial, hipStream_t st) {
+    ProfScope ps(s, PK_RESIDUAL, level_index(s, L), st);
+    DISPATCH_B(s->b, k_residual<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(largs<T>(L), va, vb, rhs, r, d,
+                                                                         c1, xout, partial));
+}
+template <typename T>
+static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* r, T* dn, T cd, T cr,
+                        int assign, hipStream_t st) {
+    ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
+    DISPATCH_B(s->b, k_cheb_step<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(largs<T>(L), d, x, r, dn, cd, cr,
+                                                                          assign));
+}
+
+template <typename T>
+static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
+    const int n = (int)s->nc_dofs;
+    ProfScope ps(s, PK_COARSE, s->L - 1, st);
+    dim3 g(blocks_for(n), s->nchunk);
+    k_coarse_gemv<T><<<g, kWG, 0, st>>>(n, s->rows_per_chunk, s->Ainv, rc, s->cpart);
+    k_coarse_reduce<T><<<blocks_for(n), kWG, 0, st>>>(n, s->nchunk, s->cpart, xc);
+}
+
+// One V-cycle from level l; the result is x + d (d may be null).
+template <typename T>
+static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
+    DevLevel& L = s->lv[l];
+    T* b = (T*)L.vb;
+    if (l == s->L - 1) {
+        coarse_solve<T>(s, b, (T*)L.vx, st);
+        *xres = (T*)L.vx;
+        *dres = nullptr;
+        return;
+    }
+    const double theta = 0.5 * (L.lam_hi + L.lam_lo), delta = 0.5 * (L.lam_hi - L.lam_lo);
+    const double sigma1 = theta / delta;
+    const T c1 = (T)(1.0 / theta);
+    T *x = (T*)L.vx, *x2 = (T*)L.vx2, *r = (T*)L.vr, *d = (T*)L.vd, *d2 = (T*)L.vd2;
+    bool xzero = true, pending = false;
+    const T* dinv = largs<T>(L).dinv;
+    auto sweep = [&]() {
+        if (xzero && !pending) {
+            k_cheb_init0<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, b, dinv, r, d, c1);
+        } else if (pending) {
+            // r = b - A(x + d), materialise x + d into x2
+            launch_residual<T>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, d2, c1, x2, nullptr, st);
+            std::swap(x, x2);
+            std::swap(d, d2);
+            xzero = false;
+        } else {
+            launch_residual<T>(s, L, x, (const T*)nullptr, b, r, d, c1, (T*)nullptr, nullptr, st);
+        }
+        double rho = 1.0 / sigma1;
+        for (int i = 1; i < s->cheb_k; ++i) {
+            const double rn = 1.0 / (2.0 * sigma1 - rho);
+            launch_step<T>(s, L, d, x, r, d2, (T)(rn * rho), (T)(2.0 * rn / delta), xzero ? 1 : 0, st);
+            xzero = false;
+            std::swap(d, d2);
+            rho = rn;
+        }
+        pending = true;
+    };
+    for (int k = 0; k < s->cheb_s; ++k) sweep();
+    // residual for the coarse correction, materialising the pending update
+    DevLevel& C = s->lv[l + 1];
+    if (pending) {
+        launch_residual<T>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, (T*)nullptr, c1, x2, nullptr, st);
+        std::swap(x, x2);
+        xzero = false;
+        pending = false;
+    } else if (xzero) {
+        hipMemcpyAsync(r, b, L.N * sizeof(T), hipMemcpyDeviceToDevice, st);
+    } else {
+        launch_residual<T>(s, L, x, (const T*)nullptr, b, r, (T*)nullptr, c1, (T*)nullptr, nullptr, st);
+    }
+    {
+    ProfScope ps(s, PK_RESTRICT, l, st);
+    DISPATCH_B(s->b, k_restrict<T, BV><<<blocks_for(C.N), kWG, 0, st>>>(C.n, C.child_ptr, C.child_list,
+                                                                         Pof<T>(L), r, (T*)C.vb));
+    }
+    T *xc, *dc;
+    vcycle<T>(s, l + 1, st, &xc, &dc);
+    if (xzero) {
+        hipMemsetAsync(x, 0, L.N * sizeof(T), st);
+        xzero = false;
+    }
+    {
+    ProfScope ps(s, PK_PROLONG, l, st);
+    DISPATCH_B(s->b, k_prolong_add<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(L.n, L.parent, Pof<T>(L), xc,
+                                                                             dc, x));
+    }
+    for (int k = 0; k < s->cheb_s; ++k) sweep();
+    // hand back the level's buffers as they are now named
+    L.vx = x;
+    L.vx2 = x2;
+    L.vd = d;
+    L.vd2 = d2;
+    *xres = x;
+    *dres = pending ? d : nullptr;
+}
+
+// z = V(r), r and z FP64 of length N.
+static void apply_vcycle(dgmg_solver* s, const double* r, double* z, hipStream_t st) {
+    DevLevel& L0 = s->lv[0];
+    if (s->prec == DGMG_PREC_FP64) {
+        L0.vb = (void*)r;
+        double *x, *d;
+        vcycle<double>(s, 0, st, &x, &d);
+        k_cast<double, double><<<blocks_for(s->N), kWG, 0, st>>>(s->N, x, d, z);
+    } else {
+        k_cast<double, float><<<blocks_for(s->N), kWG, 0, st>>>(s->N, r, nullptr, (float*)L0.vb);
+        float *x, *d;
+        vcycle<float>(s, 0, st, &x, &d);
+        k_cast<float, double><<<blocks_for(s->N), kWG, 0, st>>>(s->N, x, d, z);
+    }
+}
+
+static double read_scalars(dgmg_solver* s, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(s->sc_host, s->sc, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return s->sc_host[0];
+}
+
+static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& o, dgmg_pcg_stats* stats,
+               hipStream_t st) {
+    const int64_t N = s->N;
+    const unsigned nb = blocks_for(N);
+    DevLevel& L0 = s->lv[0];
+    // r = b - A x, ||r||^2
+    launch_residual<double>(s, L0, x, nullptr, b, s->r, nullptr, 1.0, nullptr, s->partial, st);
+    k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 0, 0);
+    double bnorm = 0.0;
+    if (o.tol_mode == DGMG_TOL_REL_B) {
+        k_dot<<<nb, kWG, 0, st>>>(N, b, b, s->partial);
+        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 6, 0);
+    }
+    read_scalars(s, st);
+    const double r0 = std::sqrt(s->sc_host[0]);
+    if (o.tol_mode == DGMG_TOL_REL_B) bnorm = std::sqrt(s->sc_host[6]);
+    if (!std::isfinite(r0)) fail(DGMG_ENAN, "non-finite initial residual");
+    const double thresh = o.tol_mode == DGMG_TOL_ABS ? o.tol : (o.tol_mode == DGMG_TOL_REL_B ? o.tol * bnorm : o.tol * r0);
+    stats->its = 0;
+    stats->r0 = r0;
+    stats->rfin = r0;
+    stats->converged = 0;
+    if (r0 == 0.0 || r0 <= thresh) {
+        stats->converged = 1;
+        return DGMG_OK;
+    }
+    apply_vcycle(s, s->r, s->z, st);
+    k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
+    k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 1, 0);
+    k_update_p<<<nb, kWG, 0, st>>>(N, s->sc, s->z, s->pv, 1);
+    int its = 0;
+    while (its < o.max_it) {
+        launch_apply<double>(s, L0, s->pv, nullptr, s->q, s->pv, s->partial, st);
+        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 2, 0);
+        k_update_xr<<<nb, kWG, 0, st>>>(N, s->sc, s->pv, s->q, x, s->r, s->partial);
+        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 0, 0);
+        read_scalars(s, st);
+        ++its;
+        const double gam = s->sc_host[1], pq = s->sc_host[2];
+        const double rn = std::sqrt(s->sc_host[0]);
+        stats->its = its;
+        stats->rfin = rn;
+        if (!(pq > 0.0) || !(gam > 0.0)) {
+            if (!std::isfinite(pq) || !std::isfinite(gam)) fail(DGMG_ENAN, "non-finite PCG scalar");
+            fail(DGMG_ENOTSPD, "PCG breakdown: (p, A p) <= 0 or (r, z) <= 0");
+        }
+        if (!std::isfinite(rn)) fail(DGMG_ENAN, "non-finite residual");
+        if (rn <= thresh) {
+            stats->converged = 1;
+            return DGMG_OK;
+        }
+        if (o.flexible) std::swap(s->z, s->zold);
+        apply_vcycle(s, s->r, s->z, st);
+        if (o.flexible) {
+            k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->zold, s->partial);
+            k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 5, 0);
+        }
+        k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
+        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 3, o.flexible ? 2 : 1);
+        k_update_p<<<nb, kWG, 0, st>>>(N, s->sc, s->z, s->pv, 0);
+    }
+    return DGMG_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------------ setup
+static void build_nbr(const BlockOp& A, std::vector<int32_t>& ptr, std::vector<int32_t>& cell,
+                      std::vector<int32_t>& code) {
+    ptr.assign(A.n + 1, 0);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        ptr[A.fc[2 * f] + 1]++;
+        ptr[A.fc[2 * f + 1] + 1]++;
+    }
+    for (int64_t K = 0; K < A.n; ++K) ptr[K + 1] += ptr[K];
+    cell.assign(ptr[A.n], 0);
+    code.assign(ptr[A.n], 0);
+    std::vector<int32_t> pos(ptr.begin(), ptr.end() - 1);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        const int64_t p = A.fc[2 * f], m = A.fc[2 * f + 1];
+        cell[pos[p]] = (int32_t)m;
+        code[pos[p]++] = (int32_t)(f << 1);
+        cell[pos[m]] = (int32_t)p;
+        code[pos[m]++] = (int32_t)((f << 1) | 1);
+    }
+}
+
+static void upload_level(dgmg_solver* s, int l) {
+    const BlockOp& A = s->ops[l];
+    DevLevel& L = s->lv[l];
+    const int b = s->b;
+    L.n = (int32_t)A.n;
+    L.nf = (int32_t)A.nf;
+    L.N = A.n * b;
+    std::vector<int32_t> ptr, cell, code;
+    build_nbr(A, ptr, cell, code);
+    L.nbr_ptr = s->upload(ptr);
+    L.nbr_cell = s->upload(cell);
+    L.nbr_code = s->upload(code);
+    std::vector<double> dinv(L.N);
+    for (int64_t K = 0; K < A.n; ++K)
+        for (int i = 0; i < b; ++i) dinv[K * b + i] = 1.0 / A.diag[((size_t)K * b + i) * b + i];
+    const bool last = (l == s->L - 1);
+    if (!last || s->L == 1) {
+        L.diag64 = s->upload(to_colmajor<double>(A.diag, b));
+        L.fblk64 = s->upload(to_colmajor<double>(A.fblk, b));
+        L.dinv64 = s->upload(dinv);
+        if (s->prec == DGMG_PREC_MIXED) {
+            L.diag32 = s->upload(to_colmajor<float>(A.diag, b));
+            L.fblk32 = s->upload(to_colmajor<float>(A.fblk, b));
+            std::vector<float> df(dinv.begin(), dinv.end());
+            L.dinv32 = s->upload(df);
+        }
+    }
+    if (!last) {
+        std::vector<int32_t> par(s->parents[l].begin(), s->parents[l].end());
+        L.parent = s->upload(par);
+        L.P64 = s->upload(to_colmajor<double>(s->Ph[l], b));
+        if (s->prec == DGMG_PREC_MIXED) L.P32 = s->upload(to_colmajor<float>(s->Ph[l], b));
+    }
+    if (l > 0) {
+        const auto& par = s->parents[l - 1];
+        std::vector<int32_t> cp(A.n + 1, 0), cl(par.size());
+        for (auto K : par) cp[K + 1]++;
+        for (int64_t K = 0; K < A.n; ++K) cp[K + 1] += cp[K];
+        std::vector<int32_t> pos(cp.begin(), cp.end() - 1);
+        for (size_t e = 0; e < par.size(); ++e) cl[pos[par[e]]++] = (int32_t)e;
+        L.child_ptr = s->upload(cp);
+        L.child_list = s->upload(cl);
+    }
+    const size_t es = s->prec == DGMG_PREC_MIXED ? sizeof(float) : sizeof(double);
+    auto vec = [&]() -> void* { return (void*)s->dalloc<char>(L.N * es); };
+    L.vb = vec(); L.vx = vec(); L.vx2 = vec(); L.vr = vec(); L.vd = vec(); L.vd2 = vec();
+}
+
+}  // namespace dgmg
+
+// ====================================================================== C ABI
+#define API_BEGIN try {
+#define API_END                                                          \
+    }                                                                    \
+    catch (const Error& e) {                                             \
+        set_last_error(e.msg);                                           \
+        return e.code;                                                   \
+    }                                                                    \
+    catch (const std::bad_alloc&) {                                      \
+        set_last_error("out of host memory");                            \
+        return DGMG_ENOMEM;                                              \
+    }                                                                    \
+    catch (const std::exception& e) {                                    \
+        set_last_error(e.what());                                        \
+        return DGMG_EINVAL;                                              \
+    }
+
+extern "C" {
+
+const char* dgmg_last_error(void) { return g_last_error.c_str(); }
+
+int dgmg_build_hierarchy(const dgmg_mesh* m, const dgmg_agglo_opts* o, dgmg_hierarchy** out) {
+    API_BEGIN
+    if (!m || !o || !out || !m->xyz || !m->cell_vtx) fail(DGMG_EINVAL, "null argument");
+    if (m->dim != 2 && m->dim != 3) fail(DGMG_EUNSUPPORTED, "dimension must be 2 or 3");
+    if (m->n_cells <= 0 || m->n_vert <= 0) fail(DGMG_EINVAL, "empty mesh");
+    if (o->n_levels < 1 || o->n_levels > DGMG_MAX_LEVELS) fail(DGMG_EINVAL, "bad number of levels");
+    auto* h = new dgmg_hierarchy();
+    std::unique_ptr<dgmg_hierarchy> guard(h);
+    const int d = m->dim, nc = 1 << d;
+    h->dim = d;
+    h->n_vert = m->n_vert;
+    h->n_cells = m->n_cells;
+    h->xyz.assign(m->xyz, m->xyz + (size_t)m->n_vert * d);
+    h->cells.assign(m->cell_vtx, m->cell_vtx + (size_t)m->n_cells * nc);
+    for (auto v : h->cells)
+        if (v < 0 || v >= m->n_vert) fail(DGMG_EINVAL, "vertex id out of range");
+    h->n_levels = o->n_levels;
+    h->n_ent.assign(1, m->n_cells);
+    if (o->method == DGMG_AGGLO_GRID) {
+        double lo[3], hi[3];
+        for (int a = 0; a < d; ++a) {
+            lo[a] = INFINITY;
+            hi[a] = -INFINITY;
+        }
+        for (int64_t v = 0; v < m->n_vert; ++v)
+            for (int a = 0; a < d; ++a) {
+                lo[a] = std::min(lo[a], h->xyz[(size_t)v * d + a]);
+                hi[a] = std::max(hi[a], h->xyz[(size_t)v * d + a]);
+            }
+        std::vector<double> cen((size_t)h->n_cells * d, 0.0);
+        for (int64_t c = 0; c < h->n_cells; ++c)
+            for (int k = 0; k < nc; ++k)
+                for (int a = 0; a < d; ++a) cen[(size_t)c * d + a] += h->xyz[(size_t)h->cells[(size_t)c * nc + k] * d + a];
+        for (auto& v : cen) v /= nc;
+        std::vector<int64_t> prev_id(h->n_cells);  // level-(l-1) id of each fine cell
+        for (int64_t c = 0; c < h->n_cells; ++c) prev_id[c] = c;
+        for (int l = 1; l < o->n_levels; ++l) {
+            int64_t nbins = 1;
+            for (int a = 0; a < d; ++a) {
+                if (o->grid_bins[l][a] < 1) fail(DGMG_EINVAL, "grid_bins must be >= 1");
+                nbins *= o->grid_bins[l][a];
+            }
+            std::vector<int64_t> id(h->n_cells);
+            for (int64_t c = 0; c < h->n_cells; ++c) {
+                int64_t lin = 0;
+                for (int a = d - 1; a >= 0; --a) {
+                    const int nb = o->grid_bins[l][a];
+                    int64_t k = (int64_t)std::floor((cen[(size_t)c * d + a] - lo[a]) / (hi[a] - lo[a]) * nb);
+                    k = std::min<int64_t>(std::max<int64_t>(k, 0), nb - 1);
+                    lin = lin * nb + k;
+                }
+                id[c] = lin;
+            }
+            std::vector<int64_t> par(h->n_ent[l - 1], -1);
+            std::vector<char> used(nbins, 0);
+            for (int64_t c = 0; c < h->n_cells; ++c) {
+                int64_t& pp = par[prev_id[c]];
+                if (pp >= 0 && pp != id[c]) fail(DGMG_EINVAL, "grid bins do not nest across levels");
+                pp = id[c];
+                used[id[c]] = 1;
+            }
+            for (int64_t k = 0; k < nbins; ++k)
+                if (!used[k]) fail(DGMG_EINVAL, "empty agglomerate (grid bin without cells)");
+            h->parent.push_back(par);
+            h->n_ent.push_back(nbins);
+            prev_id = id;
+        }
+    } else if (o->method == DGMG_AGGLO_USER) {
+        if (!o->user_parents) fail(DGMG_EINVAL, "user_parents is null");
+        for (int l = 1; l < o->n_levels; ++l) {
+            const int64_t* up = o->user_parents[l - 1];
+            std::vector<int64_t> par(up, up + h->n_ent[l - 1]);
+            int64_t mx = -1;
+            for (auto v : par) {
+                if (v < 0) fail(DGMG_EINVAL, "negative parent id");
+                mx = std::max(mx, v);
+            }
+            std::vector<char> used(mx + 1, 0);
+            for (auto v : par) used[v] = 1;
+            for (auto u : used)
+                if (!u) fail(DGMG_EINVAL, "parent ids are not contiguous");
+            h->parent.push_back(par);
+            h->n_ent.push_back(mx + 1);
+        }
+    } else {
+        fail(DGMG_EUNSUPPORTED, "agglomeration method not available");
+    }
+    *out = guard.release();
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_hierarchy_info(const dgmg_hierarchy* h, int32_t level, int32_t* n_levels, int64_t* n_ent) {
+    API_BEGIN
+    if (!h) fail(DGMG_EINVAL, "null hierarchy");
+    if (n_levels) *n_levels = h->n_levels;
+    if (n_ent) {
+        if (level < 0 || level >= h->n_levels) fail(DGMG_EINVAL, "level out of range");
+        *n_ent = h->n_ent[level];
+    }
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_hierarchy_parents(const dgmg_hierarchy* h, int32_t level, int64_t* out) {
+    API_BEGIN
+    if (!h || !out) fail(DGMG_EINVAL, "null argument");
+    if (level < 0 || level >= h->n_levels - 1) fail(DGMG_EINVAL, "level out of range");
+    std::copy(h->parent[level].begin(), h->parent[level].end(), out);
+    return DGMG_OK;
+    API_END
+}
+
+void dgmg_destroy_hierarchy(dgmg_hierarchy* h) { delete h; }
+
+int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg_physics* ph,
+                      const dgmg_mg_opts* mg, dgmg_solver** out) {
+    API_BEGIN
+    if (!h || !disc || !ph || !mg || !out) fail(DGMG_EINVAL, "null argument");
+    if (!ph->D_cell) fail(DGMG_EINVAL, "D_cell is null");
+    if (!(ph->dt > 0) || !(ph->chi > 0) || !(ph->Cm > 0)) fail(DGMG_EINVAL, "dt, chi, Cm must be > 0");
+    if (ph->bdf != 1 && ph->bdf != 2) fail(DGMG_EINVAL, "bdf must be 1 or 2");
+    if (mg->cheb_degree < 1 || mg->cheb_sweeps < 0) fail(DGMG_EINVAL, "bad Chebyshev options");
+    if (ph->model < 0 || ph->model > 2) fail(DGMG_EINVAL, "unknown ionic model");
+    const int need[3] = {4, 3, 28};
+    if (ph->n_params != need[ph->model] || !ph->params) fail(DGMG_EINVAL, "wrong number of ionic parameters");
+    auto* s = new dgmg_solver();
+    std::unique_ptr<dgmg_solver> guard(s);
+    RefElement re;
+    re.init(h->dim, disc->p);
+    s->dim = h->dim;
+    s->p = disc->p;
+    s->b = re.b;
+    s->L = h->n_levels;
+    s->prec = mg->precision;
+    s->bdf = ph->bdf;
+    s->cheb_k = mg->cheb_degree;
+    s->cheb_s = mg->cheb_sweeps;
+    s->N = h->n_cells * re.b;
+    s->S = ph->model == DGMG_MODEL_BO ? 3 : 1;
+    s->parents = h->parent;
+    const double cM = (ph->bdf == 2 ? 1.5 : 1.0) * ph->chi * ph->Cm / ph->dt;
+    s->cU = ph->bdf == 2 ? ph->chi * ph->Cm / (2.0 * ph->dt) : ph->chi * ph->Cm / ph->dt;
+    s->ip.model = ph->model;
+    s->ip.S = s->S;
+    s->ip.bdf = ph->bdf;
+    s->ip.dt = ph->dt;
+    s->ip.chi = ph->chi;
+    s->ip.Cm = ph->Cm;
+    for (int k = 0; k < ph->n_params; ++k) s->ip.p[k] = ph->params[k];
+
+    double t0 = now_s();
+    Faces F = find_faces(*h);
+    s->ops.resize(s->L);
+    assemble_fine(*h, F, re, *disc, *ph, cM, s->ops[0], s->mass_h);
+    double t1 = now_s();
+    s->info.t_assembly = t1 - t0;
+    // boxes and prolongations
+    std::vector<std::vector<double>> lo(s->L), hi(s->L);
+    for (int l = 1; l < s->L; ++l) level_boxes(*h, l, lo[l], hi[l]);
+    double t2 = now_s();
+    s->info.t_hierarchy = t2 - t1;
+    s->Ph.resize(s->L);
+    for (int l = 0; l + 1 < s->L; ++l) prolongation_blocks(*h, re, l, lo[l], hi[l], lo[l + 1], hi[l + 1], s->Ph[l]);
+    double t3 = now_s();
+    s->info.t_transfer = t3 - t2;
+    for (int l = 0; l + 1 < s->L; ++l) galerkin(s->ops[l], s->Ph[l], h->parent[l], h->n_ent[l + 1], s->ops[l + 1]);
+    double t4 = now_s();
+    s->info.t_galerkin = t4 - t3;
+    s->lv.resize(s->L);
+    for (int l = 0; l + 1 < s->L; ++l) {
+        if (mg->lam_override) {
+            s->lv[l].lam_lo = mg->lam_override[2 * l];
+            s->lv[l].lam_hi = mg->lam_override[2 * l + 1];
+        } else {
+            const double th = lanczos_theta_max(s->ops[l], mg->lanczos_steps);
+            s->lv[l].lam_hi = mg->lam_safety * th;
+            s->lv[l].lam_lo = s->lv[l].lam_hi / mg->smooth_range;
+        }
+        if (!(s->lv[l].lam_hi > s->lv[l].lam_lo) || !(s->lv[l].lam_lo > 0))
+            fail(DGMG_EINVAL, "invalid Chebyshev interval");
+    }
+    double t5 = now_s();
+    s->info.t_smoother = t5 - t4;
+    std::vector<double> Ac;
+    dense_from_blocks(s->ops[s->L - 1], Ac);
+    s->nc_dofs = s->ops[s->L - 1].n * s->b;
+    cholesky_inverse(Ac, s->nc_dofs);
+    double t6 = now_s();
+    s->info.t_coarse = t6 - t5;
+
+    // info
+    s->info.dim = s->dim;
+    s->info.p = s->p;
+    s->info.b = s->b;
+    s->info.n_levels = s->L;
+    s->info.precision = s->prec;
+    s->info.model = ph->model;
+    s->info.n_gates = s->S;
+    s->info.n_dofs = s->N;
+    double nnz0 = 0, nnz = 0;
+    for (int l = 0; l < s->L; ++l) {
+        s->info.n_cells[l] = s->ops[l].n;
+        s->info.n_faces[l] = s->ops[l].nf;
+        s->info.lam_lo[l] = s->lv[l].lam_lo;
+        s->info.lam_hi[l] = s->lv[l].lam_hi;
+        double z = (double)(s->ops[l].n + 2 * s->ops[l].nf) * s->b * s->b;
+        if (l == 0) nnz0 = z;
+        nnz += z;
+    }
+    s->info.op_complexity = nnz / nnz0;
+
+    if (mg->device_setup) {
+        for (int l = 0; l < s->L; ++l) upload_level(s, l);
+        s->Ainv = s->upload(Ac);
+        const int n = (int)s->nc_dofs;
+        const int colblk = (n + kWG - 1) / kWG;
+        int nchunk = std::max(1, std::min(n / 8, 1024 / colblk));
+        s->rows_per_chunk = (n + nchunk - 1) / nchunk;
+        s->nchunk = (n + s->rows_per_chunk - 1) / s->rows_per_chunk;
+        s->cpart = s->dalloc<double>((size_t)s->nchunk * n);
+        const int64_t N = s->N;
+        s->r = s->dalloc<double>(N);
+        s->z = s->dalloc<double>(N);
+        s->zold = s->dalloc<double>(N);
+        s->pv = s->dalloc<double>(N);
+        s->q = s->dalloc<double>(N);
+        s->bwork = s->dalloc<double>(N);
+        s->tmp64a = s->dalloc<double>(N);
+        s->tmp64b = s->dalloc<double>(N);
+        s->partial = s->dalloc<double>(blocks_for(N) + 16);
+        s->sc = s->dalloc<double>(8);
+        HIPCHK(hipMemset(s->sc, 0, 8 * sizeof(double)));
+        HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * sizeof(double), hipHostMallocDefault));
+        s->mass = s->upload(to_colmajor<double>(s->mass_h, s->b));
+        HIPCHK(hipDeviceSynchronize());
+        s->on_device = true;
+    }
+    s->info.t_upload = now_s() - t6;
+    s->info.device_bytes = s->dev_bytes;
+    *out = guard.release();
+    return DGMG_OK;
+    API_END
+}
+
+void dgmg_destroy_solver(dgmg_solver* s) { delete s; }
+
+int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info) {
+    API_BEGIN
+    if (!s || !info) fail(DGMG_EINVAL, "null argument");
+    *info = s->info;
+    return DGMG_OK;
+    API_END
+}
+
+static void need_device(const dgmg_solver* s) {
+    if (!s) fail(DGMG_EINVAL, "null solver");
+    if (!s->on_device) fail(DGMG_EINVAL, "solver was set up without device data");
+}
+
+int dgmg_pcg_solve(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts* o,
+                   dgmg_pcg_stats* st, void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (!b || !x || !o || !st) fail(DGMG_EINVAL, "null argument");
+    return pcg(s, b, x, *o, st, (hipStream_t)stream);
+    API_END
+}
+
+int dgmg_ionic_step(dgmg_solver* s, const double* U, const double* Up, const double* W,
+                    const double* Wp, double* Wn, double* g, void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (!U || !Up || !W || !Wp || !Wn || !g) fail(DGMG_EINVAL, "null argument");
+    k_ionic<<<blocks_for(s->N), 256, 0, (hipStream_t)stream>>>(s->N, s->ip, U, Up, W, Wp, Wn, g);
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_time_step(dgmg_solver* s, dgmg_state* z, double t_next, const double* iapp,
+                   const dgmg_pcg_opts* o, dgmg_pcg_stats* st, void* stream) {
+    API_BEGIN
+    (void)t_next;
+    need_device(s);
+    if (!z || !o || !st || !z->U || !z->Uprev || !z->W || !z->Wprev || !z->g) fail(DGMG_EINVAL, "null argument");
+    hipStream_t hs = (hipStream_t)stream;
+    // gates W_{n+1} into the W_{n-1} buffer, nodal ionic current g
+    k_ionic<<<blocks_for(s->N), 256, 0, hs>>>(s->N, s->ip, z->U, z->Uprev, z->W, z->Wprev, z->Wprev, z->g);
+    // load vector; the warm start U_n is written into the U_{n-1} buffer
+    const int cells_per = 256 / s->b;
+    const unsigned nblk = (unsigned)((s->lv[0].n + cells_per - 1) / cells_per);
+    DISPATCH_B(s->b, k_rhs<BV><<<nblk, cells_per * BV, 0, hs>>>(s->lv[0].n, s->ip, s->cU, s->mass, z->U,
+                                                                 z->Uprev, iapp, z->g, s->bwork, z->Uprev));
+    HIPCHK(hipGetLastError());
+    int rc = pcg(s, s->bwork, z->Uprev, *o, st, hs);
+    std::swap(z->U, z->Uprev);
+    std::swap(z->W, z->Wprev);
+    return rc;
+    API_END
+}
+
+int dgmg_apply(dgmg_solver* s, int32_t level, int32_t prec, const double* x, double* y, void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (level < 0 || level >= s->L) fail(DGMG_EINVAL, "level out of range");
+    hipStream_t hs = (hipStream_t)stream;
+    DevLevel& L = s->lv[level];
+    if (level == s->L - 1 && s->L > 1) fail(DGMG_EUNSUPPORTED, "the coarsest level is stored factorised");
+    if (prec == DGMG_PREC_FP64) {
+        launch_apply<double>(s, L, x, nullptr, y, nullptr, nullptr, hs);
+    } else {
+        if (s->prec != DGMG_PREC_MIXED) fail(DGMG_EINVAL, "no FP32 copy in an FP64 solver");
+        k_cast<double, float><<<blocks_for(L.N), kWG, 0, hs>>>(L.N, x, nullptr, (float*)L.vx2);
+        launch_apply<float>(s, L, (float*)L.vx2, nullptr, (float*)L.vr, nullptr, nullptr, hs);
+        k_cast<float, double><<<blocks_for(L.N), kWG, 0, hs>>>(L.N, (float*)L.vr, nullptr, y);
+    }
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_vcycle(dgmg_solver* s, const double* r, double* z, void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (!r || !z) fail(DGMG_EINVAL, "null argument");
+    apply_vcycle(s, r, z, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_mass_apply(dgmg_solver* s, const double* f, double* b, void* stream) {
+    API_BEGIN
+    need_device(s);
+    DISPATCH_B(s->b, k_mass<BV><<<blocks_for(s->N), 256, 0, (hipStream_t)stream>>>(s->lv[0].n, s->mass, f, b));
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_profile_begin(dgmg_solver* s, int32_t kind, int32_t level) {
+    API_BEGIN
+    need_device(s);
+    if (kind < 0 || kind > PK_COARSE) fail(DGMG_EINVAL, "unknown kernel kind");
+    s->prof_kind = kind;
+    s->prof_level = level;
+    s->prof_used = 0;
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms) {
+    API_BEGIN
+    need_device(s);
+    double tot = 0.0;
+    for (size_t k = 0; k < s->prof_used; ++k) {
+        HIPCHK(hipEventSynchronize(s->prof_ev[k].second));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, s->prof_ev[k].first, s->prof_ev[k].second));
+        tot += ms;
+    }
+    if (launches) *launches = (int64_t)s->prof_used;
+    if (total_ms) *total_ms = tot;
+    s->prof_kind = -1;
+    s->prof_level = -1;
+    s->prof_used = 0;
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_export_level(const dgmg_solver* s, int32_t level, double* diag, int64_t* fc, double* fb,
+                      double* P, int64_t* parents) {
+    API_BEGIN
+    if (!s) fail(DGMG_EINVAL, "null solver");
+    if (level < 0 || level >= s->L) fail(DGMG_EINVAL, "level out of range");
+    const BlockOp& A = s->ops[level];
+    if (diag) std::copy(A.diag.begin(), A.diag.end(), diag);
+    if (fc) std::copy(A.fc.begin(), A.fc.end(), fc);
+    if (fb) std::copy(A.fblk.begin(), A.fblk.end(), fb);
+    if (level + 1 < s->L) {
+        if (P) std::copy(s->Ph[level].begin(), s->Ph[level].end(), P);
+        if (parents) std::copy(s->parents[level].begin(), s->parents[level].end(), parents);
+    }
+    return DGMG_OK;
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects bad input on the host (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2602_16312_amd import _ffi as F
+from paper_2602_16312_amd import api, problem
+from workloads import make_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "dgmg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgmg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(F.EXPORTS) == syms
+
+
+def test_bad_inputs_are_rejected_on_host():
+    pr = make_problem("c1", n=8)
+    with pytest.raises(F.DGMGError) as e:
+        api.build_hierarchy(pr["xyz"], pr["cell_vtx"], 0)
+    assert e.value.code == -1
+    bad = pr["cell_vtx"].copy()
+    bad[0, 0] = 10 ** 6
+    with pytest.raises(F.DGMGError):
+        api.build_hierarchy(pr["xyz"], bad, 1)
+    # bins that do not nest
+    with pytest.raises(F.DGMGError):
+        api.build_hierarchy(pr["xyz"], pr["cell_vtx"], 3, grid_bins=[[1, 1, 1], [3, 3, 1], [2, 2, 1]])
+    h = api.build_hierarchy(pr["xyz"], pr["cell_vtx"], 2, grid_bins=[[1, 1, 1], [2, 2, 1]])
+    with pytest.raises(F.DGMGError):
+        api.setup_levels(h, 1, pr["D_cell"], 1.0, 1.0, 0.01, "fhn", [1.0, 2.0], device_setup=False)
+    with pytest.raises(F.DGMGError) as e:
+        api.setup_levels(h, 5, pr["D_cell"], 1.0, 1.0, 0.01, "fhn", pr["params"], device_setup=False)
+    assert e.value.code == -6
+    # inverted cell -> non-positive Jacobian
+    inv = pr["cell_vtx"].copy()
+    inv[3] = inv[3][[1, 0, 3, 2]]
+    with pytest.raises(F.DGMGError):
+        h2 = api.build_hierarchy(pr["xyz"], inv, 1)
+        api.setup_levels(h2, 1, pr["D_cell"], 1.0, 1.0, 0.01, "fhn", pr["params"],
+                         device_setup=False)
+    # solve calls on a host-only solver fail cleanly
+    s = api.setup_levels(h, 1, pr["D_cell"], 1.0, 1.0, 0.01, "fhn", pr["params"],
+                         device_setup=False)
+    rc = F.lib().dgmg_vcycle(s.handle, None, None, None)
+    assert rc == -1
+
+
+def test_indefinite_coarse_operator_is_reported():
+    """A negative penalty makes the one-level operator indefinite; the
+    coarse Cholesky reports ENOTSPD."""
+    pr = make_problem("c1", n=4)
+    h = api.build_hierarchy(pr["xyz"], pr["cell_vtx"], 1)
+    with pytest.raises(F.DGMGError) as e:
+        api.setup_levels(h, 1, pr["D_cell"] * 1e5, 1.0, 1.0, 1e3, "fhn", pr["params"],
+                         penalty=("fixed", -50.0), device_setup=False)
+    assert e.value.code == -2

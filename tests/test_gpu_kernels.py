@@ -1,0 +1,174 @@
+"""GPU parity of the operator-level kernels against the FP64 oracle:
+block apply (FP64 and FP32 level copies), V-cycle as an operator, mass
+blocks, ionic update, PCG solves and their edge cases."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, need_gpu, rel, say, torch
+from paper_2602_16312_amd import api, problem
+from paper_2602_16312_amd._ffi import DGMGError
+from workloads import make_problem
+from oracle.assemble import system_matrix, mass_blocks
+from oracle.hierarchy import build_hierarchy as oracle_hierarchy
+from oracle.ionic import gate_step, ionic_current
+from oracle.mg import VCycle, pcg
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [("c1", 32, {}), ("c2", 64, {}), ("c2", 36, {"p": 3, "group": [3]}),
+         ("c3", 8, {}), ("c3", 6, {"p": 1, "group": [3]})]
+
+
+def _setup(name, n, kw, precision="fp64", lam=True):
+    pr = make_problem(name, n=n, **kw)
+    A0, M, A, cM = system_matrix(pr)
+    oh = oracle_hierarchy(pr)
+    mg = VCycle(A0, oh["P"])
+    h, s = problem.build(pr, precision=precision,
+                         lam_override=mg.lam if lam else None)
+    return pr, mg, h, s
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("name,n,kw", SIZES)
+def test_apply_all_levels(name, n, kw):
+    pr, mg, h, s = _setup(name, n, kw, precision="mixed")
+    rng = np.random.default_rng(1)
+    for l in range(len(mg.A) - 1):
+        x = rng.standard_normal(mg.A[l].shape[0])
+        ref = mg.A[l] @ x
+        y = torch.empty(len(x), dtype=torch.float64, device="cuda")
+        say("apply", name, n, kw, "level", l, "fp64")
+        api.apply(s, l, dev(x), y, "fp64")
+        assert rel(host(y), ref) <= 1e-13
+        say("apply", name, n, kw, "level", l, "fp32")
+        api.apply(s, l, dev(x), y, "mixed")
+        assert rel(host(y), ref) <= 2e-6
+
+
+@pytest.mark.parametrize("name,n,kw", SIZES[:4])
+def test_vcycle_operator(name, n, kw):
+    rng = np.random.default_rng(2)
+    for prec, tol in (("fp64", 1e-11), ("mixed", 2e-5)):
+        pr, mg, h, s = _setup(name, n, kw, precision=prec)
+        r = rng.standard_normal(pr["N"])
+        ref = mg(r)
+        z = torch.empty(pr["N"], dtype=torch.float64, device="cuda")
+        say("vcycle", name, n, kw, prec)
+        api.vcycle(s, dev(r), z)
+        assert rel(host(z), ref) <= tol, prec
+
+
+def test_mass_blocks():
+    pr = make_problem("c2", n=32)
+    h, s = problem.build(pr)
+    Mk = mass_blocks(pr)
+    f = np.random.default_rng(3).standard_normal(pr["N"])
+    ref = np.einsum("nij,nj->ni", Mk, f.reshape(pr["n_cells"], -1)).ravel()
+    b = torch.empty(pr["N"], dtype=torch.float64, device="cuda")
+    say("mass_apply c2 32")
+    api.mass_apply(s, dev(f), b)
+    assert rel(host(b), ref) <= 1e-14
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_ionic_step(name):
+    pr = make_problem(name, n=4)
+    h, s = problem.build(pr)
+    N, S = pr["N"], pr["S"]
+    rng = np.random.default_rng(4)
+    U = rng.uniform(-0.1, 1.2, N)
+    Up = U + rng.uniform(-0.05, 0.05, N)
+    W = rng.uniform(0.0, 1.0, (S, N))
+    Wp = W + rng.uniform(-0.02, 0.02, (S, N))
+    us = 2 * U - Up
+    Wref = gate_step(pr["model"], pr["params"], us, W, Wp, pr["dt"])
+    gref = ionic_current(pr["model"], pr["params"], us, Wref)
+    Wn = torch.empty(S * N, dtype=torch.float64, device="cuda")
+    g = torch.empty(N, dtype=torch.float64, device="cuda")
+    say("ionic_step", name)
+    api.ionic_step(s, dev(U), dev(Up), dev(W.ravel()), dev(Wp.ravel()), Wn, g)
+    assert rel(host(Wn).reshape(S, N), Wref) <= 1e-13
+    assert rel(host(g), gref) <= 1e-12
+
+
+@pytest.mark.parametrize("name,n,kw", SIZES[:4])
+def test_pcg_solve_fp64(name, n, kw):
+    pr, mg, h, s = _setup(name, n, kw)
+    A0 = mg.A[0]
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(pr["N"])
+    x0 = 0.1 * rng.standard_normal(pr["N"])
+    xr, str_ = pcg(A0, b, x0, mg, 1e-12)
+    x = dev(x0)
+    say("pcg fp64", name, n, kw)
+    st = api.pcg_solve(s, dev(b), x, tol=1e-12)
+    assert st["converged"]
+    assert abs(st["its"] - str_["its"]) <= 1
+    assert rel(host(x), xr) <= 1e-10
+    assert abs(st["r0"] - str_["r0"]) <= 1e-12 * str_["r0"]
+    # true residual of the GPU solution, evaluated by the oracle
+    xg = host(x)
+    assert np.linalg.norm(b - A0 @ xg) <= 1.5e-12 * st["r0"]
+
+
+def test_pcg_mixed_reaches_fp64_accuracy():
+    pr, mg, h, s = _setup("c2", 64, {}, precision="mixed")
+    A0 = mg.A[0]
+    b = np.random.default_rng(6).standard_normal(pr["N"])
+    x = torch.zeros(pr["N"], dtype=torch.float64, device="cuda")
+    say("pcg mixed c2 64")
+    st = api.pcg_solve(s, dev(b), x, tol=1e-10)
+    assert st["converged"]
+    xg = host(x)
+    xd = np.linalg.solve(A0.toarray(), b) if pr["N"] < 5000 else pcg(A0, b, 0 * b, mg, 1e-14)[0]
+    assert np.linalg.norm(b - A0 @ xg) <= 1.5e-10 * np.linalg.norm(b)
+    assert rel(xg, xd) <= 1e-8
+
+
+def test_pcg_edge_cases():
+    pr, mg, h, s = _setup("c1", 16, {})
+    N = pr["N"]
+    z = torch.zeros(N, dtype=torch.float64, device="cuda")
+    say("pcg zero rhs")
+    st = api.pcg_solve(s, torch.zeros_like(z), z, tol=1e-10)
+    assert st["its"] == 0 and st["converged"] and st["r0"] == 0.0
+    b = dev(np.random.default_rng(7).standard_normal(N))
+    x = torch.zeros_like(z)
+    say("pcg max_it 1")
+    st = api.pcg_solve(s, b, x, tol=1e-14, max_it=1)
+    assert st["rc"] == 1 and not st["converged"] and st["its"] == 1
+    say("pcg abs and rel_b modes")
+    x.zero_()
+    st = api.pcg_solve(s, b, x, tol=1e-9, tol_mode="rel_b")
+    assert st["converged"] and st["rfin"] <= 1e-9 * float(torch.linalg.norm(b))
+    x.zero_()
+    st = api.pcg_solve(s, b, x, tol=1e-9 * st["r0"], tol_mode="abs")
+    assert st["converged"]
+    say("pcg flexible")
+    x.zero_()
+    st2 = api.pcg_solve(s, b, x, tol=1e-10, flexible=True)
+    assert st2["converged"]
+    say("pcg nan rhs")
+    bn = b.clone()
+    bn[5] = float("nan")
+    x.zero_()
+    with pytest.raises(DGMGError) as e:
+        api.pcg_solve(s, bn, x, tol=1e-10)
+    assert e.value.code == -3
+
+
+def test_bitwise_repeatable():
+    pr, mg, h, s = _setup("c2", 64, {}, precision="mixed")
+    b = dev(np.random.default_rng(8).standard_normal(pr["N"]))
+    outs = []
+    for k in range(2):
+        x = torch.zeros(pr["N"], dtype=torch.float64, device="cuda")
+        say("repeatability run", k)
+        api.pcg_solve(s, b, x, tol=1e-10)
+        outs.append(host(x))
+    assert np.array_equal(outs[0], outs[1])

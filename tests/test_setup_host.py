@@ -1,0 +1,80 @@
+"""The library's host setup (assembly, agglomeration, prolongation, Galerkin
+products, Lanczos) against the independent oracle, on the CPU."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2602_16312_amd import problem
+from workloads import make_problem
+from oracle.assemble import system_matrix
+from oracle.hierarchy import build_hierarchy as oracle_hierarchy
+from oracle.mg import VCycle
+
+
+def dense_level(ex):
+    d, fc, fb = ex["diag"], ex["face_cells"], ex["face_blocks"]
+    n, b, _ = d.shape
+    rows, cols, vals = [], [], []
+    loc = np.arange(b)
+    for K in range(n):
+        rows.append(np.repeat(K * b + loc, b)); cols.append(np.tile(K * b + loc, b))
+        vals.append(d[K].ravel())
+    for f, (p, m) in enumerate(fc):
+        rows.append(np.repeat(p * b + loc, b)); cols.append(np.tile(m * b + loc, b))
+        vals.append(fb[f].ravel())
+        rows.append(np.repeat(m * b + loc, b)); cols.append(np.tile(p * b + loc, b))
+        vals.append(fb[f].T.ravel())
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n * b, n * b))
+
+
+CASES = [("c1", 8, {}), ("c2", 16, {}), ("c2", 32, {"p": 1}), ("c3", 4, {}),
+         ("c1", 8, {"bdf": 1})]
+
+
+@pytest.mark.parametrize("name,n,kw", CASES)
+def test_levels_match_oracle(name, n, kw):
+    bdf = kw.pop("bdf", 2)
+    pr = make_problem(name, n=n, **kw)
+    h, s = problem.build(pr, device_setup=False, bdf=bdf)
+    A0, M, A, cM = system_matrix(pr, bdf=bdf)
+    oh = oracle_hierarchy(pr)
+    mg = VCycle(A0, oh["P"])
+    info = s.info()
+    assert info["n_cells"] == oh["n"]
+    for l in range(info["n_levels"]):
+        ex = s.export_level(l)
+        Al = dense_level(ex)
+        ref = mg.A[l]
+        assert abs(Al - ref).max() <= 1e-12 * abs(ref).max(), l
+        if l + 1 < info["n_levels"]:
+            assert np.array_equal(ex["parents"], oh["parents"][l])
+            b = info["b"]
+            Pl = oh["P"][l].toarray()
+            for e in range(0, ex["P"].shape[0], max(1, ex["P"].shape[0] // 7)):
+                K = ex["parents"][e]
+                assert np.allclose(ex["P"][e], Pl[e * b:(e + 1) * b, K * b:(K + 1) * b],
+                                   atol=1e-13)
+    for l in range(info["n_levels"] - 1):
+        assert abs(info["lam_hi"][l] - mg.lam[l][1]) <= 1e-10 * mg.lam[l][1]
+        assert abs(info["lam_lo"][l] - mg.lam[l][0]) <= 1e-10 * mg.lam[l][0]
+
+
+def test_cell_scaling_and_fixed_penalty():
+    pr = make_problem("c1", n=8)
+    rng = np.random.default_rng(11)
+    s_cell = rng.uniform(0.5, 2.0, pr["n_cells"])
+    h, s = problem.build(pr, device_setup=False, cell_scale=s_cell)
+    A0, M, A, cM = system_matrix(pr, scale=s_cell)
+    Al = dense_level(s.export_level(0))
+    assert abs(Al - A0).max() <= 1e-12 * abs(A0).max()
+
+
+def test_operator_complexity_and_counts():
+    pr = make_problem("c2", n=64)
+    h, s = problem.build(pr, device_setup=False)
+    info = s.info()
+    assert info["n_cells"] == [4096, 256, 16]
+    assert info["n_dofs"] == 4096 * 9
+    # 4x4 grouping on a grid: each coarse level has ~1/16 of the blocks
+    assert 1.0 < info["op_complexity"] < 1.08

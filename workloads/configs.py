@@ -47,11 +47,13 @@ CONFIGS = {
                model="fhn", params=[19.5, 0.13, 0.01, 0.5],
                penalty=("fixed", 10.0 * 1 ** 2 * 32), ic="corner_disc",
                stim=None, tol=1e-10),
-    # 256x256 jittered Q2, Aliev-Panfilov, three levels (4x4 grouping twice)
+    # 256x256 jittered Q2, Aliev-Panfilov, three levels (4x4 grouping twice).
+    # The paper's penalty (factor 1) leaves A_0 indefinite on a few of the
+    # most distorted cells of this seeded mesh; factor 2 restores coercivity.
     "c2": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
                sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=100,
                model="ap", params=[8.0, 0.15, 0.002],
-               penalty=("paper",), ic="corner_disc", stim=None, tol=1e-8),
+               penalty=("paper", 2.0), ic="corner_disc", stim=None, tol=1e-8),
     # 64^3 Q2 cube, rotating fibres, Bueno-Orovio (ms), four levels (2x2x2)
     "c3": dict(dim=3, n=64, p=2, jitter=0.0, seed=None, group=[2, 2, 2],
                sigma=("fibre_z", 1.2e-3, 2.5e-4), chi=1.0, Cm=1.0, dt=5e-2,
@@ -63,7 +65,7 @@ CONFIGS = {
     "c5": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
                sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=50,
                model="ap", params=[8.0, 0.15, 0.002],
-               penalty=("paper",), ic="corner_disc", stim=None, tol=1e-8,
+               penalty=("paper", 2.0), ic="corner_disc", stim=None, tol=1e-8,
                sensors=(64, 2605), target_seed=2606),
 }
 
