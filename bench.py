@@ -24,6 +24,10 @@ METRIC = "DoFs/s per time step (PCG+V-cycle to 1e-8), mixed vs FP64; iters; HBM 
 HBM_PEAK_GBS = 8000.0
 
 
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def _stats(v):
     import numpy as np
     a = np.asarray(v, dtype=float)
@@ -51,6 +55,7 @@ def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None):
     t0 = time.perf_counter()
     h, s = problem.build(pr, precision=precision)
     setup_s = time.perf_counter() - t0
+    log(f"{precision}: setup {setup_s:.1f} s")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()),
                    dev(pr["W0"].ravel()),
@@ -71,13 +76,16 @@ def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = api.profile_end(s) if profile_kind else None
+    log(f"{precision}: {steps} steps in {wall:.3f} s, its {its[:10]}...")
     return dict(wall=wall, its=its, setup_s=setup_s, info=s.info(), prof=prof,
                 U=st.U.cpu().numpy())
 
 
 def cpu_baseline(pr, tol, nsteps):
     from oracle.stepper import Simulation
+    log("cpu baseline: oracle setup")
     sim = Simulation(pr)
+    log("cpu baseline: timing steps")
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     _, _, stats = sim.run(nsteps, tol, record=False)
