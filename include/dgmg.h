@@ -244,6 +244,14 @@ int dgmg_export_level(const dgmg_solver* s, int32_t level, double* diag,
 int dgmg_profile_begin(dgmg_solver* s, int32_t kind, int32_t level);
 int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms);
 
+/* Average duration (ms, HIP events on `stream`) of `reps` back-to-back
+ * launches of one smoother kernel (kind 0: fused Chebyshev step, 1: fused
+ * residual) on `level` < n_levels - 1, in the solver's V-cycle precision.
+ * Uses the level's internal work vectors only (their contents are
+ * overwritten); caller data are untouched. */
+int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t reps, void* stream,
+                      double* avg_ms);
+
 const char* dgmg_last_error(void);
 
 #ifdef __cplusplus

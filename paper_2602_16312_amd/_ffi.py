@@ -16,7 +16,7 @@ EXPORTS = [
     "dgmg_destroy_hierarchy", "dgmg_setup_levels", "dgmg_destroy_solver",
     "dgmg_get_info", "dgmg_pcg_solve", "dgmg_ionic_step", "dgmg_time_step",
     "dgmg_apply", "dgmg_vcycle", "dgmg_mass_apply", "dgmg_export_level",
-    "dgmg_profile_begin", "dgmg_profile_end", "dgmg_last_error",
+    "dgmg_profile_begin", "dgmg_profile_end", "dgmg_kernel_bench", "dgmg_last_error",
 ]
 
 dp = C.POINTER(C.c_double)
@@ -115,6 +115,7 @@ def lib():
         L.dgmg_export_level.argtypes = [vp, C.c_int32, dp, i64p, dp, dp, i64p]
         L.dgmg_profile_begin.argtypes = [vp, C.c_int32, C.c_int32]
         L.dgmg_profile_end.argtypes = [vp, i64p, dp]
+        L.dgmg_kernel_bench.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, dp]
         L.dgmg_last_error.restype = C.c_char_p
         _lib = L
     return _lib

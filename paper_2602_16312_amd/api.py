@@ -259,3 +259,11 @@ def profile_end(solver):
     ms = C.c_double()
     F.check(F.lib().dgmg_profile_end(solver.handle, C.byref(n), C.byref(ms)))
     return n.value, ms.value
+
+
+def kernel_bench(solver, kind="cheb_step", level=0, reps=200, stream=None):
+    """Average duration in ms of back-to-back launches of one smoother kernel."""
+    ms = C.c_double()
+    F.check(F.lib().dgmg_kernel_bench(solver.handle, KERNEL_KINDS[kind], level, reps,
+                                      _stream(stream), C.byref(ms)))
+    return ms.value

@@ -119,7 +119,8 @@ __global__ __launch_bounds__(256) void k_rhs(int32_t n, IonicParams P, double cU
     }
     __syncthreads();
     if (!act) return;
-    const double* M = mass + (size_t)cell * B * B + i;   // column-major: (i, j) at j*B + i
+    // column-major (i, j) at j*B + i, block stride padded to whole 16-byte vectors
+    const double* M = mass + (size_t)cell * ((B * B + 1) / 2 * 2) + i;
     const double* fc = f + lc * B;
     double acc = 0.0;
 #pragma unroll
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void k_mass(int32_t n, const double* __restric
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int cell = t / B, i = t - cell * B;
     if (cell >= n) return;
-    const double* M = mass + (size_t)cell * B * B + i;
+    const double* M = mass + (size_t)cell * ((B * B + 1) / 2 * 2) + i;
     const double* fc = fv + (size_t)cell * B;
     double acc = 0.0;
 #pragma unroll

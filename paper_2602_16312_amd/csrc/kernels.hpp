@@ -2,19 +2,24 @@
 //
 // Layout on the device (one level, scalar type T = double or float):
 //  * vectors: cell-major, DoF (K, i) at K*B + i;
-//  * cell blocks diag[K] and face blocks fblk[f] are B x B and stored
-//    column-major (entry (i, j) at j*B + i) so that the B lanes owning the
-//    rows of one cell read consecutive addresses for every column j;
-//  * face f couples plus cell (rows) and minus cell (columns); the plus side
-//    applies F, the minus side applies F^T from the same stored block (A is
-//    symmetric, section 3), so every face block is stored once;
-//  * cell -> neighbour lists (CSR) hold the neighbour cell and
-//    (face << 1 | side), side 1 meaning "this cell is the minus side";
-//  * prolongation blocks P_e (fine node i, coarse function j) column-major.
-// One thread owns one DoF row.  Workgroups are mapped XCD-aware: the 8 XCDs
-// receive consecutive workgroup ids round-robin, so tile = (id % 8) * per +
-// id / 8 gives each XCD a contiguous range of cells and keeps the second
-// read of a face block (by the neighbour) in that XCD's L2 where possible.
+//  * operator: "tile-ELL".  Cells are grouped in tiles of TC = 256/B cells
+//    (one workgroup, thread = (cell in tile, row i)).  Tile t owns ns_t slots
+//    (its cell blocks, then one slot per neighbour entry, ns_t = 1 + largest
+//    neighbour count in the tile); slot s holds, for every cell of the tile,
+//    the B x B block coupling that cell to its s-th column cell, already
+//    oriented for the row cell (a face block F for the plus cell, F^T for the
+//    minus cell; zero where the cell has fewer neighbours).  Entries are
+//    interleaved so that for a fixed (slot, column j) the TC*B rows of the
+//    tile are contiguous: vals[(slot*B + j)*TC*B + lc*B + i].  A wave's 64
+//    lanes therefore read 64 consecutive values per load.  Each face block is
+//    stored twice (once per side): reading a single stored copy transposed
+//    from the other side costs more in cache-line traffic than the second
+//    copy costs in bytes on this hardware;
+//  * prolongation blocks use the same interleaving with one slot per tile.
+// Workgroups are mapped XCD-aware: the 8 XCDs receive consecutive workgroup
+// ids round-robin, so tile = (id % 8) * per + id / 8 gives each XCD a
+// contiguous range of cells (neighbouring tiles share their x gathers in the
+// XCD's L2).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -33,59 +38,72 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 
 template <typename T>
 struct LevelArgs {
-    const T* __restrict__ diag;
-    const T* __restrict__ fblk;
+    const T* __restrict__ vals;            // tile-ELL blocks
+    const int32_t* __restrict__ slot_ptr;  // ntiles + 1
+    const int32_t* __restrict__ snb;       // (slot, cell in tile) -> column cell
     const T* __restrict__ dinv;
-    const int32_t* __restrict__ nbr_ptr;
-    const int32_t* __restrict__ nbr_cell;
-    const int32_t* __restrict__ nbr_code;
     int32_t n;
 };
 
-// (A v)[cell, i] with v = va + vb (vb may be null).
 template <typename T, int B>
-__device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int cell, int i,
-                                       const T* __restrict__ va, const T* __restrict__ vb) {
-    constexpr int BB = B * B;
-    T acc = 0;
-    {
-        const T* D = L.diag + (size_t)cell * BB + i;
-        const T* v = va + (size_t)cell * B;
-        if (vb) {
-            const T* w = vb + (size_t)cell * B;
+struct Tile {
+    static constexpr int TC = kWG / B;   // cells per tile / workgroup
+    static constexpr int TR = TC * B;    // rows per tile
+};
+
+// Slots whose loads are issued together before any of them is accumulated
+// (bounded so that G*B values stay in registers): all five slots of a 2D
+// quad cell for B <= 9, fewer for larger blocks.
+template <int B>
+constexpr int slot_group() {
+    return (48 / B) < 1 ? 1 : ((48 / B) > 5 ? 5 : (48 / B));
+}
+
+// (A v) at row (tile*TC + lc, i) of the tile's thread (lc, i), v = va (+ vb
+// when VB).  Loads of a group of G slots -- block values and the gathered
+// vector segments -- are all issued before the group is accumulated; slots
+// past a count reload a valid slot (cache hit) and are skipped.
+template <typename T, int B, bool VB>
+__device__ __forceinline__ void gather_group(const T* __restrict__ va, const T* __restrict__ vb,
+                                             int nb, T* v) {
+    const T* x = va + (size_t)nb * B;
+    if constexpr (VB) {
+        const T* y = vb + (size_t)nb * B;
 #pragma unroll
-            for (int j = 0; j < B; ++j) acc += D[j * B] * (v[j] + w[j]);
-        } else {
+        for (int j = 0; j < B; ++j) v[j] = x[j] + y[j];
+    } else {
 #pragma unroll
-            for (int j = 0; j < B; ++j) acc += D[j * B] * v[j];
-        }
+        for (int j = 0; j < B; ++j) v[j] = x[j];
     }
-    const int e0 = L.nbr_ptr[cell], e1 = L.nbr_ptr[cell + 1];
-    for (int e = e0; e < e1; ++e) {
-        const int nb = L.nbr_cell[e];
-        const int code = L.nbr_code[e];
-        const T* F = L.fblk + (size_t)(code >> 1) * BB;
-        const T* v = va + (size_t)nb * B;
-        const T* w = vb ? vb + (size_t)nb * B : nullptr;
-        if ((code & 1) == 0) {
-            F += i;  // row i of F: entries at j*B + i
-            if (w) {
+}
+
+template <typename T, int B, bool VB>
+__device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int lc,
+                                           const T* __restrict__ va, const T* __restrict__ vb) {
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, G = slot_group<B>();
+    const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;
+    const T* __restrict__ A = L.vals + (size_t)s0 * B * TR + threadIdx.x;
+    const int32_t* __restrict__ nbp = L.snb + (size_t)s0 * TC + lc;
+    T acc = 0;
+    for (int g = 0; g < ns; g += G) {
+        int nbq[G];
+        T a[G][B], v[G][B];
 #pragma unroll
-                for (int j = 0; j < B; ++j) acc += F[j * B] * (v[j] + w[j]);
-            } else {
+        for (int q = 0; q < G; ++q) nbq[q] = nbp[(size_t)min(g + q, ns - 1) * TC];
 #pragma unroll
-                for (int j = 0; j < B; ++j) acc += F[j * B] * v[j];
-            }
-        } else {
-            F += (size_t)i * B;  // row i of F^T = column i of F: contiguous
-            if (w) {
+        for (int q = 0; q < G; ++q) {
+            const T* As = A + (size_t)min(g + q, ns - 1) * B * TR;
 #pragma unroll
-                for (int j = 0; j < B; ++j) acc += F[j] * (v[j] + w[j]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < B; ++j) acc += F[j] * v[j];
-            }
+            for (int j = 0; j < B; ++j) a[q][j] = As[(size_t)j * TR];
         }
+#pragma unroll
+        for (int q = 0; q < G; ++q) gather_group<T, B, VB>(va, vb, nbq[q], v[q]);
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if (g + q < ns) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc += a[q][j] * v[q][j];
+            }
     }
     return acc;
 }
@@ -106,41 +124,64 @@ __device__ __forceinline__ void wg_sum_store(double v, double* partial) {
 }
 
 // ---------------------------------------------------------------- apply
-// y = A (va + vb); optional partial of dot(w, y).
+#define DGMG_TILE_THREAD(T, B)                                   \
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);            \
+    const int lc = threadIdx.x / B;                              \
+    const int cell = tile * Tile<T, B>::TC + lc;                 \
+    const bool active = lc < Tile<T, B>::TC && cell < L.n;       \
+    const int t = cell * B + (threadIdx.x - lc * B);
+
+// y = A va; optional partial of dot(w, y).
 template <typename T, int B>
 __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restrict__ va,
-                                               const T* __restrict__ vb, T* __restrict__ y,
+                                               T* __restrict__ y,
                                                const T* __restrict__ w, double* __restrict__ partial) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int t = tile * kWG + threadIdx.x;
-    const int cell = t / B, i = t - cell * B;
+    DGMG_TILE_THREAD(T, B)
     double contrib = 0.0;
-    if (cell < L.n) {
-        const T a = row_apply<T, B>(L, cell, i, va, vb);
+    if (active) {
+        const T a = ell_row_apply<T, B, false>(L, tile, lc, va, nullptr);
         y[t] = a;
         if (w) contrib = (double)w[t] * (double)a;
     }
     if (partial) wg_sum_store(contrib, partial);
 }
 
-// Residual: r = rhs - A (va + vb); optional d = dinv * r * c1, x_out = va + vb,
-// partial of ||r||^2.
-template <typename T, int B>
+// Residual r = rhs - A (va + vb), with optional epilogues: d = dinv * r * c1,
+// xout = va + vb, partial of ||r||^2, and restriction partials
+// rp[cell, j] = sum_i P_cell(i, j) r[cell, i] (P in tile-interleaved layout)
+// for the coarse correction.  r may be null when only rp is wanted.
+template <typename T, int B, bool VB>
 __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __restrict__ va,
                                                   const T* __restrict__ vb, const T* __restrict__ rhs,
                                                   T* __restrict__ r, T* __restrict__ d, T c1,
-                                                  T* __restrict__ xout, double* __restrict__ partial) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int t = tile * kWG + threadIdx.x;
-    const int cell = t / B, i = t - cell * B;
+                                                  T* __restrict__ xout, double* __restrict__ partial,
+                                                  const T* __restrict__ P, T* __restrict__ rp) {
+    DGMG_TILE_THREAD(T, B)
     double contrib = 0.0;
-    if (cell < L.n) {
-        const T a = row_apply<T, B>(L, cell, i, va, vb);
-        const T rr = rhs[t] - a;
-        r[t] = rr;
+    T rr = 0;
+    if (active) {
+        const T a = ell_row_apply<T, B, VB>(L, tile, lc, va, vb);
+        rr = rhs[t] - a;
+        if (r) r[t] = rr;
         if (d) d[t] = L.dinv[t] * rr * c1;
-        if (xout) xout[t] = vb ? va[t] + vb[t] : va[t];
+        if (xout) xout[t] = VB ? va[t] + vb[t] : va[t];
         contrib = (double)rr * (double)rr;
+    }
+    if (P) {
+        __shared__ T rs[kWG];
+        rs[threadIdx.x] = rr;
+        __syncthreads();
+        if (active) {
+            // thread (lc, j): column j of P_cell, contiguous in i
+            constexpr int TR = Tile<T, B>::TR;
+            const int j = threadIdx.x - lc * B;
+            const T* Pc = P + ((size_t)tile * B + j) * TR + lc * B;
+            const T* rc = rs + lc * B;
+            T s = 0;
+#pragma unroll
+            for (int k = 0; k < B; ++k) s += Pc[k] * rc[k];
+            rp[t] = s;
+        }
     }
     if (partial) wg_sum_store(contrib, partial);
 }
@@ -151,11 +192,9 @@ template <typename T, int B>
 __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __restrict__ d,
                                                    T* __restrict__ x, T* __restrict__ r,
                                                    T* __restrict__ dn, T cd, T cr, int assign) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int t = tile * kWG + threadIdx.x;
-    const int cell = t / B, i = t - cell * B;
-    if (cell >= L.n) return;
-    const T a = row_apply<T, B>(L, cell, i, d, nullptr);
+    DGMG_TILE_THREAD(T, B)
+    if (!active) return;
+    const T a = ell_row_apply<T, B, false>(L, tile, lc, d, nullptr);
     const T dt = d[t];
     x[t] = assign ? dt : x[t] + dt;
     const T rr = r[t] - a;
@@ -176,80 +215,109 @@ __global__ __launch_bounds__(kWG) void k_cheb_init0(int64_t N, const T* __restri
 }
 
 // ----------------------------------------------------------- transfers
-// Restriction rc[K, j] = sum_{e child of K} sum_i P_e(i, j) r[e, i].
+// Restriction, second half: rc[K, j] = sum over children e of rp[e, j]
+// (child ids of a group are loaded before their values).
 template <typename T, int B>
-__global__ __launch_bounds__(kWG) void k_restrict(int32_t nC, const int32_t* __restrict__ cptr,
-                                                  const int32_t* __restrict__ clist,
-                                                  const T* __restrict__ P, const T* __restrict__ r,
-                                                  T* __restrict__ rc) {
+__global__ __launch_bounds__(kWG) void k_restrict_sum(int32_t nC, const int32_t* __restrict__ cptr,
+                                                      const int32_t* __restrict__ clist,
+                                                      const T* __restrict__ rp, T* __restrict__ rc) {
+    constexpr int G = 8;
     const int t = blockIdx.x * kWG + threadIdx.x;
     const int K = t / B, j = t - K * B;
     if (K >= nC) return;
     T acc = 0;
     const int c0 = cptr[K], c1 = cptr[K + 1];
-    for (int c = c0; c < c1; ++c) {
-        const int e = clist[c];
-        const T* Pe = P + (size_t)e * B * B + (size_t)j * B;  // column j, contiguous in i
-        const T* re = r + (size_t)e * B;
+    for (int c = c0; c < c1; c += G) {
+        int e[G];
+        T v[G];
 #pragma unroll
-        for (int i = 0; i < B; ++i) acc += Pe[i] * re[i];
+        for (int q = 0; q < G; ++q) e[q] = clist[min(c + q, c1 - 1)];
+#pragma unroll
+        for (int q = 0; q < G; ++q) v[q] = rp[(size_t)e[q] * B + j];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if (c + q < c1) acc += v[q];
     }
     rc[t] = acc;
 }
 
-// Prolongation with correction: x[e, i] += sum_j P_e(i, j) (xc + dc)[parent(e), j].
+// Prolongation with correction: x[e, i] += sum_j P_e(i, j) (xc + dc)[parent(e), j]
+// (P tile-interleaved: one slot per tile).
 template <typename T, int B>
 __global__ __launch_bounds__(kWG) void k_prolong_add(int32_t n, const int32_t* __restrict__ parent,
                                                      const T* __restrict__ P, const T* __restrict__ xc,
                                                      const T* __restrict__ dc, T* __restrict__ x) {
-    const int t = blockIdx.x * kWG + threadIdx.x;
-    const int e = t / B, i = t - e * B;
-    if (e >= n) return;
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
+    const int tile = blockIdx.x;
+    const int lc = threadIdx.x / B;
+    const int e = tile * TC + lc;
+    if (lc >= TC || e >= n) return;
+    const int t = e * B + (threadIdx.x - lc * B);
     const int K = parent[e];
-    const T* Pe = P + (size_t)e * B * B + i;
+    const T* Pe = P + (size_t)tile * B * TR + threadIdx.x;
     const T* v = xc + (size_t)K * B;
     T acc = 0;
     if (dc) {
         const T* w = dc + (size_t)K * B;
 #pragma unroll
-        for (int j = 0; j < B; ++j) acc += Pe[j * B] * (v[j] + w[j]);
+        for (int j = 0; j < B; ++j) acc += Pe[(size_t)j * TR] * (v[j] + w[j]);
     } else {
 #pragma unroll
-        for (int j = 0; j < B; ++j) acc += Pe[j * B] * v[j];
+        for (int j = 0; j < B; ++j) acc += Pe[(size_t)j * TR] * v[j];
     }
     x[t] += acc;
 }
 
 // ------------------------------------------------------------ coarse
-// Split-K dense GEMV with the symmetric coarse inverse (row-major, FP64):
-// partial[chunk][col] = sum_{rows in chunk} Ainv[row][col] * r[row].
-template <typename Tin>
-__global__ __launch_bounds__(kWG) void k_coarse_gemv(int32_t n, int32_t rows_per_chunk,
-                                                     const double* __restrict__ Ainv,
-                                                     const Tin* __restrict__ r,
-                                                     double* __restrict__ partial) {
-    const int col = blockIdx.x * kWG + threadIdx.x;
-    const int chunk = blockIdx.y;
-    const int r0 = chunk * rows_per_chunk;
-    const int r1 = min(n, r0 + rows_per_chunk);
-    if (col >= n) return;
-    double acc = 0.0;
-    for (int row = r0; row < r1; ++row) acc += Ainv[(size_t)row * n + col] * (double)r[row];
-    partial[(size_t)chunk * n + col] = acc;
-}
-
-template <typename Tout>
-__global__ __launch_bounds__(kWG) void k_coarse_reduce(int32_t n, int32_t nchunk,
-                                                       const double* __restrict__ partial,
-                                                       Tout* __restrict__ x) {
-    const int col = blockIdx.x * kWG + threadIdx.x;
-    if (col >= n) return;
-    double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += partial[(size_t)c * n + col];
-    x[col] = (Tout)s;
+// x = Ainv r with the dense symmetric FP64 coarse inverse (row-major): each
+// wave owns kCoarseRowsPerWave rows and reads them with coalesced loads; r is
+// staged in LDS chunk by chunk (converted to FP64) and shared by the
+// workgroup's 4 waves.
+constexpr int kCoarseRowsPerWave = 2;
+constexpr int kCoarseChunk = 4096;
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kWG) void k_coarse_solve(int32_t n, const double* __restrict__ Ainv,
+                                                      const Tin* __restrict__ r,
+                                                      Tout* __restrict__ x) {
+    __shared__ double rs[kCoarseChunk];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row0 = (blockIdx.x * (kWG / 64) + wave) * kCoarseRowsPerWave;
+    double acc[kCoarseRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kCoarseRowsPerWave; ++k) acc[k] = 0.0;
+    for (int c0 = 0; c0 < n; c0 += kCoarseChunk) {
+        const int len = min(kCoarseChunk, n - c0);
+        __syncthreads();
+        for (int k = threadIdx.x; k < len; k += kWG) rs[k] = (double)r[c0 + k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kCoarseRowsPerWave; ++k) {
+            const int row = row0 + k;
+            if (row < n) {
+                const double* a = Ainv + (size_t)row * n + c0;
+                double s = 0.0;
+                for (int c = lane; c < len; c += 64) s += a[c] * rs[c];
+                acc[k] += s;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kCoarseRowsPerWave; ++k) {
+        double s = acc[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        const int row = row0 + k;
+        if (lane == 0 && row < n) x[row] = (Tout)s;
+    }
 }
 
 // ------------------------------------------------------------ vectors
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_fill(int64_t N, T* __restrict__ x, T v) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t < N) x[t] = v;
+}
+
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(kWG) void k_cast(int64_t N, const Tin* __restrict__ a,
                                               const Tin* __restrict__ b, Tout* __restrict__ out) {

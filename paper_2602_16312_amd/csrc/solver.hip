@@ -59,11 +59,11 @@ static inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads 
 struct DevLevel {
     int32_t n = 0, nf = 0;
     int64_t N = 0;
-    int32_t *nbr_ptr = nullptr, *nbr_cell = nullptr, *nbr_code = nullptr;
+    int32_t *slot_ptr = nullptr, *snb = nullptr;          // tile-ELL structure
     int32_t *child_ptr = nullptr, *child_list = nullptr;  // children on level l-1
     int32_t* parent = nullptr;                             // parent on level l+1
-    double *diag64 = nullptr, *fblk64 = nullptr, *dinv64 = nullptr, *P64 = nullptr;
-    float *diag32 = nullptr, *fblk32 = nullptr, *dinv32 = nullptr, *P32 = nullptr;
+    double *vals64 = nullptr, *dinv64 = nullptr, *P64 = nullptr;
+    float *vals32 = nullptr, *dinv32 = nullptr, *P32 = nullptr;
     void *vb = nullptr, *vx = nullptr, *vx2 = nullptr, *vr = nullptr, *vd = nullptr, *vd2 = nullptr;
     double lam_lo = 0, lam_hi = 0;
 };
@@ -83,8 +83,6 @@ struct dgmg_solver {
     // coarse
     int64_t nc_dofs = 0;
     double* Ainv = nullptr;
-    double* cpart = nullptr;
-    int nchunk = 1, rows_per_chunk = 1;
     // outer PCG work
     double *r = nullptr, *z = nullptr, *zold = nullptr, *pv = nullptr, *q = nullptr, *bwork = nullptr;
     double *tmp64a = nullptr, *tmp64b = nullptr;
@@ -135,14 +133,21 @@ struct dgmg_solver {
 
 namespace dgmg {
 
-// row-major b x b blocks -> column-major, optionally converted
+// padded block stride of the device layout (whole 16-byte vectors)
+template <typename T>
+static size_t block_stride(int b) {
+    const size_t ev = 16 / sizeof(T);
+    return ((size_t)b * b + ev - 1) / ev * ev;
+}
+
+// row-major b x b blocks -> column-major with padded stride, converted to T
 template <typename T>
 static std::vector<T> to_colmajor(const std::vector<double>& a, int b) {
-    const size_t bb = (size_t)b * b, nblk = a.size() / bb;
-    std::vector<T> out(a.size());
+    const size_t bb = (size_t)b * b, nblk = a.size() / bb, bs = block_stride<T>(b);
+    std::vector<T> out(nblk * bs, (T)0);
     for (size_t k = 0; k < nblk; ++k)
         for (int i = 0; i < b; ++i)
-            for (int j = 0; j < b; ++j) out[k * bb + (size_t)j * b + i] = (T)a[k * bb + (size_t)i * b + j];
+            for (int j = 0; j < b; ++j) out[k * bs + (size_t)j * b + i] = (T)a[k * bb + (size_t)i * b + j];
     return out;
 }
 
@@ -150,11 +155,11 @@ template <typename T>
 static LevelArgs<T> largs(const DevLevel& L);
 template <>
 LevelArgs<double> largs<double>(const DevLevel& L) {
-    return {L.diag64, L.fblk64, L.dinv64, L.nbr_ptr, L.nbr_cell, L.nbr_code, L.n};
+    return {L.vals64, L.slot_ptr, L.snb, L.dinv64, L.n};
 }
 template <>
 LevelArgs<float> largs<float>(const DevLevel& L) {
-    return {L.diag32, L.fblk32, L.dinv32, L.nbr_ptr, L.nbr_cell, L.nbr_code, L.n};
+    return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n};
 }
 template <typename T>
 static const T* Pof(const DevLevel& L);
@@ -192,34 +197,51 @@ enum { PK_CHEB_STEP = 0, PK_RESIDUAL = 1, PK_APPLY = 2, PK_RESTRICT = 3, PK_PROL
 static int level_index(const dgmg_solver* s, const DevLevel& L) { return (int)(&L - s->lv.data()); }
 
 // ---------------------------------------------------------------- launchers
+template <typename T, int B>
+static unsigned tiles_for(const DevLevel& L) {
+    return (unsigned)((L.n + Tile<T, B>::TC - 1) / Tile<T, B>::TC);
+}
+// number of workgroups (tiles) of the block kernels on a level; also the
+// number of partial sums they write
 template <typename T>
-static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, T* y,
-                         const T* w, double* partial, hipStream_t st) {
+static unsigned level_tiles(const dgmg_solver* s, const DevLevel& L) {
+    unsigned g = 0;
+    DISPATCH_B(s->b, g = tiles_for<T, BV>(L));
+    return g;
+}
+template <typename T>
+static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, const T* w,
+                         double* partial, hipStream_t st) {
     ProfScope ps(s, PK_APPLY, level_index(s, L), st);
-    DISPATCH_B(s->b, k_apply<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(largs<T>(L), va, vb, y, w, partial));
+    DISPATCH_B(s->b, k_apply<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w, partial));
 }
 template <typename T>
 static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, const T* rhs,
-                            T* r, T* d, T c1, T* xout, double* partial, hipStream_t st) {
+                            T* r, T* d, T c1, T* xout, double* partial, hipStream_t st,
+                            const T* P = nullptr, T* rp = nullptr) {
     ProfScope ps(s, PK_RESIDUAL, level_index(s, L), st);
-    DISPATCH_B(s->b, k_residual<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(largs<T>(L), va, vb, rhs, r, d,
-                                                                         c1, xout, partial));
+    if (vb) {
+        DISPATCH_B(s->b, k_residual<T, BV, true><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                             largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+    } else {
+        DISPATCH_B(s->b, k_residual<T, BV, false><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                             largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+    }
 }
 template <typename T>
 static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* r, T* dn, T cd, T cr,
                         int assign, hipStream_t st) {
     ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
-    DISPATCH_B(s->b, k_cheb_step<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(largs<T>(L), d, x, r, dn, cd, cr,
-                                                                          assign));
+    DISPATCH_B(s->b, k_cheb_step<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r, dn, cd,
+                                                                              cr, assign));
 }
 
 template <typename T>
 static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
     const int n = (int)s->nc_dofs;
     ProfScope ps(s, PK_COARSE, s->L - 1, st);
-    dim3 g(blocks_for(n), s->nchunk);
-    k_coarse_gemv<T><<<g, kWG, 0, st>>>(n, s->rows_per_chunk, s->Ainv, rc, s->cpart);
-    k_coarse_reduce<T><<<blocks_for(n), kWG, 0, st>>>(n, s->nchunk, s->cpart, xc);
+    const int rows_per_wg = (kWG / 64) * kCoarseRowsPerWave;
+    k_coarse_solve<T, T><<<(n + rows_per_wg - 1) / rows_per_wg, kWG, 0, st>>>(n, s->Ainv, rc, xc);
 }
 
 // One V-cycle from level l; the result is x + d (d may be null).
@@ -262,33 +284,34 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
         pending = true;
     };
     for (int k = 0; k < s->cheb_s; ++k) sweep();
-    // residual for the coarse correction, materialising the pending update
+    // residual for the coarse correction (materialising the pending update),
+    // with the per-cell restriction partials P_e^T r_e in its epilogue
     DevLevel& C = s->lv[l + 1];
+    T* rp = d2;   // free: the pending d is consumed here
     if (pending) {
-        launch_residual<T>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, (T*)nullptr, c1, x2, nullptr, st);
+        launch_residual<T>(s, L, xzero ? d : x, xzero ? nullptr : d, b, (T*)nullptr, (T*)nullptr, c1, x2,
+                           nullptr, st, Pof<T>(L), rp);
         std::swap(x, x2);
         xzero = false;
         pending = false;
-    } else if (xzero) {
-        hipMemcpyAsync(r, b, L.N * sizeof(T), hipMemcpyDeviceToDevice, st);
     } else {
-        launch_residual<T>(s, L, x, (const T*)nullptr, b, r, (T*)nullptr, c1, (T*)nullptr, nullptr, st);
+        // no smoothing: x = 0 and r = b
+        k_fill<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, x, (T)0);
+        xzero = false;
+        launch_residual<T>(s, L, x, (const T*)nullptr, b, (T*)nullptr, (T*)nullptr, c1, (T*)nullptr,
+                           nullptr, st, Pof<T>(L), rp);
     }
     {
     ProfScope ps(s, PK_RESTRICT, l, st);
-    DISPATCH_B(s->b, k_restrict<T, BV><<<blocks_for(C.N), kWG, 0, st>>>(C.n, C.child_ptr, C.child_list,
-                                                                         Pof<T>(L), r, (T*)C.vb));
+    DISPATCH_B(s->b, k_restrict_sum<T, BV><<<blocks_for(C.N), kWG, 0, st>>>(C.n, C.child_ptr, C.child_list,
+                                                                             rp, (T*)C.vb));
     }
     T *xc, *dc;
     vcycle<T>(s, l + 1, st, &xc, &dc);
-    if (xzero) {
-        hipMemsetAsync(x, 0, L.N * sizeof(T), st);
-        xzero = false;
-    }
     {
     ProfScope ps(s, PK_PROLONG, l, st);
-    DISPATCH_B(s->b, k_prolong_add<T, BV><<<blocks_for(L.N), kWG, 0, st>>>(L.n, L.parent, Pof<T>(L), xc,
-                                                                             dc, x));
+    DISPATCH_B(s->b, k_prolong_add<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent, Pof<T>(L), xc,
+                                                                                 dc, x));
     }
     for (int k = 0; k < s->cheb_s; ++k) sweep();
     // hand back the level's buffers as they are now named
@@ -327,9 +350,10 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
     const int64_t N = s->N;
     const unsigned nb = blocks_for(N);
     DevLevel& L0 = s->lv[0];
+    const unsigned nt = level_tiles<double>(s, L0);   // partials of the block kernels
     // r = b - A x, ||r||^2
     launch_residual<double>(s, L0, x, nullptr, b, s->r, nullptr, 1.0, nullptr, s->partial, st);
-    k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 0, 0);
+    k_finalize<<<1, kWG, 0, st>>>(nt, s->partial, s->sc, 0, 0);
     double bnorm = 0.0;
     if (o.tol_mode == DGMG_TOL_REL_B) {
         k_dot<<<nb, kWG, 0, st>>>(N, b, b, s->partial);
@@ -354,8 +378,8 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
     k_update_p<<<nb, kWG, 0, st>>>(N, s->sc, s->z, s->pv, 1);
     int its = 0;
     while (its < o.max_it) {
-        launch_apply<double>(s, L0, s->pv, nullptr, s->q, s->pv, s->partial, st);
-        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 2, 0);
+        launch_apply<double>(s, L0, s->pv, s->q, s->pv, s->partial, st);
+        k_finalize<<<1, kWG, 0, st>>>(nt, s->partial, s->sc, 2, 0);
         k_update_xr<<<nb, kWG, 0, st>>>(N, s->sc, s->pv, s->q, x, s->r, s->partial);
         k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 0, 0);
         read_scalars(s, st);
@@ -407,6 +431,77 @@ static void build_nbr(const BlockOp& A, std::vector<int32_t>& ptr, std::vector<i
     }
 }
 
+// Tile-ELL layout of a level operator (see kernels.hpp): per tile of
+// TC = 256/b cells, slot 0 holds the cell blocks and slot r >= 1 the r-th
+// neighbour block of every cell, oriented for the row cell and interleaved
+// so that the tile's rows are contiguous for each (slot, column).
+struct TileEll {
+    std::vector<int32_t> slot_ptr, snb;
+    std::vector<double> vals;
+};
+static TileEll build_tile_ell(const BlockOp& A) {
+    const int b = A.b, TC = kWG / b, TR = TC * b;
+    const int64_t n = A.n, ntiles = (n + TC - 1) / TC;
+    std::vector<int32_t> ptr, cell, code;
+    build_nbr(A, ptr, cell, code);
+    TileEll E;
+    E.slot_ptr.assign(ntiles + 1, 0);
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int mx = 0;
+        for (int lc = 0; lc < TC; ++lc) {
+            const int64_t c = t * TC + lc;
+            if (c < n) mx = std::max(mx, ptr[c + 1] - ptr[c]);
+        }
+        E.slot_ptr[t + 1] = E.slot_ptr[t] + 1 + mx;
+    }
+    const int64_t nslots = E.slot_ptr[ntiles];
+    E.vals.assign((size_t)nslots * b * TR, 0.0);
+    E.snb.assign((size_t)nslots * TC, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int64_t s0 = E.slot_ptr[t], ns = E.slot_ptr[t + 1] - s0;
+        for (int lc = 0; lc < TC; ++lc) {
+            const int64_t c = t * TC + lc;
+            if (c >= n) continue;
+            for (int64_t sl = 0; sl < ns; ++sl) E.snb[(size_t)(s0 + sl) * TC + lc] = (int32_t)c;
+            auto put = [&](int64_t gs, const double* blk, bool transpose) {
+                for (int i = 0; i < b; ++i)
+                    for (int j = 0; j < b; ++j)
+                        E.vals[((size_t)gs * b + j) * TR + (size_t)lc * b + i] =
+                            transpose ? blk[j * b + i] : blk[i * b + j];
+            };
+            put(s0, &A.diag[(size_t)c * b * b], false);
+            for (int32_t e = ptr[c]; e < ptr[c + 1]; ++e) {
+                const int64_t gs = s0 + 1 + (e - ptr[c]);
+                E.snb[(size_t)gs * TC + lc] = cell[e];
+                put(gs, &A.fblk[(size_t)(code[e] >> 1) * b * b], (code[e] & 1) != 0);
+            }
+        }
+    }
+    return E;
+}
+
+// prolongation blocks (row-major per fine entity) in tile-interleaved layout
+template <typename T>
+static std::vector<T> interleave_P(const std::vector<double>& P, int b, int64_t n) {
+    const int TC = kWG / b, TR = TC * b;
+    const int64_t ntiles = (n + TC - 1) / TC;
+    std::vector<T> out((size_t)ntiles * b * TR, (T)0);
+    for (int64_t e = 0; e < n; ++e) {
+        const int64_t t = e / TC;
+        const int lc = (int)(e - t * TC);
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j)
+                out[((size_t)t * b + j) * TR + (size_t)lc * b + i] = (T)P[((size_t)e * b + i) * b + j];
+    }
+    return out;
+}
+
+template <typename T>
+static std::vector<T> convert(const std::vector<double>& a) {
+    return std::vector<T>(a.begin(), a.end());
+}
+
 static void upload_level(dgmg_solver* s, int l) {
     const BlockOp& A = s->ops[l];
     DevLevel& L = s->lv[l];
@@ -414,31 +509,26 @@ static void upload_level(dgmg_solver* s, int l) {
     L.n = (int32_t)A.n;
     L.nf = (int32_t)A.nf;
     L.N = A.n * b;
-    std::vector<int32_t> ptr, cell, code;
-    build_nbr(A, ptr, cell, code);
-    L.nbr_ptr = s->upload(ptr);
-    L.nbr_cell = s->upload(cell);
-    L.nbr_code = s->upload(code);
     std::vector<double> dinv(L.N);
     for (int64_t K = 0; K < A.n; ++K)
         for (int i = 0; i < b; ++i) dinv[K * b + i] = 1.0 / A.diag[((size_t)K * b + i) * b + i];
     const bool last = (l == s->L - 1);
     if (!last || s->L == 1) {
-        L.diag64 = s->upload(to_colmajor<double>(A.diag, b));
-        L.fblk64 = s->upload(to_colmajor<double>(A.fblk, b));
+        TileEll E = build_tile_ell(A);
+        L.slot_ptr = s->upload(E.slot_ptr);
+        L.snb = s->upload(E.snb);
+        L.vals64 = s->upload(E.vals);
         L.dinv64 = s->upload(dinv);
         if (s->prec == DGMG_PREC_MIXED) {
-            L.diag32 = s->upload(to_colmajor<float>(A.diag, b));
-            L.fblk32 = s->upload(to_colmajor<float>(A.fblk, b));
-            std::vector<float> df(dinv.begin(), dinv.end());
-            L.dinv32 = s->upload(df);
+            L.vals32 = s->upload(convert<float>(E.vals));
+            L.dinv32 = s->upload(convert<float>(dinv));
         }
     }
     if (!last) {
         std::vector<int32_t> par(s->parents[l].begin(), s->parents[l].end());
         L.parent = s->upload(par);
-        L.P64 = s->upload(to_colmajor<double>(s->Ph[l], b));
-        if (s->prec == DGMG_PREC_MIXED) L.P32 = s->upload(to_colmajor<float>(s->Ph[l], b));
+        L.P64 = s->upload(interleave_P<double>(s->Ph[l], b, A.n));
+        if (s->prec == DGMG_PREC_MIXED) L.P32 = s->upload(interleave_P<float>(s->Ph[l], b, A.n));
     }
     if (l > 0) {
         const auto& par = s->parents[l - 1];
@@ -693,12 +783,6 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     if (mg->device_setup) {
         for (int l = 0; l < s->L; ++l) upload_level(s, l);
         s->Ainv = s->upload(Ac);
-        const int n = (int)s->nc_dofs;
-        const int colblk = (n + kWG - 1) / kWG;
-        int nchunk = std::max(1, std::min(n / 8, 1024 / colblk));
-        s->rows_per_chunk = (n + nchunk - 1) / nchunk;
-        s->nchunk = (n + s->rows_per_chunk - 1) / s->rows_per_chunk;
-        s->cpart = s->dalloc<double>((size_t)s->nchunk * n);
         const int64_t N = s->N;
         s->r = s->dalloc<double>(N);
         s->z = s->dalloc<double>(N);
@@ -708,7 +792,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         s->bwork = s->dalloc<double>(N);
         s->tmp64a = s->dalloc<double>(N);
         s->tmp64b = s->dalloc<double>(N);
-        s->partial = s->dalloc<double>(blocks_for(N) + 16);
+        s->partial = s->dalloc<double>(std::max(blocks_for(N), level_tiles<double>(s, s->lv[0])) + 16);
         s->sc = s->dalloc<double>(8);
         HIPCHK(hipMemset(s->sc, 0, 8 * sizeof(double)));
         HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * sizeof(double), hipHostMallocDefault));
@@ -788,11 +872,11 @@ int dgmg_apply(dgmg_solver* s, int32_t level, int32_t prec, const double* x, dou
     DevLevel& L = s->lv[level];
     if (level == s->L - 1 && s->L > 1) fail(DGMG_EUNSUPPORTED, "the coarsest level is stored factorised");
     if (prec == DGMG_PREC_FP64) {
-        launch_apply<double>(s, L, x, nullptr, y, nullptr, nullptr, hs);
+        launch_apply<double>(s, L, x, y, nullptr, nullptr, hs);
     } else {
         if (s->prec != DGMG_PREC_MIXED) fail(DGMG_EINVAL, "no FP32 copy in an FP64 solver");
         k_cast<double, float><<<blocks_for(L.N), kWG, 0, hs>>>(L.N, x, nullptr, (float*)L.vx2);
-        launch_apply<float>(s, L, (float*)L.vx2, nullptr, (float*)L.vr, nullptr, nullptr, hs);
+        launch_apply<float>(s, L, (float*)L.vx2, (float*)L.vr, nullptr, nullptr, hs);
         k_cast<float, double><<<blocks_for(L.N), kWG, 0, hs>>>(L.N, (float*)L.vr, nullptr, y);
     }
     HIPCHK(hipGetLastError());
@@ -845,6 +929,49 @@ int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms) {
     s->prof_kind = -1;
     s->prof_level = -1;
     s->prof_used = 0;
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t reps, void* stream,
+                      double* avg_ms) {
+    API_BEGIN
+    need_device(s);
+    if (level < 0 || level >= s->L - 1 || reps < 1) fail(DGMG_EINVAL, "bad level or repetition count");
+    if (kind != PK_CHEB_STEP && kind != PK_RESIDUAL) fail(DGMG_EINVAL, "kernel kind not benchmarkable");
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel& L = s->lv[level];
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        T *x = (T*)L.vx, *r = (T*)L.vr, *d = (T*)L.vd, *d2 = (T*)L.vd2, *x2 = (T*)L.vx2;
+        const T* bb = (const T*)L.vb;
+        const T* dinv = largs<T>(L).dinv;
+        // defined inputs: x = d = dinv, r = b
+        k_cast<T, T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, dinv, nullptr, x);
+        k_cast<T, T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, dinv, nullptr, d);
+        k_cast<T, T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, dinv, nullptr, r);
+        HIPCHK(hipEventRecord(a, st));
+        for (int k = 0; k < reps; ++k) {
+            if (kind == PK_CHEB_STEP) {
+                launch_step<T>(s, L, d, x, r, d2, (T)0.5, (T)0.1, 0, st);
+                std::swap(d, d2);
+            } else {
+                launch_residual<T>(s, L, x, d, bb ? bb : r, r, d2, (T)0.5, x2, nullptr, st);
+            }
+        }
+        HIPCHK(hipEventRecord(b, st));
+    };
+    if (s->prec == DGMG_PREC_MIXED) run(float{});
+    else run(double{});
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / reps;
     return DGMG_OK;
     API_END
 }
