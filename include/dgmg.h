@@ -131,7 +131,9 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * (lo, hi) per smoothed level) replaces the estimate.  precision MIXED runs
  * the V-cycle in FP32 with the coarse solve and the outer PCG in FP64.
  * device_setup = 0 stops after the host setup (inspection on machines
- * without a GPU; solve calls then fail with DGMG_EINVAL). */
+ * without a GPU; solve calls then fail with DGMG_EINVAL).  adjoint = 1 also
+ * stores the conductivity derivatives dA/ds_K (cell stiffness and per-side
+ * face matrices, FP64) needed by dgmg_grad_accumulate (FHN and AP models). */
 typedef struct {
     int32_t cheb_degree;
     int32_t cheb_sweeps;
@@ -141,6 +143,7 @@ typedef struct {
     const double* lam_override;
     int32_t precision;
     int32_t device_setup;
+    int32_t adjoint;
 } dgmg_mg_opts;
 
 /* Assembles A_0 = 3 chi C_m/(2 dt) M + A (eq. fully_discrete; bdf = 1 uses
@@ -234,6 +237,31 @@ int dgmg_mass_apply(dgmg_solver* s, const double* f, double* b, void* stream);
 int dgmg_export_level(const dgmg_solver* s, int32_t level, double* diag,
                       int64_t* face_cells, double* face_blocks, double* prolong,
                       int64_t* parents);
+
+/* ---- discrete adjoint (gradient of a sensor misfit with respect to the
+ * per-cell conductivity scalings s_K, D_K -> s_K D_K; extension of the
+ * time stepping of section 3.1).  A(s) = sum_K s_K dA/ds_K. ---- */
+
+/* Sensors: host cells (n) and host reference points (n x dim, in [0,1]^dim)
+ * of the evaluation functionals e_k^T U = sum_i U[cell_k, i] phi_i(ref_k). */
+int dgmg_set_sensors(dgmg_solver* s, int32_t n, const int64_t* cells, const double* ref);
+/* r_k = e_k^T U - target_k (device target: n floats); device loss[0] +=
+ * sum_k r_k^2; when device Ubar (N) is non-NULL, Ubar += sum_k 2 r_k e_k. */
+int dgmg_sensor_misfit(dgmg_solver* s, const double* U, const double* target, double* Ubar,
+                       double* loss, void* stream);
+/* Reverse of the ionic update and load vector of the step that produced
+ * U_{n+1} from the state (U = U_n, Uprev = U_{n-1}, W = W_n, Wprev = W_{n-1}):
+ * given device lambda = A_0^-1 Ubar_{n+1} (N) and the incoming adjoint of
+ * W_{n+1} (device Wbar_in, S x N), accumulates into device Ubar (of U_n),
+ * Uprevbar (of U_{n-1}), Wbar (of W_n), Wprevbar (of W_{n-1}).  Needs
+ * adjoint = 1 at set-up. */
+int dgmg_adjoint_step(dgmg_solver* s, const double* U, const double* Uprev, const double* W,
+                      const double* Wprev, const double* lambda, const double* Wbar_in, double* Ubar,
+                      double* Uprevbar, double* Wbar, double* Wprevbar, void* stream);
+/* device grad[K] += -lambda^T (dA/ds_K) U over the cell and face blocks of K
+ * (device lambda, U: N; grad: n_cells).  Needs adjoint = 1 at set-up. */
+int dgmg_grad_accumulate(dgmg_solver* s, const double* lambda, const double* U, double* grad,
+                         void* stream);
 
 /* Kernel timing with HIP events recorded on the caller's stream around every
  * launch of one kernel kind on one level, between begin and end: kind 0 the

@@ -17,6 +17,7 @@ EXPORTS = [
     "dgmg_get_info", "dgmg_pcg_solve", "dgmg_ionic_step", "dgmg_time_step",
     "dgmg_apply", "dgmg_vcycle", "dgmg_mass_apply", "dgmg_export_level",
     "dgmg_profile_begin", "dgmg_profile_end", "dgmg_kernel_bench", "dgmg_last_error",
+    "dgmg_set_sensors", "dgmg_sensor_misfit", "dgmg_adjoint_step", "dgmg_grad_accumulate",
 ]
 
 dp = C.POINTER(C.c_double)
@@ -49,7 +50,8 @@ class MGOpts(C.Structure):
     _fields_ = [("cheb_degree", C.c_int32), ("cheb_sweeps", C.c_int32),
                 ("lanczos_steps", C.c_int32), ("lam_safety", C.c_double),
                 ("smooth_range", C.c_double), ("lam_override", dp),
-                ("precision", C.c_int32), ("device_setup", C.c_int32)]
+                ("precision", C.c_int32), ("device_setup", C.c_int32),
+                ("adjoint", C.c_int32)]
 
 
 class SolverInfo(C.Structure):
@@ -116,6 +118,10 @@ def lib():
         L.dgmg_profile_begin.argtypes = [vp, C.c_int32, C.c_int32]
         L.dgmg_profile_end.argtypes = [vp, i64p, dp]
         L.dgmg_kernel_bench.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, dp]
+        L.dgmg_set_sensors.argtypes = [vp, C.c_int32, i64p, dp]
+        L.dgmg_sensor_misfit.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.dgmg_adjoint_step.argtypes = [vp] * 12
+        L.dgmg_grad_accumulate.argtypes = [vp, vp, vp, vp, vp]
         L.dgmg_last_error.restype = C.c_char_p
         _lib = L
     return _lib

@@ -147,7 +147,7 @@ class Solver:
 def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",),
                  bdf=2, cell_scale=None, precision="fp64", cheb_degree=3,
                  cheb_sweeps=3, lanczos_steps=20, lam_safety=1.2,
-                 smooth_range=20.0, lam_override=None, device_setup=True):
+                 smooth_range=20.0, lam_override=None, device_setup=True, adjoint=False):
     """dgmg_setup_levels: assembly, Galerkin hierarchy, smoother, coarse factor."""
     d = F.Disc(p, 0 if penalty[0] == "paper" else 1,
                float(penalty[1]) if len(penalty) > 1 else 0.0)
@@ -164,7 +164,7 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
         lam, lo = _dptr(np.asarray(lam_override, dtype=np.float64).ravel())
         keep.append(lam)
     mg = F.MGOpts(cheb_degree, cheb_sweeps, lanczos_steps, lam_safety, smooth_range,
-                  lo, PRECISIONS[precision], 1 if device_setup else 0)
+                  lo, PRECISIONS[precision], 1 if device_setup else 0, 1 if adjoint else 0)
     s = C.c_void_p()
     F.check(F.lib().dgmg_setup_levels(hier.handle, C.byref(d), C.byref(ph), C.byref(mg),
                                       C.byref(s)))
@@ -267,3 +267,30 @@ def kernel_bench(solver, kind="cheb_step", level=0, reps=200, stream=None):
     F.check(F.lib().dgmg_kernel_bench(solver.handle, KERNEL_KINDS[kind], level, reps,
                                       _stream(stream), C.byref(ms)))
     return ms.value
+
+
+def set_sensors(solver, cells, ref):
+    """dgmg_set_sensors: point-evaluation functionals (cell, reference point)."""
+    cells, cp = _iptr(cells)
+    ref, rp = _dptr(ref)
+    F.check(F.lib().dgmg_set_sensors(solver.handle, len(cells), cp, rp))
+
+
+def sensor_misfit(solver, U, target, Ubar, loss, stream=None):
+    """dgmg_sensor_misfit: loss += |E U - target|^2; Ubar += 2 E^T (E U - target)."""
+    F.check(F.lib().dgmg_sensor_misfit(solver.handle, _dev(U), _dev(target), _dev(Ubar),
+                                       _dev(loss), _stream(stream)))
+
+
+def adjoint_step(solver, U, Uprev, W, Wprev, lam, Wbar_in, Ubar, Uprevbar, Wbar, Wprevbar,
+                 stream=None):
+    """dgmg_adjoint_step: reverse of the ionic update and load vector of a step."""
+    F.check(F.lib().dgmg_adjoint_step(solver.handle, _dev(U), _dev(Uprev), _dev(W), _dev(Wprev),
+                                      _dev(lam), _dev(Wbar_in), _dev(Ubar), _dev(Uprevbar),
+                                      _dev(Wbar), _dev(Wprevbar), _stream(stream)))
+
+
+def grad_accumulate(solver, lam, U, grad, stream=None):
+    """dgmg_grad_accumulate: grad_K -= lambda^T dA/ds_K U."""
+    F.check(F.lib().dgmg_grad_accumulate(solver.handle, _dev(lam), _dev(U), _dev(grad),
+                                         _stream(stream)))

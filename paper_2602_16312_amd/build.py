@@ -39,7 +39,8 @@ def build(verbose=False):
         _run([HIPCC, "-x", "hip"] + DEVICE_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC] + DEVICE_FLAGS + ["-shared", "-fopenmp", "-o", tmp] + objs)
+    _run([HIPCC] + DEVICE_FLAGS + ["-shared", "-fopenmp", "-o", tmp] + objs +
+         ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

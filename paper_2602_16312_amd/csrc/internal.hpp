@@ -65,10 +65,15 @@ struct Faces {                                 // interior faces of the fine mes
 };
 
 Faces find_faces(const Hierarchy& h);
+// dA/ds_K pieces: unscaled cell stiffness S_K (n x b x b, row-major) and, per
+// face, the face matrices of each side alone (2 x 2b x 2b over [K+, K-] DoFs)
+struct AdjointBlocks {
+    std::vector<double> S, X;
+};
 // Assembles A_0 = cM * M + A (cell and face blocks) and the per-cell mass blocks.
 void assemble_fine(const Hierarchy& h, const Faces& F, const RefElement& re,
                    const dgmg_disc& disc, const dgmg_physics& ph, double cM, BlockOp& A0,
-                   std::vector<double>& mass);
+                   std::vector<double>& mass, AdjointBlocks* adj = nullptr);
 
 // Prolongation blocks P_e (n_l x b x b, row-major: fine node i, coarse basis j)
 // from level l+1 to level l, with per-level bounding boxes.

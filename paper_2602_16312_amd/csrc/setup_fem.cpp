@@ -289,7 +289,7 @@ static void corners_of(const Hierarchy& h, int64_t c, double* X) {
 
 void assemble_fine(const Hierarchy& h, const Faces& F, const RefElement& re,
                    const dgmg_disc& disc, const dgmg_physics& ph, double cM, BlockOp& A0,
-                   std::vector<double>& mass) {
+                   std::vector<double>& mass, AdjointBlocks* adj) {
     const int d = re.d, b = re.b, bb = b * b, symn = d * (d + 1) / 2;
     const int64_t n = h.n_cells;
     A0.n = n;
@@ -297,14 +297,19 @@ void assemble_fine(const Hierarchy& h, const Faces& F, const RefElement& re,
     A0.diag.assign((size_t)n * bb, 0.0);
     mass.assign((size_t)n * bb, 0.0);
     std::vector<double> vol(n, 0.0);
+    if (adj) {
+        adj->S.assign((size_t)n * bb, 0.0);
+        adj->X.assign((size_t)F.plus.size() * 2 * 4 * bb, 0.0);
+    }
     int bad = 0;
 
 #pragma omp parallel for schedule(static) reduction(+ : bad)
     for (int64_t c = 0; c < n; ++c) {
         double X[24], D[9], J[9], det, JiT[9];
         corners_of(h, c, X);
-        unpack_D(d, &ph.D_cell[(size_t)c * symn], ph.cell_scale ? ph.cell_scale[c] : 1.0, D);
-        std::vector<double> G((size_t)b * d), DG((size_t)b * d);
+        const double sc = ph.cell_scale ? ph.cell_scale[c] : 1.0;
+        unpack_D(d, &ph.D_cell[(size_t)c * symn], 1.0, D);   // unscaled: S_K is linear in D
+        std::vector<double> G((size_t)b * d), DG((size_t)b * d), Sun((size_t)bb, 0.0);
         double* Md = &mass[(size_t)c * bb];
         double* Ad = &A0.diag[(size_t)c * bb];
         double v = 0.0;
@@ -332,11 +337,12 @@ void assemble_fine(const Hierarchy& h, const Faces& F, const RefElement& re,
                     double s = 0.0;
                     for (int a = 0; a < d; ++a) s += G[i * d + a] * DG[j * d + a];
                     Md[i * b + j] += wd * phi[i] * phi[j];
-                    Ad[i * b + j] += wd * s;
+                    Sun[i * b + j] += wd * s;
                 }
         }
         vol[c] = v;
-        for (int k = 0; k < bb; ++k) Ad[k] += cM * Md[k];
+        for (int k = 0; k < bb; ++k) Ad[k] = sc * Sun[k] + cM * Md[k];
+        if (adj) std::copy(Sun.begin(), Sun.end(), adj->S.begin() + (size_t)c * bb);
     }
     if (bad) fail(DGMG_EINVAL, "non-positive Jacobian determinant in the mesh");
 
@@ -375,6 +381,76 @@ void assemble_fine(const Hierarchy& h, const Faces& F, const RefElement& re,
         }
     }
     const int B2 = 2 * b;
+    // local 2b x 2b matrix of the face terms of a_h over [K+ DoFs, K- DoFs]
+    // for the given (already scaled) tensors of the two sides
+    auto face_local = [&](int64_t f, const double* Dp, const double* Dm, double* L) {
+        const int64_t cp = F.plus[f], cm = F.minus[f];
+        const int ax = F.axis[f];
+        double Xp[24], Xm[24], J[9], detp, detm, JiTp[9], JiTm[9];
+        corners_of(h, cp, Xp);
+        corners_of(h, cm, Xm);
+        std::fill(L, L + (size_t)B2 * B2, 0.0);
+        // |F| first (needed by the paper's penalty)
+        std::vector<double> nrmv((size_t)qf * d), dS(qf);
+        double area = 0.0;
+        for (int iq = 0; iq < qf; ++iq) {
+            size_t o = (size_t)ax * qf + iq;
+            cell_map(d, Xp, &fxi_p[o * d], nullptr, J, &detp, JiTp);
+            double nv[3], nn = 0.0;
+            for (int a = 0; a < d; ++a) {
+                nv[a] = JiTp[a * d + ax];
+                nn += nv[a] * nv[a];
+            }
+            nn = std::sqrt(nn);
+            for (int a = 0; a < d; ++a) nrmv[(size_t)iq * d + a] = nv[a] / nn;
+            dS[iq] = fw[o] * std::fabs(detp) * nn;
+            area += dS[iq];
+        }
+        const double cpen = disc.eta > 0.0 ? disc.eta : 1.0;
+        double eta = disc.penalty_mode == DGMG_PENALTY_FIXED
+                         ? disc.eta
+                         : cpen * re.p * (re.p + 1) * 0.5 * (area / vol[cp] + area / vol[cm]);
+        std::vector<double> jump(B2), flux(B2);
+        for (int iq = 0; iq < qf; ++iq) {
+            size_t o = (size_t)ax * qf + iq;
+            cell_map(d, Xp, &fxi_p[o * d], nullptr, J, &detp, JiTp);
+            cell_map(d, Xm, &fxi_m[o * d], nullptr, J, &detm, JiTm);
+            const double* nv = &nrmv[(size_t)iq * d];
+            double Dnp[3], Dnm[3], nDn = 0.0;
+            for (int a = 0; a < d; ++a) {
+                Dnp[a] = Dnm[a] = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    Dnp[a] += Dp[a * d + k] * nv[k];
+                    Dnm[a] += Dm[a * d + k] * nv[k];
+                }
+            }
+            for (int a = 0; a < d; ++a) nDn += 0.5 * nv[a] * (Dnp[a] + Dnm[a]);
+            const double sig = eta * nDn;
+            for (int i = 0; i < b; ++i) {
+                const double* gp = &fg_p[(o * b + i) * d];
+                const double* gm = &fg_m[(o * b + i) * d];
+                double fp = 0.0, fm = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    double Gp = 0.0, Gm = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        Gp += JiTp[a * d + k] * gp[k];
+                        Gm += JiTm[a * d + k] * gm[k];
+                    }
+                    fp += Gp * Dnp[a];
+                    fm += Gm * Dnm[a];
+                }
+                jump[i] = fphi_p[o * b + i];
+                jump[b + i] = -fphi_m[o * b + i];
+                flux[i] = fp;
+                flux[b + i] = fm;
+            }
+            const double w = dS[iq];
+            for (int I = 0; I < B2; ++I)
+                for (int Jx = 0; Jx < B2; ++Jx)
+                    L[I * B2 + Jx] += w * (-0.5 * jump[I] * flux[Jx] - 0.5 * flux[I] * jump[Jx] +
+                                           sig * jump[I] * jump[Jx]);
+        }
+    };
     const int64_t chunk = 16384;
     std::vector<double> loc((size_t)chunk * B2 * B2);
     for (int64_t f0 = 0; f0 < nf; f0 += chunk) {
@@ -382,73 +458,17 @@ void assemble_fine(const Hierarchy& h, const Faces& F, const RefElement& re,
 #pragma omp parallel for schedule(static)
         for (int64_t f = f0; f < f1; ++f) {
             const int64_t cp = F.plus[f], cm = F.minus[f];
-            const int ax = F.axis[f];
-            double Xp[24], Xm[24], Dp[9], Dm[9], J[9], detp, detm, JiTp[9], JiTm[9];
-            corners_of(h, cp, Xp);
-            corners_of(h, cm, Xm);
+            double Dp[9], Dm[9], Z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             unpack_D(d, &ph.D_cell[(size_t)cp * symn], ph.cell_scale ? ph.cell_scale[cp] : 1.0, Dp);
             unpack_D(d, &ph.D_cell[(size_t)cm * symn], ph.cell_scale ? ph.cell_scale[cm] : 1.0, Dm);
-            double* L = &loc[(size_t)(f - f0) * B2 * B2];
-            std::fill(L, L + (size_t)B2 * B2, 0.0);
-            // |F| first (needed by the paper's penalty)
-            std::vector<double> nrmv((size_t)qf * d), dS(qf);
-            double area = 0.0;
-            for (int iq = 0; iq < qf; ++iq) {
-                size_t o = (size_t)ax * qf + iq;
-                cell_map(d, Xp, &fxi_p[o * d], nullptr, J, &detp, JiTp);
-                double nv[3], nn = 0.0;
-                for (int a = 0; a < d; ++a) {
-                    nv[a] = JiTp[a * d + ax];
-                    nn += nv[a] * nv[a];
-                }
-                nn = std::sqrt(nn);
-                for (int a = 0; a < d; ++a) nrmv[(size_t)iq * d + a] = nv[a] / nn;
-                dS[iq] = fw[o] * std::fabs(detp) * nn;
-                area += dS[iq];
-            }
-            const double cpen = disc.eta > 0.0 ? disc.eta : 1.0;
-            double eta = disc.penalty_mode == DGMG_PENALTY_FIXED
-                             ? disc.eta
-                             : cpen * re.p * (re.p + 1) * 0.5 * (area / vol[cp] + area / vol[cm]);
-            std::vector<double> jump(B2), flux(B2);
-            for (int iq = 0; iq < qf; ++iq) {
-                size_t o = (size_t)ax * qf + iq;
-                cell_map(d, Xp, &fxi_p[o * d], nullptr, J, &detp, JiTp);
-                cell_map(d, Xm, &fxi_m[o * d], nullptr, J, &detm, JiTm);
-                const double* nv = &nrmv[(size_t)iq * d];
-                double Dnp[3], Dnm[3], nDn = 0.0;
-                for (int a = 0; a < d; ++a) {
-                    Dnp[a] = Dnm[a] = 0.0;
-                    for (int k = 0; k < d; ++k) {
-                        Dnp[a] += Dp[a * d + k] * nv[k];
-                        Dnm[a] += Dm[a * d + k] * nv[k];
-                    }
-                }
-                for (int a = 0; a < d; ++a) nDn += 0.5 * nv[a] * (Dnp[a] + Dnm[a]);
-                const double sig = eta * nDn;
-                for (int i = 0; i < b; ++i) {
-                    const double* gp = &fg_p[(o * b + i) * d];
-                    const double* gm = &fg_m[(o * b + i) * d];
-                    double fp = 0.0, fm = 0.0;
-                    for (int a = 0; a < d; ++a) {
-                        double Gp = 0.0, Gm = 0.0;
-                        for (int k = 0; k < d; ++k) {
-                            Gp += JiTp[a * d + k] * gp[k];
-                            Gm += JiTm[a * d + k] * gm[k];
-                        }
-                        fp += Gp * Dnp[a];
-                        fm += Gm * Dnm[a];
-                    }
-                    jump[i] = fphi_p[o * b + i];
-                    jump[b + i] = -fphi_m[o * b + i];
-                    flux[i] = fp;
-                    flux[b + i] = fm;
-                }
-                const double w = dS[iq];
-                for (int I = 0; I < B2; ++I)
-                    for (int Jx = 0; Jx < B2; ++Jx)
-                        L[I * B2 + Jx] += w * (-0.5 * jump[I] * flux[Jx] - 0.5 * flux[I] * jump[Jx] +
-                                               sig * jump[I] * jump[Jx]);
+            face_local(f, Dp, Dm, &loc[(size_t)(f - f0) * B2 * B2]);
+            if (adj) {
+                // side-split derivative blocks with the unscaled tensors
+                double Up[9], Um[9];
+                unpack_D(d, &ph.D_cell[(size_t)cp * symn], 1.0, Up);
+                unpack_D(d, &ph.D_cell[(size_t)cm * symn], 1.0, Um);
+                face_local(f, Up, Z, &adj->X[(size_t)f * 2 * B2 * B2]);
+                face_local(f, Z, Um, &adj->X[((size_t)f * 2 + 1) * B2 * B2]);
             }
         }
         // accumulate serially (cells shared between faces of a chunk)

@@ -186,7 +186,28 @@ void galerkin(const BlockOp& A, const std::vector<double>& P, const std::vector<
     }
 }
 
-void host_apply(const BlockOp& A, const double* x, double* y) {
+// y = A x with a per-cell gather over the cell's faces (parallel, no races).
+struct CellFaces {
+    std::vector<int64_t> ptr, code;   // code = face << 1 | (cell is the minus side)
+};
+static CellFaces cell_faces(const BlockOp& A) {
+    CellFaces C;
+    C.ptr.assign(A.n + 1, 0);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        C.ptr[A.fc[2 * f] + 1]++;
+        C.ptr[A.fc[2 * f + 1] + 1]++;
+    }
+    for (int64_t K = 0; K < A.n; ++K) C.ptr[K + 1] += C.ptr[K];
+    C.code.resize(C.ptr[A.n]);
+    std::vector<int64_t> pos(C.ptr.begin(), C.ptr.end() - 1);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        C.code[pos[A.fc[2 * f]]++] = f << 1;
+        C.code[pos[A.fc[2 * f + 1]]++] = (f << 1) | 1;
+    }
+    return C;
+}
+
+static void apply_with(const BlockOp& A, const CellFaces& C, const double* x, double* y) {
     const int b = A.b, bb = b * b;
 #pragma omp parallel for schedule(static)
     for (int64_t K = 0; K < A.n; ++K) {
@@ -196,22 +217,24 @@ void host_apply(const BlockOp& A, const double* x, double* y) {
             for (int j = 0; j < b; ++j) s += D[i * b + j] * x[K * b + j];
             y[K * b + i] = s;
         }
-    }
-    // face contributions: serial over faces (each touches two cells)
-    for (int64_t f = 0; f < A.nf; ++f) {
-        const int64_t p = A.fc[2 * f], m = A.fc[2 * f + 1];
-        const double* F = &A.fblk[(size_t)f * bb];
-        for (int i = 0; i < b; ++i) {
-            double sp = 0.0, sm = 0.0;
-            for (int j = 0; j < b; ++j) {
-                sp += F[i * b + j] * x[m * b + j];
-                sm += F[j * b + i] * x[p * b + j];
+        for (int64_t e = C.ptr[K]; e < C.ptr[K + 1]; ++e) {
+            const int64_t f = C.code[e] >> 1;
+            const bool minus = (C.code[e] & 1) != 0;
+            const int64_t nb = minus ? A.fc[2 * f] : A.fc[2 * f + 1];
+            const double* F = &A.fblk[(size_t)f * bb];
+            for (int i = 0; i < b; ++i) {
+                double s = 0.0;
+                if (!minus)
+                    for (int j = 0; j < b; ++j) s += F[i * b + j] * x[nb * b + j];
+                else
+                    for (int j = 0; j < b; ++j) s += F[j * b + i] * x[nb * b + j];
+                y[K * b + i] += s;
             }
-            y[p * b + i] += sp;
-            y[m * b + i] += sm;
         }
     }
 }
+
+void host_apply(const BlockOp& A, const double* x, double* y) { apply_with(A, cell_faces(A), x, y); }
 
 // Largest eigenvalue of a symmetric tridiagonal matrix by Sturm-sequence
 // bisection (count of eigenvalues below a shift).
@@ -263,9 +286,10 @@ double lanczos_theta_max(const BlockOp& A, int steps) {
     std::vector<double> al, be;
     double beta = 0.0;
     const int64_t mmax = std::min<int64_t>(steps, n);
+    const CellFaces C = cell_faces(A);
     for (int64_t j = 0; j < mmax; ++j) {
         for (int64_t i = 0; i < n; ++i) tmp[i] = s[i] * v[i];
-        host_apply(A, tmp.data(), w.data());
+        apply_with(A, C, tmp.data(), w.data());
         double a = 0.0;
         for (int64_t i = 0; i < n; ++i) {
             w[i] = s[i] * w[i] - beta * vp[i];

@@ -11,6 +11,8 @@
 // last "x += d" of a sweep is carried as a pending correction and fused into
 // the next kernel that reads x.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -22,6 +24,7 @@
 #include <stdexcept>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "internal.hpp"
 #include "ionic.hpp"
 #include "kernels.hpp"
@@ -55,6 +58,9 @@ static double now_s() {
 }
 
 static inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kWG - 1) / kWG); }
+
+// coarse problems above this size are factorised on the device at set-up
+constexpr int64_t kHostCholeskyMax = 4096;
 
 struct DevLevel {
     int32_t n = 0, nf = 0;
@@ -90,6 +96,16 @@ struct dgmg_solver {
     double* sc = nullptr;
     double* sc_host = nullptr;
     double* mass = nullptr;
+    // adjoint data (optional)
+    bool has_adjoint = false;
+    double *adjS = nullptr, *adjX = nullptr, *adjq = nullptr;
+    int64_t* adj_fc = nullptr;
+    int32_t *adj_nptr = nullptr, *adj_ncode = nullptr;
+    int64_t nf0 = 0;
+    // sensors (optional)
+    int32_t n_sensors = 0;
+    int64_t* scell = nullptr;
+    double* sw = nullptr;
     IonicParams ip{};
     double cU = 0.0;
     std::vector<void*> allocs;
@@ -502,6 +518,43 @@ static std::vector<T> convert(const std::vector<double>& a) {
     return std::vector<T>(a.begin(), a.end());
 }
 
+// Fills the strict upper triangle (column-major view) of an n x n matrix
+// from its lower triangle.
+__global__ void k_symmetrize(int32_t n, double* __restrict__ a) {
+    const int i = blockIdx.x * kWG + threadIdx.x;   // row
+    const int j = blockIdx.y;                       // column
+    if (i < j && j < n) a[(size_t)j * n + i] = a[(size_t)i * n + j];
+}
+
+// Dense SPD inverse on the device (set-up only): Cholesky factorisation and
+// inverse from the factor with rocSOLVER, then symmetrisation.  A is
+// symmetric, so row- and column-major storage coincide.
+static double* device_spd_inverse(dgmg_solver* s, const std::vector<double>& a, int64_t n) {
+    double* d = s->upload(a);
+    int* info = s->dalloc<int>(1);
+    rocblas_handle hnd;
+    if (rocblas_create_handle(&hnd) != rocblas_status_success) fail(DGMG_EHIP, "rocblas_create_handle failed");
+    rocblas_status st1 = rocsolver_dpotrf(hnd, rocblas_fill_lower, (rocblas_int)n, d, (rocblas_int)n, info);
+    int h_info = 0;
+    HIPCHK(hipMemcpy(&h_info, info, sizeof(int), hipMemcpyDeviceToHost));
+    if (st1 != rocblas_status_success) {
+        rocblas_destroy_handle(hnd);
+        fail(DGMG_EHIP, "rocsolver_dpotrf failed");
+    }
+    if (h_info != 0) {
+        rocblas_destroy_handle(hnd);
+        fail(DGMG_ENOTSPD, "coarse operator is not positive definite");
+    }
+    rocblas_status st2 = rocsolver_dpotri(hnd, rocblas_fill_lower, (rocblas_int)n, d, (rocblas_int)n, info);
+    HIPCHK(hipMemcpy(&h_info, info, sizeof(int), hipMemcpyDeviceToHost));
+    rocblas_destroy_handle(hnd);
+    if (st2 != rocblas_status_success || h_info != 0) fail(DGMG_EHIP, "rocsolver_dpotri failed");
+    dim3 g((unsigned)((n + kWG - 1) / kWG), (unsigned)n);
+    k_symmetrize<<<g, kWG>>>((int32_t)n, d);
+    HIPCHK(hipDeviceSynchronize());
+    return d;
+}
+
 static void upload_level(dgmg_solver* s, int l) {
     const BlockOp& A = s->ops[l];
     DevLevel& L = s->lv[l];
@@ -722,7 +775,11 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     double t0 = now_s();
     Faces F = find_faces(*h);
     s->ops.resize(s->L);
-    assemble_fine(*h, F, re, *disc, *ph, cM, s->ops[0], s->mass_h);
+    AdjointBlocks adj;
+    const bool want_adj = mg->adjoint != 0;
+    if (want_adj && ph->model == DGMG_MODEL_BO)
+        fail(DGMG_EUNSUPPORTED, "the adjoint is implemented for the FHN and Aliev-Panfilov models");
+    assemble_fine(*h, F, re, *disc, *ph, cM, s->ops[0], s->mass_h, want_adj ? &adj : nullptr);
     double t1 = now_s();
     s->info.t_assembly = t1 - t0;
     // boxes and prolongations
@@ -755,7 +812,13 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     std::vector<double> Ac;
     dense_from_blocks(s->ops[s->L - 1], Ac);
     s->nc_dofs = s->ops[s->L - 1].n * s->b;
-    cholesky_inverse(Ac, s->nc_dofs);
+    // large coarse problems are factorised on the device (set-up only)
+    const bool coarse_on_device = mg->device_setup && s->nc_dofs > kHostCholeskyMax;
+    if (!coarse_on_device) {
+        if (s->nc_dofs > kHostCholeskyMax)
+            fail(DGMG_EUNSUPPORTED, "coarse problem too large for the host factorisation");
+        cholesky_inverse(Ac, s->nc_dofs);
+    }
     double t6 = now_s();
     s->info.t_coarse = t6 - t5;
 
@@ -782,7 +845,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
 
     if (mg->device_setup) {
         for (int l = 0; l < s->L; ++l) upload_level(s, l);
-        s->Ainv = s->upload(Ac);
+        s->Ainv = coarse_on_device ? device_spd_inverse(s, Ac, s->nc_dofs) : s->upload(Ac);
         const int64_t N = s->N;
         s->r = s->dalloc<double>(N);
         s->z = s->dalloc<double>(N);
@@ -797,6 +860,30 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         HIPCHK(hipMemset(s->sc, 0, 8 * sizeof(double)));
         HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * sizeof(double), hipHostMallocDefault));
         s->mass = s->upload(to_colmajor<double>(s->mass_h, s->b));
+        if (want_adj) {
+            const int b = s->b, R = 2 * b;
+            const BlockOp& A = s->ops[0];
+            std::vector<double> Sc(adj.S.size());
+            for (int64_t K = 0; K < A.n; ++K)
+                for (int i = 0; i < b; ++i)
+                    for (int j = 0; j < b; ++j)
+                        Sc[((size_t)K * b + j) * b + i] = adj.S[((size_t)K * b + i) * b + j];
+            std::vector<double> Xc(adj.X.size());
+            for (size_t blk = 0; blk < adj.X.size() / ((size_t)R * R); ++blk)
+                for (int I = 0; I < R; ++I)
+                    for (int J = 0; J < R; ++J)
+                        Xc[(blk * R + J) * R + I] = adj.X[(blk * R + I) * R + J];
+            s->adjS = s->upload(Sc);
+            s->adjX = s->upload(Xc);
+            s->adj_fc = s->upload(A.fc);
+            std::vector<int32_t> ptr, cell, code;
+            build_nbr(A, ptr, cell, code);
+            s->adj_nptr = s->upload(ptr);
+            s->adj_ncode = s->upload(code);
+            s->nf0 = A.nf;
+            s->adjq = s->dalloc<double>(2 * (size_t)A.nf + 2);
+            s->has_adjoint = true;
+        }
         HIPCHK(hipDeviceSynchronize());
         s->on_device = true;
     }
@@ -929,6 +1016,73 @@ int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms) {
     s->prof_kind = -1;
     s->prof_level = -1;
     s->prof_used = 0;
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_set_sensors(dgmg_solver* s, int32_t n, const int64_t* cells, const double* ref) {
+    API_BEGIN
+    need_device(s);
+    if (n < 0 || (n > 0 && (!cells || !ref))) fail(DGMG_EINVAL, "bad sensor arrays");
+    RefElement re;
+    re.init(s->dim, s->p);
+    std::vector<int64_t> c(cells, cells + n);
+    std::vector<double> w((size_t)n * s->b);
+    for (int k = 0; k < n; ++k) {
+        if (c[k] < 0 || c[k] >= s->lv[0].n) fail(DGMG_EINVAL, "sensor cell out of range");
+        tensor_eval(re, ref + (size_t)k * s->dim, &w[(size_t)k * s->b], nullptr);
+    }
+    s->scell = s->upload(c);
+    s->sw = s->upload(w);
+    s->n_sensors = n;
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_sensor_misfit(dgmg_solver* s, const double* U, const double* target, double* Ubar,
+                       double* loss, void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (!U || !target || !loss) fail(DGMG_EINVAL, "null argument");
+    DISPATCH_B(s->b, k_sensor_misfit<BV><<<1, 256, 0, (hipStream_t)stream>>>(s->n_sensors, s->scell, s->sw, U,
+                                                                              target, Ubar, loss));
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_adjoint_step(dgmg_solver* s, const double* U, const double* Uprev, const double* W,
+                      const double* Wprev, const double* lambda, const double* Wbar_in, double* Ubar,
+                      double* Uprevbar, double* Wbar, double* Wprevbar, void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (!s->has_adjoint) fail(DGMG_EINVAL, "solver was set up without adjoint data");
+    if (!U || !Uprev || !W || !Wprev || !lambda || !Wbar_in || !Ubar || !Uprevbar || !Wbar || !Wprevbar)
+        fail(DGMG_EINVAL, "null argument");
+    const int cells_per = 256 / s->b;
+    const unsigned nblk = (unsigned)((s->lv[0].n + cells_per - 1) / cells_per);
+    DISPATCH_B(s->b, k_adjoint_step<BV><<<nblk, cells_per * BV, 0, (hipStream_t)stream>>>(
+                         s->lv[0].n, s->ip, s->cU, s->mass, U, Uprev, W, Wprev, lambda, Wbar_in, Ubar,
+                         Uprevbar, Wbar, Wprevbar));
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_grad_accumulate(dgmg_solver* s, const double* lambda, const double* U, double* grad,
+                         void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (!s->has_adjoint) fail(DGMG_EINVAL, "solver was set up without adjoint data");
+    if (!lambda || !U || !grad) fail(DGMG_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int b = s->b;
+    const int fpw = 256 / (2 * b), cpw = 256 / b;
+    DISPATCH_B(b, k_grad_faces<BV><<<(unsigned)((s->nf0 + fpw - 1) / fpw), 256, 0, st>>>(
+                      (int32_t)s->nf0, s->adj_fc, s->adjX, lambda, U, s->adjq));
+    DISPATCH_B(b, k_grad_cells<BV><<<(unsigned)((s->lv[0].n + cpw - 1) / cpw), 256, 0, st>>>(
+                      s->lv[0].n, s->adjS, s->adj_nptr, s->adj_ncode, s->adjq, lambda, U, grad));
+    HIPCHK(hipGetLastError());
     return DGMG_OK;
     API_END
 }

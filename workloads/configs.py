@@ -143,7 +143,7 @@ def make_problem(name, n=None, steps=None, **overrides):
                 stim_tend=stim_tend, model_id=MODEL_IDS[cfg["model"]],
                 params=np.asarray(cfg["params"], dtype=np.float64),
                 node_xyz=nodes)
-    if "sensors" in cfg:
+    if cfg.get("sensors"):
         ns, seed = cfg["sensors"]
         rng = np.random.default_rng(seed)
         prob["sensor_cell"] = rng.integers(0, nc, size=ns).astype(np.int64)
