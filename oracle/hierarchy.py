@@ -15,8 +15,13 @@ Readings:
   level >= 1 this is the exact embedding; on jittered cells it is nodal
   interpolation.
 
+* on unstructured meshes an STR (sort-tile-recursive) bulk-loaded R-tree of
+  fanout 8 stands in for the R*-tree; the agglomerates of level l are the
+  leaves below the tree nodes l levels above the leaves.
+
 Pins (tests/test_oracle_mg.py): partition is a disjoint cover and nests,
-P 1_c = 1_f, P reproduces coarse polynomials at fine nodes.
+P 1_c = 1_f, P reproduces coarse polynomials at fine nodes; STR groups are
+full (all but a few per strip hold exactly M items) and spatially compact.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -120,11 +125,16 @@ def prolongation(fine_pts, parent, lo, hi, p):
 
 
 def build_hierarchy(prob):
-    """Parents, boxes and prolongations of the grid-grouped hierarchy of a
-    problem dict.  Returns dict(parents, lo, hi, P, n) with P[l] mapping
+    """Parents, boxes and prolongations of the agglomerated hierarchy of a
+    problem dict (grid grouping, or an STR-packed R-tree when the problem
+    asks for one).  Returns dict(parents, lo, hi, P, n) with P[l] mapping
     level l+1 to level l."""
     xyz, cells, p = prob["xyz"], prob["cell_vtx"], prob["p"]
-    parents = grid_partitions(xyz, cells, prob["n"], prob["group"])
+    if prob.get("agglo", ("grid",))[0] == "rtree_str":
+        _, fanout, n_levels = prob["agglo"]
+        parents = str_partitions(xyz, cells, fanout, n_levels)
+    else:
+        parents = grid_partitions(xyz, cells, prob["n"], prob["group"])
     ids = members_level0(parents, cells.shape[0])
     ns = [cells.shape[0]] + [int(i.max()) + 1 for i in ids[1:]]
     los, his = [None], [None]
@@ -139,3 +149,56 @@ def build_hierarchy(prob):
             pts = box_nodes(los[l], his[l], p)
         P.append(prolongation(pts, parents[l], los[l + 1], his[l + 1], p))
     return dict(parents=parents, lo=los, hi=his, P=P, n=ns, ids=ids)
+
+
+def str_pack(centers, M):
+    """Sort-tile-recursive packing of items (centres [N, d]) into groups of
+    at most M: sort by x into S^(d-1)*M-item slabs (S = smallest integer with
+    S^d >= ceil(N/M)), each slab by y into S*M-item strips (3D), each strip by
+    z, then consecutive runs of M.  Ties are broken by item id.  Returns the
+    group id of every item (groups numbered in packing order)."""
+    N, d = centers.shape
+    P = -(-N // M)
+    S = 1
+    while S ** d < P:
+        S += 1
+    ids = np.arange(N)
+    order = np.lexsort((ids, centers[:, 0]))
+    parent = np.empty(N, dtype=np.int64)
+    g = 0
+    slab = S ** (d - 1) * M
+    for a in range(0, N, slab):
+        sl = order[a:a + slab]
+        sl = sl[np.lexsort((sl, centers[sl, 1]))]
+        runs = [sl]
+        if d == 3:
+            strip = S * M
+            runs = []
+            for b in range(0, len(sl), strip):
+                st = sl[b:b + strip]
+                runs.append(st[np.lexsort((st, centers[st, 2]))])
+        for run in runs:
+            for c in range(0, len(run), M):
+                parent[run[c:c + M]] = g
+                g += 1
+    return parent
+
+
+def str_partitions(xyz, cells, fanout, n_levels):
+    """Nested agglomerates from an STR-packed R-tree: level l+1 packs the
+    minimum bounding boxes of level l (leaves: the cells' boxes), and every
+    tree node gathers the leaves below it (Algorithms 1 and 2)."""
+    lo = xyz[cells].min(axis=1)
+    hi = xyz[cells].max(axis=1)
+    parents = []
+    for _ in range(n_levels - 1):
+        centers = 0.5 * (lo + hi)
+        par = str_pack(centers, fanout)
+        n_new = int(par.max()) + 1
+        nlo = np.full((n_new, lo.shape[1]), np.inf)
+        nhi = np.full((n_new, lo.shape[1]), -np.inf)
+        np.minimum.at(nlo, par, lo)
+        np.maximum.at(nhi, par, hi)
+        parents.append(par)
+        lo, hi = nlo, nhi
+    return parents

@@ -617,6 +617,55 @@ static void upload_level(dgmg_solver* s, int l) {
         return DGMG_EINVAL;                                              \
     }
 
+// Sort-tile-recursive packing of items with boxes (lo, hi) into groups of at
+// most M: with P = ceil(N/M) and S the smallest integer with S^d >= P, sort
+// by centre x into slabs of S^(d-1) M items, each slab by y into strips of
+// S M items (3D), each strip by z, then cut consecutive runs of M.  Ties are
+// broken by item id.  Returns the number of groups; par receives each
+// item's group (numbered in packing order).
+static int64_t str_pack(const std::vector<double>& lo, const std::vector<double>& hi, int d, int M,
+                        std::vector<int64_t>& par) {
+    const int64_t N = (int64_t)(lo.size() / d);
+    const int64_t P = (N + M - 1) / M;
+    int64_t S = 1;
+    auto pw = [&](int64_t v) { int64_t r = 1; for (int k = 0; k < d; ++k) r *= v; return r; };
+    while (pw(S) < P) ++S;
+    auto cen = [&](int64_t i, int a) { return 0.5 * (lo[(size_t)i * d + a] + hi[(size_t)i * d + a]); };
+    auto by = [&](int a) {
+        return [&, a](int64_t x, int64_t y) {
+            const double cx = cen(x, a), cy = cen(y, a);
+            return cx < cy || (cx == cy && x < y);
+        };
+    };
+    std::vector<int64_t> order(N);
+    for (int64_t i = 0; i < N; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), by(0));
+    par.assign(N, -1);
+    int64_t g = 0;
+    const int64_t slab = pw(S) / S * M;
+    for (int64_t a0 = 0; a0 < N; a0 += slab) {
+        const int64_t a1 = std::min(N, a0 + slab);
+        std::sort(order.begin() + a0, order.begin() + a1, by(1));
+        auto cut = [&](int64_t r0, int64_t r1) {
+            for (int64_t c = r0; c < r1; c += M) {
+                for (int64_t k = c; k < std::min(r1, c + M); ++k) par[order[k]] = g;
+                ++g;
+            }
+        };
+        if (d == 3) {
+            const int64_t strip = S * M;
+            for (int64_t b0 = a0; b0 < a1; b0 += strip) {
+                const int64_t b1 = std::min(a1, b0 + strip);
+                std::sort(order.begin() + b0, order.begin() + b1, by(2));
+                cut(b0, b1);
+            }
+        } else {
+            cut(a0, a1);
+        }
+    }
+    return g;
+}
+
 extern "C" {
 
 const char* dgmg_last_error(void) { return g_last_error.c_str(); }
@@ -687,6 +736,37 @@ int dgmg_build_hierarchy(const dgmg_mesh* m, const dgmg_agglo_opts* o, dgmg_hier
             h->parent.push_back(par);
             h->n_ent.push_back(nbins);
             prev_id = id;
+        }
+    } else if (o->method == DGMG_AGGLO_RTREE_STR) {
+        // STR bulk-loaded R-tree: level l+1 packs the bounding boxes of level l
+        // (Algorithms 1 and 2 on a sort-tile-recursive tree)
+        const int M = o->rtree_fanout;
+        if (M < 2) fail(DGMG_EINVAL, "rtree_fanout must be >= 2");
+        std::vector<double> lo((size_t)h->n_cells * d), hi((size_t)h->n_cells * d);
+        for (int64_t c = 0; c < h->n_cells; ++c)
+            for (int a = 0; a < d; ++a) {
+                double mn = INFINITY, mx = -INFINITY;
+                for (int k = 0; k < nc; ++k) {
+                    const double x = h->xyz[(size_t)h->cells[(size_t)c * nc + k] * d + a];
+                    mn = std::min(mn, x);
+                    mx = std::max(mx, x);
+                }
+                lo[(size_t)c * d + a] = mn;
+                hi[(size_t)c * d + a] = mx;
+            }
+        for (int l = 1; l < o->n_levels; ++l) {
+            std::vector<int64_t> par;
+            const int64_t ngrp = str_pack(lo, hi, d, M, par);
+            std::vector<double> nlo((size_t)ngrp * d, INFINITY), nhi((size_t)ngrp * d, -INFINITY);
+            for (size_t e = 0; e < par.size(); ++e)
+                for (int a = 0; a < d; ++a) {
+                    nlo[(size_t)par[e] * d + a] = std::min(nlo[(size_t)par[e] * d + a], lo[e * d + a]);
+                    nhi[(size_t)par[e] * d + a] = std::max(nhi[(size_t)par[e] * d + a], hi[e * d + a]);
+                }
+            h->parent.push_back(par);
+            h->n_ent.push_back(ngrp);
+            lo.swap(nlo);
+            hi.swap(nhi);
         }
     } else if (o->method == DGMG_AGGLO_USER) {
         if (!o->user_parents) fail(DGMG_EINVAL, "user_parents is null");

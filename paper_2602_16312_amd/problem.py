@@ -19,9 +19,14 @@ def grid_bins(n, dim, factors):
 def build(prob, precision="fp64", lam_override=None, cell_scale=None,
           device_setup=True, bdf=2, **mg):
     """(hierarchy, solver) for a problem mapping."""
-    levels = 1 + len(prob["group"])
-    h = api.build_hierarchy(prob["xyz"], prob["cell_vtx"], levels, method="grid",
-                            grid_bins=grid_bins(prob["n"], prob["dim"], prob["group"]))
+    agglo = prob.get("agglo", ("grid",))
+    if agglo[0] == "rtree_str":
+        h = api.build_hierarchy(prob["xyz"], prob["cell_vtx"], agglo[2], method="rtree_str",
+                                fanout=agglo[1])
+    else:
+        levels = 1 + len(prob["group"])
+        h = api.build_hierarchy(prob["xyz"], prob["cell_vtx"], levels, method="grid",
+                                grid_bins=grid_bins(prob["n"], prob["dim"], prob["group"]))
     s = api.setup_levels(h, prob["p"], prob["D_cell"], prob["chi"], prob["Cm"],
                          prob["dt"], prob["model"], np.asarray(prob["params"], float),
                          penalty=prob["penalty"], bdf=bdf, cell_scale=cell_scale,

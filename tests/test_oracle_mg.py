@@ -168,3 +168,31 @@ def test_pcg_against_dense_and_special_cases():
     # warm start equal to the solution: zero iterations
     x2, st2 = pcg(A0, A0 @ xd, xd, mg, 1e-10)
     assert st2["its"] <= 1
+
+
+def test_str_packing_groups_and_nesting():
+    """STR packing: a disjoint cover, groups of at most M with all but the
+    tail of each strip full, nested levels, spatially compact groups."""
+    from workloads.meshes import shell_mesh
+    from oracle.hierarchy import str_partitions, str_pack
+    xyz, cells, _ = shell_mesh(0.08)
+    pars = str_partitions(xyz, cells, 8, 4)
+    n = cells.shape[0]
+    for par in pars:
+        sizes = np.bincount(par)
+        assert sizes.min() >= 1 and sizes.max() <= 8
+        assert np.array_equal(np.unique(par), np.arange(len(sizes)))
+        assert (sizes == 8).mean() > 0.9
+        n = len(sizes)
+    # compactness: group extent comparable to the fanout's cube root x h
+    cen = xyz[cells].mean(axis=1)
+    ext = np.zeros((len(np.unique(pars[0])), 3))
+    for k in range(3):
+        mx = np.full(ext.shape[0], -np.inf); mn = np.full(ext.shape[0], np.inf)
+        np.maximum.at(mx, pars[0], cen[:, k]); np.minimum.at(mn, pars[0], cen[:, k])
+        ext[:, k] = mx - mn
+    assert np.median(ext.max(axis=1)) <= 3 * 0.08
+    # 2D packing of a regular grid gives M-runs along y inside x-slabs
+    c2 = np.stack(np.meshgrid(np.arange(8.0), np.arange(8.0), indexing="ij"), -1).reshape(-1, 2)
+    par = str_pack(c2, 4)
+    assert np.bincount(par).tolist() == [4] * 16

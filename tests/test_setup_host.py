@@ -78,3 +78,21 @@ def test_operator_complexity_and_counts():
     assert info["n_dofs"] == 4096 * 9
     # 4x4 grouping on a grid: each coarse level has ~1/16 of the blocks
     assert 1.0 < info["op_complexity"] < 1.08
+
+
+def test_str_hierarchy_and_shell_levels_match_oracle():
+    """STR R-tree agglomeration (library C++ vs oracle numpy) is identical on
+    the jittered shell, and the Galerkin levels built on it agree."""
+    pr = make_problem("c4", h=0.09)
+    h, s = problem.build(pr, device_setup=False)
+    oh = oracle_hierarchy(pr)
+    for l in range(len(oh["parents"])):
+        assert np.array_equal(h.parents(l), oh["parents"][l])
+    A0, M, A, cM = system_matrix(pr)
+    mg = VCycle(A0, oh["P"])
+    info = s.info()
+    assert info["n_cells"] == oh["n"]
+    for l in range(info["n_levels"]):
+        Al = dense_level(s.export_level(l))
+        assert abs(Al - mg.A[l]).max() <= 1e-12 * abs(mg.A[l]).max(), l
+    assert 1.1 < info["op_complexity"] < 1.4

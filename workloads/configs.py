@@ -13,7 +13,8 @@ Ionic parameter vectors (fixed order, shared by every consumer):
 """
 import numpy as np
 
-from .meshes import structured_mesh, cell_centroids, dof_nodes
+from .meshes import (structured_mesh, cell_centroids, dof_nodes, shell_mesh,
+                     shell_transmural)
 
 BO_PARAM_NAMES = [
     "tau_o1", "tau_o2", "tau_so1", "tau_so2", "tau_si", "tau_fi",
@@ -61,6 +62,16 @@ CONFIGS = {
                params=[BO_EPI[k] for k in BO_PARAM_NAMES],
                penalty=("paper",), ic="rest", stim=("corner_block", 0.125, 0.3, 3.0),
                tol=1e-8),
+    # ventricle-like truncated ellipsoidal shell (~1.0M voxel hexes, interior
+    # nodes jittered +-0.15 h), Q1, transmural fibres, Bueno-Orovio (ms),
+    # five STR R-tree levels of fanout 8, eight stimulus sites (apex + 7
+    # endocardial) for the multi-right-hand-side runs.
+    "c4": dict(kind="shell", dim=3, h=0.0147, p=1, jitter=0.15, seed=2603,
+               agglo=("rtree_str", 8, 5), group=[],
+               sigma=("fibre_shell", 1.2e-3, 2.5e-4), chi=1.0, Cm=1.0, dt=5e-2,
+               steps=20, model="bo", params=[BO_EPI[k] for k in BO_PARAM_NAMES],
+               penalty=("paper", 2.0), ic="rest",
+               stim=("sites", 0.15, 0.3, 3.0, 2604, 8), tol=1e-8),
     # adjoint problem: mesh and physics of c2, 50 steps
     "c5": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
                sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=50,
@@ -68,6 +79,41 @@ CONFIGS = {
                penalty=("paper", 2.0), ic="corner_disc", stim=None, tol=1e-8,
                sensors=(64, 2605), target_seed=2606),
 }
+
+
+SHELL_OUTER = (1.0, 1.0, 2.5)
+SHELL_INNER = (0.7, 0.7, 2.0)
+
+
+def _shell_fibres(cen, sl, st):
+    """D = st I + (sl - st) f f^T with f rotating from -60 deg (outer) to
+    +60 deg (inner) with the transmural coordinate, in the plane spanned by
+    the circumferential direction and the meridian tangent."""
+    t = shell_transmural(cen, SHELL_OUTER, SHELL_INNER)
+    th = np.deg2rad(-60.0 + 120.0 * t)
+    r = np.hypot(cen[:, 0], cen[:, 1])
+    ec = np.stack([-cen[:, 1], cen[:, 0], np.zeros(len(cen))], axis=1)
+    ec = np.where(r[:, None] > 1e-12, ec / np.maximum(r, 1e-300)[:, None], np.array([1.0, 0.0, 0.0]))
+    a = (1 - t)[:, None] * np.asarray(SHELL_OUTER) + t[:, None] * np.asarray(SHELL_INNER)
+    nv = cen / a ** 2
+    nv /= np.linalg.norm(nv, axis=1)[:, None]
+    el = np.cross(nv, ec)
+    el /= np.maximum(np.linalg.norm(el, axis=1), 1e-300)[:, None]
+    f = np.cos(th)[:, None] * ec + np.sin(th)[:, None] * el
+    D = st * np.eye(3)[None] + (sl - st) * f[:, :, None] * f[:, None, :]
+    return np.stack([D[:, 0, 0], D[:, 0, 1], D[:, 0, 2], D[:, 1, 1], D[:, 1, 2], D[:, 2, 2]], axis=1)
+
+
+def _stim_sites(nsites, seed):
+    """Outer apex plus seeded endocardial points (inner ellipsoid, -1.8 < z < -0.3)."""
+    rng = np.random.default_rng(seed)
+    sites = [np.array([0.0, 0.0, -SHELL_OUTER[2]])]
+    for _ in range(nsites - 1):
+        z = rng.uniform(-1.8, -0.3)
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        rr = np.sqrt(max(0.0, 1.0 - (z / SHELL_INNER[2]) ** 2))
+        sites.append(np.array([SHELL_INNER[0] * rr * np.cos(ph), SHELL_INNER[1] * rr * np.sin(ph), z]))
+    return np.array(sites)
 
 
 def _conductivity(spec, centroids, dim):
@@ -94,11 +140,14 @@ def _conductivity(spec, centroids, dim):
 def make_problem(name, n=None, steps=None, **overrides):
     """Build the input arrays of a named problem.
 
-    ``n`` overrides the number of cells per axis (small variants for tests);
-    other keyword overrides replace config entries verbatim.
+    ``n`` overrides the number of cells per axis (small variants for tests;
+    for the shell, ``h`` overrides the voxel size); other keyword overrides
+    replace config entries verbatim.
     """
     cfg = dict(CONFIGS[name])
     cfg.update(overrides)
+    if cfg.get("kind") == "shell":
+        return _make_shell(name, cfg, steps)
     if n is not None:
         if cfg["penalty"][0] == "fixed":
             # keep "10 p^2 / h" meaningful when the mesh is resized
@@ -161,3 +210,28 @@ def iapp_nodal(prob, t):
         m = np.repeat(prob["stim_mask"], prob["b"])
         out[m] = prob["stim_amp"]
     return out
+
+
+def _make_shell(name, cfg, steps):
+    if steps is not None:
+        cfg["steps"] = steps
+    xyz, cells, surf = shell_mesh(cfg["h"], SHELL_OUTER, SHELL_INNER, 0.0, cfg["jitter"], cfg["seed"])
+    cen = cell_centroids(xyz, cells)
+    nc = cells.shape[0]
+    p = cfg["p"]
+    b = (p + 1) ** 3
+    N = nc * b
+    _, rad, amp, tend, sseed, nsites = cfg["stim"]
+    sites = _stim_sites(nsites, sseed)
+    masks = np.stack([np.linalg.norm(cen - s_, axis=1) < rad for s_ in sites])
+    W0 = np.zeros((3, N))
+    W0[0] = 1.0
+    W0[1] = 1.0
+    prob = dict(cfg)
+    prob.update(name=name, xyz=xyz, cell_vtx=cells, n_cells=nc, b=b, N=N, S=3,
+                D_cell=_shell_fibres(cen, cfg["sigma"][1], cfg["sigma"][2]),
+                U0=np.zeros(N), W0=W0, stim_mask=masks[0], stim_masks=masks,
+                stim_sites=sites, stim_amp=amp, stim_tend=tend,
+                model_id=MODEL_IDS[cfg["model"]],
+                params=np.asarray(cfg["params"], dtype=np.float64))
+    return prob
