@@ -133,7 +133,11 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * device_setup = 0 stops after the host setup (inspection on machines
  * without a GPU; solve calls then fail with DGMG_EINVAL).  adjoint = 1 also
  * stores the conductivity derivatives dA/ds_K (cell stiffness and per-side
- * face matrices, FP64) needed by dgmg_grad_accumulate (FHN and AP models). */
+ * face matrices, FP64) needed by dgmg_grad_accumulate (FHN and AP models).
+ * max_rhs (0 or 1: single right-hand side; DGMG_MULTI_RHS: also size every
+ * work vector for that many columns, enabling the *_multi calls).  mfma = 1
+ * runs the FP32 Chebyshev step of 8-column solves with 8x8 blocks (3D Q1)
+ * on the matrix cores (v_mfma_f32_4x4x1f32); 0 keeps it on the vector ALUs. */
 typedef struct {
     int32_t cheb_degree;
     int32_t cheb_sweeps;
@@ -144,7 +148,12 @@ typedef struct {
     int32_t precision;
     int32_t device_setup;
     int32_t adjoint;
+    int32_t max_rhs;
+    int32_t mfma;
 } dgmg_mg_opts;
+
+/* Number of columns of the multi-right-hand-side calls. */
+enum { DGMG_MULTI_RHS = 8 };
 
 /* Assembles A_0 = 3 chi C_m/(2 dt) M + A (eq. fully_discrete; bdf = 1 uses
  * chi C_m/dt), the prolongations, the Galerkin operators A_{l+1} = P^T A_l P
@@ -219,6 +228,25 @@ int dgmg_time_step(dgmg_solver* s, dgmg_state* state, double t_next,
                    const double* iapp, const dgmg_pcg_opts* opts,
                    dgmg_pcg_stats* stats, void* stream);
 
+/* Multi-right-hand-side PCG: nrhs (= DGMG_MULTI_RHS) independent systems
+ * A_0 x_c = b_c sharing one operator and one V-cycle per iteration, each
+ * column with its own CG scalars alpha_c, beta_c and its own stopping test
+ * (a converged column is frozen while the others iterate).  device b, x:
+ * N x nrhs, column-minor (entry (DoF t, column c) at t*nrhs + c).  host stats:
+ * nrhs entries.  Requires max_rhs >= nrhs at set-up.  Returns DGMG_OK when
+ * every column converged, DGMG_NOT_CONVERGED otherwise; errors as for
+ * dgmg_pcg_solve (on any active column). */
+int dgmg_pcg_solve_multi(dgmg_solver* s, int32_t nrhs, const double* b, double* x,
+                         const dgmg_pcg_opts* opts, dgmg_pcg_stats* stats, void* stream);
+
+/* dgmg_time_step for nrhs independent simulations sharing the mesh, the
+ * conductivity and the solver (e.g. different stimulus sites): every state
+ * buffer and iapp hold nrhs columns, column-minor (U: N x nrhs, W: S x N x
+ * nrhs), stats nrhs entries. */
+int dgmg_time_step_multi(dgmg_solver* s, int32_t nrhs, dgmg_state* state, double t_next,
+                         const double* iapp, const dgmg_pcg_opts* opts,
+                         dgmg_pcg_stats* stats, void* stream);
+
 /* ---- operator-level entry points (parity tests, adjoint driver) ---- */
 
 /* y = A_level x.  prec selects the stored FP64 or FP32 copy of the level
@@ -227,6 +255,12 @@ int dgmg_apply(dgmg_solver* s, int32_t level, int32_t prec, const double* x,
                double* y, void* stream);
 /* z = B r, one V-cycle in the solver's precision mode; device r, z: N. */
 int dgmg_vcycle(dgmg_solver* s, const double* r, double* z, void* stream);
+/* dgmg_apply and dgmg_vcycle on nrhs (= DGMG_MULTI_RHS) column-minor
+ * columns (N_level x nrhs); the V-cycle is applied to every column. */
+int dgmg_apply_multi(dgmg_solver* s, int32_t level, int32_t prec, int32_t nrhs,
+                     const double* x, double* y, void* stream);
+int dgmg_vcycle_multi(dgmg_solver* s, int32_t nrhs, const double* r, double* z,
+                      void* stream);
 /* b = M f per cell (the ICI load vector); device f, b: N. */
 int dgmg_mass_apply(dgmg_solver* s, const double* f, double* b, void* stream);
 
@@ -274,11 +308,11 @@ int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms);
 
 /* Average duration (ms, HIP events on `stream`) of `reps` back-to-back
  * launches of one smoother kernel (kind 0: fused Chebyshev step, 1: fused
- * residual) on `level` < n_levels - 1, in the solver's V-cycle precision.
- * Uses the level's internal work vectors only (their contents are
- * overwritten); caller data are untouched. */
-int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t reps, void* stream,
-                      double* avg_ms);
+ * residual) on `level` < n_levels - 1, in the solver's V-cycle precision,
+ * on nrhs (1 or DGMG_MULTI_RHS) columns.  Uses the level's internal work
+ * vectors only (their contents are overwritten); caller data are untouched. */
+int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t nrhs, int32_t reps,
+                      void* stream, double* avg_ms);
 
 const char* dgmg_last_error(void);
 

@@ -6,6 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgmg.so")
 
 MAX_LEVELS = 8
+MULTI_RHS = 8          # DGMG_MULTI_RHS
 OK, NOT_CONVERGED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOTSPD", -3: "ENAN", -4: "EHIP", -5: "ENOMEM",
           -6: "EUNSUPPORTED"}
@@ -15,6 +16,7 @@ EXPORTS = [
     "dgmg_build_hierarchy", "dgmg_hierarchy_info", "dgmg_hierarchy_parents",
     "dgmg_destroy_hierarchy", "dgmg_setup_levels", "dgmg_destroy_solver",
     "dgmg_get_info", "dgmg_pcg_solve", "dgmg_ionic_step", "dgmg_time_step",
+    "dgmg_pcg_solve_multi", "dgmg_time_step_multi", "dgmg_apply_multi", "dgmg_vcycle_multi",
     "dgmg_apply", "dgmg_vcycle", "dgmg_mass_apply", "dgmg_export_level",
     "dgmg_profile_begin", "dgmg_profile_end", "dgmg_kernel_bench", "dgmg_last_error",
     "dgmg_set_sensors", "dgmg_sensor_misfit", "dgmg_adjoint_step", "dgmg_grad_accumulate",
@@ -51,7 +53,8 @@ class MGOpts(C.Structure):
                 ("lanczos_steps", C.c_int32), ("lam_safety", C.c_double),
                 ("smooth_range", C.c_double), ("lam_override", dp),
                 ("precision", C.c_int32), ("device_setup", C.c_int32),
-                ("adjoint", C.c_int32)]
+                ("adjoint", C.c_int32), ("max_rhs", C.c_int32),
+                ("mfma", C.c_int32)]
 
 
 class SolverInfo(C.Structure):
@@ -117,7 +120,13 @@ def lib():
         L.dgmg_export_level.argtypes = [vp, C.c_int32, dp, i64p, dp, dp, i64p]
         L.dgmg_profile_begin.argtypes = [vp, C.c_int32, C.c_int32]
         L.dgmg_profile_end.argtypes = [vp, i64p, dp]
-        L.dgmg_kernel_bench.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, dp]
+        L.dgmg_kernel_bench.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, dp]
+        L.dgmg_pcg_solve_multi.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(PCGOpts),
+                                           C.POINTER(PCGStats), vp]
+        L.dgmg_time_step_multi.argtypes = [vp, C.c_int32, C.POINTER(State), C.c_double, vp,
+                                           C.POINTER(PCGOpts), C.POINTER(PCGStats), vp]
+        L.dgmg_apply_multi.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+        L.dgmg_vcycle_multi.argtypes = [vp, C.c_int32, vp, vp, vp]
         L.dgmg_set_sensors.argtypes = [vp, C.c_int32, i64p, dp]
         L.dgmg_sensor_misfit.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dgmg_adjoint_step.argtypes = [vp] * 12

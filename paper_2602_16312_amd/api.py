@@ -147,7 +147,8 @@ class Solver:
 def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",),
                  bdf=2, cell_scale=None, precision="fp64", cheb_degree=3,
                  cheb_sweeps=3, lanczos_steps=20, lam_safety=1.2,
-                 smooth_range=20.0, lam_override=None, device_setup=True, adjoint=False):
+                 smooth_range=20.0, lam_override=None, device_setup=True, adjoint=False,
+                 max_rhs=1, mfma=False):
     """dgmg_setup_levels: assembly, Galerkin hierarchy, smoother, coarse factor."""
     d = F.Disc(p, 0 if penalty[0] == "paper" else 1,
                float(penalty[1]) if len(penalty) > 1 else 0.0)
@@ -164,7 +165,8 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
         lam, lo = _dptr(np.asarray(lam_override, dtype=np.float64).ravel())
         keep.append(lam)
     mg = F.MGOpts(cheb_degree, cheb_sweeps, lanczos_steps, lam_safety, smooth_range,
-                  lo, PRECISIONS[precision], 1 if device_setup else 0, 1 if adjoint else 0)
+                  lo, PRECISIONS[precision], 1 if device_setup else 0, 1 if adjoint else 0,
+                  int(max_rhs), 1 if mfma else 0)
     s = C.c_void_p()
     F.check(F.lib().dgmg_setup_levels(hier.handle, C.byref(d), C.byref(ph), C.byref(mg),
                                       C.byref(s)))
@@ -188,6 +190,17 @@ def pcg_solve(solver, b, x, tol=1e-8, tol_mode="rel_r0", max_it=500, flexible=Fa
     rc = F.check(F.lib().dgmg_pcg_solve(solver.handle, _dev(b), _dev(x), C.byref(o),
                                         C.byref(st), _stream(stream)))
     return _stats(st, rc)
+
+
+def pcg_solve_multi(solver, b, x, tol=1e-8, tol_mode="rel_r0", max_it=500, flexible=False,
+                    stream=None):
+    """dgmg_pcg_solve_multi: MULTI_RHS independent solves; b, x are [N, MULTI_RHS]
+    column-minor device tensors.  Returns one stats dict per column."""
+    st = (F.PCGStats * F.MULTI_RHS)()
+    o = _pcg_opts(tol, tol_mode, max_it, flexible)
+    rc = F.check(F.lib().dgmg_pcg_solve_multi(solver.handle, F.MULTI_RHS, _dev(b), _dev(x),
+                                              C.byref(o), st, _stream(stream)))
+    return [_stats(st[c], rc) for c in range(F.MULTI_RHS)]
 
 
 def ionic_step(solver, U, Uprev, W, Wprev, Wnext, g, stream=None):
@@ -228,6 +241,33 @@ def time_step(solver, state, t_next, iapp=None, tol=1e-8, tol_mode="rel_r0",
     return _stats(st, rc)
 
 
+def time_step_multi(solver, state, t_next, iapp=None, tol=1e-8, tol_mode="rel_r0",
+                    max_it=500, flexible=False, stream=None):
+    """dgmg_time_step_multi: MULTI_RHS independent simulations; every state
+    tensor holds MULTI_RHS columns (column-minor)."""
+    for t in (state.U, state.Uprev, state.W, state.Wprev, state.g):
+        _dev(t)
+    s = state._struct()
+    st = (F.PCGStats * F.MULTI_RHS)()
+    o = _pcg_opts(tol, tol_mode, max_it, flexible)
+    rc = F.check(F.lib().dgmg_time_step_multi(solver.handle, F.MULTI_RHS, C.byref(s), t_next,
+                                              _dev(iapp), C.byref(o), st, _stream(stream)))
+    state._adopt(s)
+    return [_stats(st[c], rc) for c in range(F.MULTI_RHS)]
+
+
+def apply_multi(solver, level, x, y, precision="fp64", stream=None):
+    """dgmg_apply_multi: Y = A_level X on MULTI_RHS column-minor columns."""
+    F.check(F.lib().dgmg_apply_multi(solver.handle, level, PRECISIONS[precision], F.MULTI_RHS,
+                                     _dev(x), _dev(y), _stream(stream)))
+
+
+def vcycle_multi(solver, r, z, stream=None):
+    """dgmg_vcycle_multi: one V-cycle on each of MULTI_RHS columns."""
+    F.check(F.lib().dgmg_vcycle_multi(solver.handle, F.MULTI_RHS, _dev(r), _dev(z),
+                                      _stream(stream)))
+
+
 def apply(solver, level, x, y, precision="fp64", stream=None):
     """dgmg_apply: y = A_level x with the FP64 or FP32 level copy."""
     F.check(F.lib().dgmg_apply(solver.handle, level, PRECISIONS[precision], _dev(x),
@@ -261,10 +301,10 @@ def profile_end(solver):
     return n.value, ms.value
 
 
-def kernel_bench(solver, kind="cheb_step", level=0, reps=200, stream=None):
+def kernel_bench(solver, kind="cheb_step", level=0, reps=200, nrhs=1, stream=None):
     """Average duration in ms of back-to-back launches of one smoother kernel."""
     ms = C.c_double()
-    F.check(F.lib().dgmg_kernel_bench(solver.handle, KERNEL_KINDS[kind], level, reps,
+    F.check(F.lib().dgmg_kernel_bench(solver.handle, KERNEL_KINDS[kind], level, nrhs, reps,
                                       _stream(stream), C.byref(ms)))
     return ms.value
 

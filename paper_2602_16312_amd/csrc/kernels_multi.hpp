@@ -1,0 +1,446 @@
+// Multi-right-hand-side variants of the per-step kernels: R independent
+// columns share every operator, transfer and smoother load.  Vectors are
+// RHS-minor: entry (DoF t, column r) at t*R + r.  Included by solver.hip
+// after kernels.hpp.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace dgmg {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// acc[r] += (A (va + vb))[row, r] for the tile thread (lc, i), slot by slot:
+// one coalesced block column value per (slot, j) and the R contiguous
+// gathered values of the column cell.
+template <typename T, int B, int R, bool VB>
+__device__ __forceinline__ void ell_row_apply_m(const LevelArgs<T>& L, int tile, int lc,
+                                                const T* __restrict__ va, const T* __restrict__ vb,
+                                                T* acc) {
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
+    const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;
+    const T* __restrict__ A = L.vals + (size_t)s0 * B * TR + threadIdx.x;
+    const int32_t* __restrict__ nbp = L.snb + (size_t)s0 * TC + lc;
+    for (int s = 0; s < ns; ++s) {
+        const int nb = nbp[(size_t)s * TC];
+        T a[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+        const T* x = va + (size_t)nb * B * R;
+        const T* y = VB ? vb + (size_t)nb * B * R : nullptr;
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T v = VB ? x[j * R + r] + y[j * R + r] : x[j * R + r];
+                acc[r] += a[j] * v;
+            }
+    }
+}
+
+// Workgroup sums of R doubles into partial[blockIdx.x * R + r].
+template <int R>
+__device__ __forceinline__ void wg_sum_store_m(const double* v, double* partial) {
+    __shared__ double red[kWG / 64][R];
+    double w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        w[r] = v[r];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w[r] += __shfl_xor(w[r], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int r = 0; r < R; ++r) red[wv][r] = w[r];
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+        double s = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k][threadIdx.x];
+        partial[(size_t)blockIdx.x * R + threadIdx.x] = s;
+    }
+}
+
+// y = A va; optional per-column partial of dot(w, y).
+template <typename T, int B, int R>
+__global__ __launch_bounds__(kWG) void k_apply_m(LevelArgs<T> L, const T* __restrict__ va,
+                                                 T* __restrict__ y, const T* __restrict__ w,
+                                                 double* __restrict__ partial) {
+    DGMG_TILE_THREAD(T, B)
+    double contrib[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) contrib[r] = 0.0;
+    if (active) {
+        T acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0;
+        ell_row_apply_m<T, B, R, false>(L, tile, lc, va, nullptr, acc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            y[(size_t)t * R + r] = acc[r];
+            if (w) contrib[r] = (double)w[(size_t)t * R + r] * (double)acc[r];
+        }
+    }
+    if (partial) wg_sum_store_m<R>(contrib, partial);
+}
+
+// Residual per column r = rhs - A (va + vb) with the same optional epilogues
+// as the single-column kernel (d, xout, per-column ||r||^2, restriction
+// partials).
+template <typename T, int B, int R, bool VB>
+__global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __restrict__ va,
+                                                    const T* __restrict__ vb, const T* __restrict__ rhs,
+                                                    T* __restrict__ r, T* __restrict__ d, T c1,
+                                                    T* __restrict__ xout, double* __restrict__ partial,
+                                                    const T* __restrict__ P, T* __restrict__ rp) {
+    DGMG_TILE_THREAD(T, B)
+    double contrib[R];
+    T rr[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        contrib[q] = 0.0;
+        rr[q] = 0;
+    }
+    if (active) {
+        T acc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0;
+        ell_row_apply_m<T, B, R, VB>(L, tile, lc, va, vb, acc);
+        const T di = L.dinv[t];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const size_t k = (size_t)t * R + q;
+            rr[q] = rhs[k] - acc[q];
+            if (r) r[k] = rr[q];
+            if (d) d[k] = di * rr[q] * c1;
+            if (xout) xout[k] = VB ? va[k] + vb[k] : va[k];
+            contrib[q] = (double)rr[q] * (double)rr[q];
+        }
+    }
+    if (P) {
+        __shared__ T rs[kWG * R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) rs[threadIdx.x * R + q] = rr[q];
+        __syncthreads();
+        if (active) {
+            constexpr int TR = Tile<T, B>::TR;
+            const int j = threadIdx.x - lc * B;
+            const T* Pc = P + ((size_t)tile * B + j) * TR + lc * B;
+            T s[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) s[q] = 0;
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const T pk = Pc[k];
+#pragma unroll
+                for (int q = 0; q < R; ++q) s[q] += pk * rs[(lc * B + k) * R + q];
+            }
+#pragma unroll
+            for (int q = 0; q < R; ++q) rp[(size_t)t * R + q] = s[q];
+        }
+    }
+    if (partial) wg_sum_store_m<R>(contrib, partial);
+}
+
+// One inner Chebyshev step on R columns (VALU).
+template <typename T, int B, int R>
+__global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __restrict__ d,
+                                                     T* __restrict__ x, T* __restrict__ r,
+                                                     T* __restrict__ dn, T cd, T cr, int assign) {
+    DGMG_TILE_THREAD(T, B)
+    if (!active) return;
+    T acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0;
+    ell_row_apply_m<T, B, R, false>(L, tile, lc, d, nullptr, acc);
+    const T di = L.dinv[t];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const size_t k = (size_t)t * R + q;
+        const T dt = d[k];
+        x[k] = assign ? dt : x[k] + dt;
+        const T rr = r[k] - acc[q];
+        r[k] = rr;
+        dn[k] = cd * dt + cr * di * rr;
+    }
+}
+
+// The same Chebyshev step for FP32 8x8 blocks and 8 columns on the matrix
+// cores: per wave 8 cells x 8 rows; v_mfma_f32_4x4x1f32 (16 blocks of 4x4)
+// with block = (cell, half of the rows) takes the tile-ELL value of the
+// lane's (cell, row) as its A operand (lane 4*blk + i supplies row i) and
+// the gathered column values as B (lane 4*blk + j supplies column j of one
+// half of the right-hand sides).  Lane 4*blk + j then holds rows
+// 4*half + 0..3 of right-hand side 4*rh + j.
+__global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, const float* __restrict__ d,
+                                                         float* __restrict__ x, float* __restrict__ r,
+                                                         float* __restrict__ dn, float cd, float cr,
+                                                         int assign) {
+    constexpr int B = 8, R = 8, TC = Tile<float, 8>::TC, TR = Tile<float, 8>::TR;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int lc = threadIdx.x / B;                 // cell in tile of the A operand lane
+    const int cell0 = tile * TC;
+    const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;
+    const float* __restrict__ A = L.vals + (size_t)s0 * B * TR + threadIdx.x;
+    const int32_t* __restrict__ nbp = L.snb + (size_t)s0 * TC + lc;
+    const int jj = lane & 3;                        // B operand / result column in block
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < ns; ++s) {
+        const int nb = nbp[(size_t)s * TC];
+        float a[B], b0[B], b1[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+        const float* xv = d + (size_t)nb * B * R;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            b0[j] = xv[j * R + jj];
+            b1[j] = xv[j * R + 4 + jj];
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[j], b0[j], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[j], b1[j], acc1, 0, 0, 0);
+        }
+    }
+    // lane (4*blk + jj) holds rows 4*(blk&1) + 0..3 of cell (threadIdx.x/64)*8 + blk/2
+    const int blk = lane >> 2;
+    const int cell = cell0 + (threadIdx.x >> 6) * 8 + (blk >> 1);
+    if (cell >= L.n) return;
+    const int row0 = 4 * (blk & 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = cell * B + row0 + i;
+        const float di = L.dinv[t];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t k = (size_t)t * R + 4 * h + jj;
+            const float av = h ? acc1[i] : acc0[i];
+            const float dt = d[k];
+            x[k] = assign ? dt : x[k] + dt;
+            const float rr = r[k] - av;
+            r[k] = rr;
+            dn[k] = cd * dt + cr * di * rr;
+        }
+    }
+}
+
+// First sweep from x = 0 on R columns: r = b, d = dinv * b * c1.
+template <typename T, int R>
+__global__ __launch_bounds__(kWG) void k_cheb_init0_m(int64_t NR, const T* __restrict__ b,
+                                                      const T* __restrict__ dinv, T* __restrict__ r,
+                                                      T* __restrict__ d, T c1) {
+    const int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (k >= NR) return;
+    const T v = b[k];
+    r[k] = v;
+    d[k] = dinv[k / R] * v * c1;
+}
+
+template <typename T, int B, int R>
+__global__ __launch_bounds__(kWG) void k_restrict_sum_m(int32_t nC, const int32_t* __restrict__ cptr,
+                                                        const int32_t* __restrict__ clist,
+                                                        const T* __restrict__ rp, T* __restrict__ rc) {
+    const int t = blockIdx.x * kWG + threadIdx.x;
+    const int K = t / (B * R);
+    if (K >= nC) return;
+    const int jr = t - K * B * R;           // (j, r) within the coarse cell
+    T acc = 0;
+    for (int c = cptr[K]; c < cptr[K + 1]; ++c) acc += rp[(size_t)clist[c] * B * R + jr];
+    rc[t] = acc;
+}
+
+template <typename T, int B, int R>
+__global__ __launch_bounds__(kWG) void k_prolong_add_m(int32_t n, const int32_t* __restrict__ parent,
+                                                       const T* __restrict__ P, const T* __restrict__ xc,
+                                                       const T* __restrict__ dc, T* __restrict__ x) {
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
+    const int tile = blockIdx.x;
+    const int lc = threadIdx.x / B;
+    const int e = tile * TC + lc;
+    if (lc >= TC || e >= n) return;
+    const int t = e * B + (threadIdx.x - lc * B);
+    const int K = parent[e];
+    const T* Pe = P + (size_t)tile * B * TR + threadIdx.x;
+    const T* v = xc + (size_t)K * B * R;
+    const T* w = dc ? dc + (size_t)K * B * R : nullptr;
+    T acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0;
+#pragma unroll 8
+    for (int j = 0; j < B; ++j) {
+        const T p = Pe[(size_t)j * TR];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += p * (w ? v[j * R + q] + w[j * R + q] : v[j * R + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) x[(size_t)t * R + q] += acc[q];
+}
+
+// X = Ainv Rhs for R columns (row-per-wave, right-hand sides staged in LDS).
+constexpr int kCoarseChunkM = 512;
+template <typename Tin, typename Tout, int R>
+__global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const double* __restrict__ Ainv,
+                                                        const Tin* __restrict__ rin,
+                                                        Tout* __restrict__ x) {
+    __shared__ double rs[kCoarseChunkM * R];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row0 = (blockIdx.x * (kWG / 64) + wave) * kCoarseRowsPerWave;
+    double acc[kCoarseRowsPerWave][R];
+#pragma unroll
+    for (int k = 0; k < kCoarseRowsPerWave; ++k)
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[k][q] = 0.0;
+    for (int c0 = 0; c0 < n; c0 += kCoarseChunkM) {
+        const int len = min(kCoarseChunkM, n - c0);
+        __syncthreads();
+        for (int k = threadIdx.x; k < len * R; k += kWG) rs[k] = (double)rin[(size_t)c0 * R + k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kCoarseRowsPerWave; ++k) {
+            const int row = row0 + k;
+            if (row < n) {
+                const double* a = Ainv + (size_t)row * n + c0;
+                for (int c = lane; c < len; c += 64) {
+                    const double av = a[c];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) acc[k][q] += av * rs[c * R + q];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kCoarseRowsPerWave; ++k) {
+        const int row = row0 + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            double s = acc[k][q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (lane == 0 && row < n) x[(size_t)row * R + q] = (Tout)s;
+        }
+    }
+}
+
+// per-column partial dots of RHS-minor vectors
+template <int R>
+__global__ __launch_bounds__(kWG) void k_dot_m(int64_t N, const double* __restrict__ a,
+                                               const double* __restrict__ b, double* __restrict__ partial) {
+    // thread handles DoF t (all R columns)
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = t < N ? a[t * R + q] * b[t * R + q] : 0.0;
+    wg_sum_store_m<R>(v, partial);
+}
+
+// Column sums of R partials into sc[slot*R + r]; mode 1/2 as the single
+// column kernel (gamma update with beta into sc[4*R + r]).
+template <int R>
+__global__ __launch_bounds__(kWG) void k_finalize_m(int32_t np, const double* __restrict__ partial,
+                                                    double* __restrict__ sc, int slot, int mode) {
+    __shared__ double red[kWG];
+    for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+        for (int k = threadIdx.x; k < np; k += kWG) s += partial[(size_t)k * R + q];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kWG / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double v = red[0];
+            if (mode == 0) {
+                sc[slot * R + q] = v;
+            } else {
+                const double g = sc[1 * R + q];
+                sc[4 * R + q] = g != 0.0 ? (mode == 1 ? v : v - sc[5 * R + q]) / g : 0.0;
+                sc[slot * R + q] = v;
+                sc[1 * R + q] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// x += alpha_r p, r -= alpha_r q for active columns; per-column ||r||^2.
+template <int R>
+__global__ __launch_bounds__(kWG) void k_update_xr_m(int64_t N, const double* __restrict__ sc,
+                                                     const int* __restrict__ active,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ partial) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        v[c] = 0.0;
+        if (t < N) {
+            const size_t k = (size_t)t * R + c;
+            const double alpha = active[c] ? sc[1 * R + c] / sc[2 * R + c] : 0.0;
+            x[k] += alpha * p[k];
+            const double rn = r[k] - alpha * q[k];
+            r[k] = rn;
+            v[c] = rn * rn;
+        }
+    }
+    wg_sum_store_m<R>(v, partial);
+}
+
+template <int R>
+__global__ __launch_bounds__(kWG) void k_update_p_m(int64_t NR, const double* __restrict__ sc,
+                                                    const double* __restrict__ z, double* __restrict__ p,
+                                                    int first) {
+    const int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (k >= NR) return;
+    p[k] = first ? z[k] : z[k] + sc[4 * R + (k % R)] * p[k];
+}
+
+// Load vector on R columns: f = cU hist + iapp - chi g, b = M_K f per column.
+template <int B, int R>
+__global__ __launch_bounds__(256) void k_rhs_m(int32_t n, IonicParams P, double cU,
+                                               const double* __restrict__ mass, const double* U,
+                                               const double* Up, const double* __restrict__ iapp,
+                                               const double* __restrict__ g, double* __restrict__ b,
+                                               double* xout) {
+    __shared__ double f[256 * R];
+    const int cells_per = blockDim.x / B;
+    const int lc = threadIdx.x / B, i = threadIdx.x - lc * B;
+    const int cell = blockIdx.x * cells_per + lc;
+    const bool act = lc < cells_per && cell < n;
+    const int64_t t = (int64_t)cell * B + i;
+    double u[R];
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const size_t k = (size_t)t * R + q;
+            u[q] = U[k];
+            const double hist = P.bdf == 2 ? 4.0 * u[q] - Up[k] : u[q];
+            f[threadIdx.x * R + q] = cU * hist + (iapp ? iapp[k] : 0.0) - P.chi * g[k];
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    const double* M = mass + (size_t)cell * ((B * B + 1) / 2 * 2) + i;
+    double acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < B; ++j) {
+        const double m = M[j * B];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += m * f[(lc * B + j) * R + q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const size_t k = (size_t)t * R + q;
+        b[k] = acc[q];
+        if (xout) xout[k] = u[q];
+    }
+}
+
+}  // namespace dgmg

@@ -22,12 +22,14 @@
 #include <memory>
 #include <new>
 #include <stdexcept>
+#include <type_traits>
 #include <vector>
 
 #include "adjoint.hpp"
 #include "internal.hpp"
 #include "ionic.hpp"
 #include "kernels.hpp"
+#include "kernels_multi.hpp"
 
 namespace dgmg {
 
@@ -83,6 +85,7 @@ struct dgmg_hierarchy : public Hierarchy {};
 struct dgmg_solver {
     int dim = 0, p = 0, b = 0, L = 0, prec = 0, S = 1, bdf = 2;
     int cheb_k = 3, cheb_s = 3;
+    int max_rhs = 1, mfma = 0;
     int64_t N = 0;
     bool on_device = false;
     std::vector<DevLevel> lv;
@@ -95,6 +98,8 @@ struct dgmg_solver {
     double* partial = nullptr;
     double* sc = nullptr;
     double* sc_host = nullptr;
+    int32_t* act = nullptr;        // per-column active mask of multi-column PCG
+    int32_t* act_host = nullptr;   // pinned staging of that mask
     double* mass = nullptr;
     // adjoint data (optional)
     bool has_adjoint = false;
@@ -144,6 +149,7 @@ struct dgmg_solver {
         }
         for (void* p : allocs) (void)hipFree(p);
         if (sc_host) (void)hipHostFree(sc_host);
+        if (act_host) (void)hipHostFree(act_host);
     }
 };
 
@@ -225,52 +231,83 @@ static unsigned level_tiles(const dgmg_solver* s, const DevLevel& L) {
     DISPATCH_B(s->b, g = tiles_for<T, BV>(L));
     return g;
 }
-template <typename T>
+template <typename T, int R = 1>
 static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, const T* w,
                          double* partial, hipStream_t st) {
     ProfScope ps(s, PK_APPLY, level_index(s, L), st);
-    DISPATCH_B(s->b, k_apply<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w, partial));
+    if constexpr (R == 1) {
+        DISPATCH_B(s->b, k_apply<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w, partial));
+    } else {
+        DISPATCH_B(s->b, k_apply_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w,
+                                                                                   partial));
+    }
 }
-template <typename T>
+template <typename T, int R = 1>
 static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, const T* rhs,
                             T* r, T* d, T c1, T* xout, double* partial, hipStream_t st,
                             const T* P = nullptr, T* rp = nullptr) {
     ProfScope ps(s, PK_RESIDUAL, level_index(s, L), st);
-    if (vb) {
-        DISPATCH_B(s->b, k_residual<T, BV, true><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                             largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+    if constexpr (R == 1) {
+        if (vb) {
+            DISPATCH_B(s->b, k_residual<T, BV, true><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+        } else {
+            DISPATCH_B(s->b, k_residual<T, BV, false><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+        }
     } else {
-        DISPATCH_B(s->b, k_residual<T, BV, false><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                             largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+        if (vb) {
+            DISPATCH_B(s->b, k_residual_m<T, BV, R, true><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+        } else {
+            DISPATCH_B(s->b, k_residual_m<T, BV, R, false><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+        }
     }
 }
-template <typename T>
+template <typename T, int R = 1>
 static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* r, T* dn, T cd, T cr,
                         int assign, hipStream_t st) {
     ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
-    DISPATCH_B(s->b, k_cheb_step<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r, dn, cd,
-                                                                              cr, assign));
+    if constexpr (R == 1) {
+        DISPATCH_B(s->b, k_cheb_step<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r, dn, cd,
+                                                                                  cr, assign));
+    } else {
+        if constexpr (std::is_same<T, float>::value && R == 8) {
+            if (s->mfma && s->b == 8) {
+                k_cheb_step_mfma8<<<tiles_for<float, 8>(L), kWG, 0, st>>>(largs<float>(L), d, x, r, dn, cd, cr,
+                                                                         assign);
+                return;
+            }
+        }
+        DISPATCH_B(s->b, k_cheb_step_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r, dn,
+                                                                                       cd, cr, assign));
+    }
 }
 
-template <typename T>
+template <typename T, int R = 1>
 static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
     const int n = (int)s->nc_dofs;
     ProfScope ps(s, PK_COARSE, s->L - 1, st);
     const int rows_per_wg = (kWG / 64) * kCoarseRowsPerWave;
-    k_coarse_solve<T, T><<<(n + rows_per_wg - 1) / rows_per_wg, kWG, 0, st>>>(n, s->Ainv, rc, xc);
+    if constexpr (R == 1)
+        k_coarse_solve<T, T><<<(n + rows_per_wg - 1) / rows_per_wg, kWG, 0, st>>>(n, s->Ainv, rc, xc);
+    else
+        k_coarse_solve_m<T, T, R><<<(n + rows_per_wg - 1) / rows_per_wg, kWG, 0, st>>>(n, s->Ainv, rc, xc);
 }
 
-// One V-cycle from level l; the result is x + d (d may be null).
-template <typename T>
+// One V-cycle from level l on R columns; the result is x + d (d may be null).
+template <typename T, int R = 1>
 static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     DevLevel& L = s->lv[l];
     T* b = (T*)L.vb;
     if (l == s->L - 1) {
-        coarse_solve<T>(s, b, (T*)L.vx, st);
+        coarse_solve<T, R>(s, b, (T*)L.vx, st);
         *xres = (T*)L.vx;
         *dres = nullptr;
         return;
     }
+    const int64_t NR = L.N * R;
     const double theta = 0.5 * (L.lam_hi + L.lam_lo), delta = 0.5 * (L.lam_hi - L.lam_lo);
     const double sigma1 = theta / delta;
     const T c1 = (T)(1.0 / theta);
@@ -279,20 +316,23 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     const T* dinv = largs<T>(L).dinv;
     auto sweep = [&]() {
         if (xzero && !pending) {
-            k_cheb_init0<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, b, dinv, r, d, c1);
+            if constexpr (R == 1)
+                k_cheb_init0<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, b, dinv, r, d, c1);
+            else
+                k_cheb_init0_m<T, R><<<blocks_for(NR), kWG, 0, st>>>(NR, b, dinv, r, d, c1);
         } else if (pending) {
             // r = b - A(x + d), materialise x + d into x2
-            launch_residual<T>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, d2, c1, x2, nullptr, st);
+            launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, d2, c1, x2, nullptr, st);
             std::swap(x, x2);
             std::swap(d, d2);
             xzero = false;
         } else {
-            launch_residual<T>(s, L, x, (const T*)nullptr, b, r, d, c1, (T*)nullptr, nullptr, st);
+            launch_residual<T, R>(s, L, x, (const T*)nullptr, b, r, d, c1, (T*)nullptr, nullptr, st);
         }
         double rho = 1.0 / sigma1;
         for (int i = 1; i < s->cheb_k; ++i) {
             const double rn = 1.0 / (2.0 * sigma1 - rho);
-            launch_step<T>(s, L, d, x, r, d2, (T)(rn * rho), (T)(2.0 * rn / delta), xzero ? 1 : 0, st);
+            launch_step<T, R>(s, L, d, x, r, d2, (T)(rn * rho), (T)(2.0 * rn / delta), xzero ? 1 : 0, st);
             xzero = false;
             std::swap(d, d2);
             rho = rn;
@@ -305,29 +345,39 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     DevLevel& C = s->lv[l + 1];
     T* rp = d2;   // free: the pending d is consumed here
     if (pending) {
-        launch_residual<T>(s, L, xzero ? d : x, xzero ? nullptr : d, b, (T*)nullptr, (T*)nullptr, c1, x2,
-                           nullptr, st, Pof<T>(L), rp);
+        launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, (T*)nullptr, (T*)nullptr, c1, x2,
+                              nullptr, st, Pof<T>(L), rp);
         std::swap(x, x2);
         xzero = false;
         pending = false;
     } else {
         // no smoothing: x = 0 and r = b
-        k_fill<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, x, (T)0);
+        k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, x, (T)0);
         xzero = false;
-        launch_residual<T>(s, L, x, (const T*)nullptr, b, (T*)nullptr, (T*)nullptr, c1, (T*)nullptr,
-                           nullptr, st, Pof<T>(L), rp);
+        launch_residual<T, R>(s, L, x, (const T*)nullptr, b, (T*)nullptr, (T*)nullptr, c1, (T*)nullptr,
+                              nullptr, st, Pof<T>(L), rp);
     }
     {
     ProfScope ps(s, PK_RESTRICT, l, st);
-    DISPATCH_B(s->b, k_restrict_sum<T, BV><<<blocks_for(C.N), kWG, 0, st>>>(C.n, C.child_ptr, C.child_list,
-                                                                             rp, (T*)C.vb));
+    if constexpr (R == 1) {
+        DISPATCH_B(s->b, k_restrict_sum<T, BV><<<blocks_for(C.N), kWG, 0, st>>>(C.n, C.child_ptr, C.child_list,
+                                                                                 rp, (T*)C.vb));
+    } else {
+        DISPATCH_B(s->b, k_restrict_sum_m<T, BV, R><<<blocks_for(C.N * R), kWG, 0, st>>>(
+                             C.n, C.child_ptr, C.child_list, rp, (T*)C.vb));
+    }
     }
     T *xc, *dc;
-    vcycle<T>(s, l + 1, st, &xc, &dc);
+    vcycle<T, R>(s, l + 1, st, &xc, &dc);
     {
     ProfScope ps(s, PK_PROLONG, l, st);
-    DISPATCH_B(s->b, k_prolong_add<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent, Pof<T>(L), xc,
-                                                                                 dc, x));
+    if constexpr (R == 1) {
+        DISPATCH_B(s->b, k_prolong_add<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent, Pof<T>(L), xc,
+                                                                                     dc, x));
+    } else {
+        DISPATCH_B(s->b, k_prolong_add_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent,
+                                                                                         Pof<T>(L), xc, dc, x));
+    }
     }
     for (int k = 0; k < s->cheb_s; ++k) sweep();
     // hand back the level's buffers as they are now named
@@ -339,24 +389,26 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     *dres = pending ? d : nullptr;
 }
 
-// z = V(r), r and z FP64 of length N.
+// z = V(r), r and z FP64 of length N x R (column-minor).
+template <int R = 1>
 static void apply_vcycle(dgmg_solver* s, const double* r, double* z, hipStream_t st) {
     DevLevel& L0 = s->lv[0];
+    const int64_t NR = s->N * R;
     if (s->prec == DGMG_PREC_FP64) {
         L0.vb = (void*)r;
         double *x, *d;
-        vcycle<double>(s, 0, st, &x, &d);
-        k_cast<double, double><<<blocks_for(s->N), kWG, 0, st>>>(s->N, x, d, z);
+        vcycle<double, R>(s, 0, st, &x, &d);
+        k_cast<double, double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z);
     } else {
-        k_cast<double, float><<<blocks_for(s->N), kWG, 0, st>>>(s->N, r, nullptr, (float*)L0.vb);
+        k_cast<double, float><<<blocks_for(NR), kWG, 0, st>>>(NR, r, nullptr, (float*)L0.vb);
         float *x, *d;
-        vcycle<float>(s, 0, st, &x, &d);
-        k_cast<float, double><<<blocks_for(s->N), kWG, 0, st>>>(s->N, x, d, z);
+        vcycle<float, R>(s, 0, st, &x, &d);
+        k_cast<float, double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z);
     }
 }
 
-static double read_scalars(dgmg_solver* s, hipStream_t st) {
-    HIPCHK(hipMemcpyAsync(s->sc_host, s->sc, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+static double read_scalars(dgmg_solver* s, hipStream_t st, int R = 1) {
+    HIPCHK(hipMemcpyAsync(s->sc_host, s->sc, 8 * (size_t)R * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return s->sc_host[0];
 }
@@ -425,6 +477,94 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
     }
     return DGMG_NOT_CONVERGED;
 }
+
+// PCG on R columns at once: every A_0 apply, V-cycle and reduction serves all
+// columns; alpha, beta and the stopping test are per column.  A converged
+// column is frozen (alpha = 0) while the others iterate.
+template <int R>
+static int pcg_multi(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& o,
+                     dgmg_pcg_stats* stats, hipStream_t st) {
+    const int64_t N = s->N, NR = N * R;
+    const unsigned nb = blocks_for(N);
+    DevLevel& L0 = s->lv[0];
+    const unsigned nt = level_tiles<double>(s, L0);
+    launch_residual<double, R>(s, L0, x, nullptr, b, s->r, nullptr, 1.0, nullptr, s->partial, st);
+    k_finalize_m<R><<<1, kWG, 0, st>>>(nt, s->partial, s->sc, 0, 0);
+    if (o.tol_mode == DGMG_TOL_REL_B) {
+        k_dot_m<R><<<nb, kWG, 0, st>>>(N, b, b, s->partial);
+        k_finalize_m<R><<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 6, 0);
+    }
+    read_scalars(s, st, R);
+    double thresh[R];
+    int n_active = 0;
+    for (int c = 0; c < R; ++c) {
+        const double r0 = std::sqrt(s->sc_host[c]);
+        if (!std::isfinite(r0)) fail(DGMG_ENAN, "non-finite initial residual");
+        const double bn = o.tol_mode == DGMG_TOL_REL_B ? std::sqrt(s->sc_host[6 * R + c]) : 0.0;
+        thresh[c] = o.tol_mode == DGMG_TOL_ABS ? o.tol : (o.tol_mode == DGMG_TOL_REL_B ? o.tol * bn : o.tol * r0);
+        stats[c].its = 0;
+        stats[c].r0 = r0;
+        stats[c].rfin = r0;
+        const bool done = r0 == 0.0 || r0 <= thresh[c];
+        stats[c].converged = done ? 1 : 0;
+        s->act_host[c] = done ? 0 : 1;
+        n_active += done ? 0 : 1;
+    }
+    if (n_active == 0) return DGMG_OK;
+    // the pinned mask is rewritten only after the next synchronisation of st
+    HIPCHK(hipMemcpyAsync(s->act, s->act_host, R * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    apply_vcycle<R>(s, s->r, s->z, st);
+    k_dot_m<R><<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
+    k_finalize_m<R><<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 1, 0);
+    k_update_p_m<R><<<blocks_for(NR), kWG, 0, st>>>(NR, s->sc, s->z, s->pv, 1);
+    int its = 0;
+    while (its < o.max_it) {
+        launch_apply<double, R>(s, L0, s->pv, s->q, s->pv, s->partial, st);
+        k_finalize_m<R><<<1, kWG, 0, st>>>(nt, s->partial, s->sc, 2, 0);
+        k_update_xr_m<R><<<nb, kWG, 0, st>>>(N, s->sc, s->act, s->pv, s->q, x, s->r, s->partial);
+        k_finalize_m<R><<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 0, 0);
+        read_scalars(s, st, R);
+        ++its;
+        n_active = 0;
+        for (int c = 0; c < R; ++c) {
+            if (!s->act_host[c]) continue;
+            const double gam = s->sc_host[1 * R + c], pq = s->sc_host[2 * R + c];
+            const double rn = std::sqrt(s->sc_host[c]);
+            stats[c].its = its;
+            stats[c].rfin = rn;
+            if (!(pq > 0.0) || !(gam > 0.0)) {
+                if (!std::isfinite(pq) || !std::isfinite(gam)) fail(DGMG_ENAN, "non-finite PCG scalar");
+                fail(DGMG_ENOTSPD, "PCG breakdown: (p, A p) <= 0 or (r, z) <= 0");
+            }
+            if (!std::isfinite(rn)) fail(DGMG_ENAN, "non-finite residual");
+            if (rn <= thresh[c]) {
+                stats[c].converged = 1;
+                s->act_host[c] = 0;
+            } else {
+                ++n_active;
+            }
+        }
+        if (n_active == 0) return DGMG_OK;
+        HIPCHK(hipMemcpyAsync(s->act, s->act_host, R * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        if (o.flexible) std::swap(s->z, s->zold);
+        apply_vcycle<R>(s, s->r, s->z, st);
+        if (o.flexible) {
+            k_dot_m<R><<<nb, kWG, 0, st>>>(N, s->r, s->zold, s->partial);
+            k_finalize_m<R><<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 5, 0);
+        }
+        k_dot_m<R><<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
+        k_finalize_m<R><<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 3, o.flexible ? 2 : 1);
+        k_update_p_m<R><<<blocks_for(NR), kWG, 0, st>>>(NR, s->sc, s->z, s->pv, 0);
+    }
+    HIPCHK(hipStreamSynchronize(st));   // the last mask upload has completed
+    return DGMG_NOT_CONVERGED;
+}
+
+#define DISPATCH_R(rval, ...)                                                          \
+    switch (rval) {                                                                    \
+        case 8: { constexpr int RV = 8; __VA_ARGS__; } break;                          \
+        default: fail(DGMG_EINVAL, "unsupported number of right-hand sides");          \
+    }
 
 // ------------------------------------------------------------------ setup
 static void build_nbr(const BlockOp& A, std::vector<int32_t>& ptr, std::vector<int32_t>& cell,
@@ -594,7 +734,7 @@ static void upload_level(dgmg_solver* s, int l) {
         L.child_list = s->upload(cl);
     }
     const size_t es = s->prec == DGMG_PREC_MIXED ? sizeof(float) : sizeof(double);
-    auto vec = [&]() -> void* { return (void*)s->dalloc<char>(L.N * es); };
+    auto vec = [&]() -> void* { return (void*)s->dalloc<char>(L.N * s->max_rhs * es); };
     L.vb = vec(); L.vx = vec(); L.vx2 = vec(); L.vr = vec(); L.vd = vec(); L.vd2 = vec();
 }
 
@@ -839,6 +979,10 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     s->bdf = ph->bdf;
     s->cheb_k = mg->cheb_degree;
     s->cheb_s = mg->cheb_sweeps;
+    if (mg->max_rhs != 0 && mg->max_rhs != 1 && mg->max_rhs != DGMG_MULTI_RHS)
+        fail(DGMG_EINVAL, "max_rhs must be 0, 1 or DGMG_MULTI_RHS");
+    s->max_rhs = mg->max_rhs > 1 ? mg->max_rhs : 1;
+    s->mfma = mg->mfma ? 1 : 0;
     s->N = h->n_cells * re.b;
     s->S = ph->model == DGMG_MODEL_BO ? 3 : 1;
     s->parents = h->parent;
@@ -926,19 +1070,21 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     if (mg->device_setup) {
         for (int l = 0; l < s->L; ++l) upload_level(s, l);
         s->Ainv = coarse_on_device ? device_spd_inverse(s, Ac, s->nc_dofs) : s->upload(Ac);
-        const int64_t N = s->N;
-        s->r = s->dalloc<double>(N);
-        s->z = s->dalloc<double>(N);
-        s->zold = s->dalloc<double>(N);
-        s->pv = s->dalloc<double>(N);
-        s->q = s->dalloc<double>(N);
-        s->bwork = s->dalloc<double>(N);
+        const int64_t N = s->N, R = s->max_rhs;
+        s->r = s->dalloc<double>(N * R);
+        s->z = s->dalloc<double>(N * R);
+        s->zold = s->dalloc<double>(N * R);
+        s->pv = s->dalloc<double>(N * R);
+        s->q = s->dalloc<double>(N * R);
+        s->bwork = s->dalloc<double>(N * R);
         s->tmp64a = s->dalloc<double>(N);
         s->tmp64b = s->dalloc<double>(N);
-        s->partial = s->dalloc<double>(std::max(blocks_for(N), level_tiles<double>(s, s->lv[0])) + 16);
-        s->sc = s->dalloc<double>(8);
-        HIPCHK(hipMemset(s->sc, 0, 8 * sizeof(double)));
-        HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * sizeof(double), hipHostMallocDefault));
+        s->partial = s->dalloc<double>((std::max(blocks_for(N), level_tiles<double>(s, s->lv[0])) + 16) * R);
+        s->sc = s->dalloc<double>(8 * R);
+        HIPCHK(hipMemset(s->sc, 0, 8 * R * sizeof(double)));
+        HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * R * sizeof(double), hipHostMallocDefault));
+        s->act = s->dalloc<int32_t>(R);
+        HIPCHK(hipHostMalloc((void**)&s->act_host, R * sizeof(int32_t), hipHostMallocDefault));
         s->mass = s->upload(to_colmajor<double>(s->mass_h, s->b));
         if (want_adj) {
             const int b = s->b, R = 2 * b;
@@ -1028,6 +1174,83 @@ int dgmg_time_step(dgmg_solver* s, dgmg_state* z, double t_next, const double* i
     std::swap(z->U, z->Uprev);
     std::swap(z->W, z->Wprev);
     return rc;
+    API_END
+}
+
+static void need_multi(const dgmg_solver* s, int32_t nrhs) {
+    need_device(s);
+    if (nrhs != DGMG_MULTI_RHS) fail(DGMG_EINVAL, "nrhs must be DGMG_MULTI_RHS");
+    if (s->max_rhs < nrhs) fail(DGMG_EINVAL, "solver was set up with max_rhs < nrhs");
+}
+
+int dgmg_pcg_solve_multi(dgmg_solver* s, int32_t nrhs, const double* b, double* x, const dgmg_pcg_opts* o,
+                         dgmg_pcg_stats* st, void* stream) {
+    API_BEGIN
+    need_multi(s, nrhs);
+    if (!b || !x || !o || !st) fail(DGMG_EINVAL, "null argument");
+    int rc = DGMG_OK;
+    DISPATCH_R(nrhs, rc = pcg_multi<RV>(s, b, x, *o, st, (hipStream_t)stream));
+    return rc;
+    API_END
+}
+
+int dgmg_time_step_multi(dgmg_solver* s, int32_t nrhs, dgmg_state* z, double t_next, const double* iapp,
+                         const dgmg_pcg_opts* o, dgmg_pcg_stats* st, void* stream) {
+    API_BEGIN
+    (void)t_next;
+    need_multi(s, nrhs);
+    if (!z || !o || !st || !z->U || !z->Uprev || !z->W || !z->Wprev || !z->g) fail(DGMG_EINVAL, "null argument");
+    hipStream_t hs = (hipStream_t)stream;
+    const int64_t NR = s->N * nrhs;
+    // pointwise: the gates of all columns are one S x (N nrhs) array
+    k_ionic<<<blocks_for(NR), 256, 0, hs>>>(NR, s->ip, z->U, z->Uprev, z->W, z->Wprev, z->Wprev, z->g);
+    const int cells_per = 256 / s->b;
+    const unsigned nblk = (unsigned)((s->lv[0].n + cells_per - 1) / cells_per);
+    int rc = DGMG_OK;
+    DISPATCH_R(nrhs, {
+        DISPATCH_B(s->b, k_rhs_m<BV, RV><<<nblk, cells_per * BV, 0, hs>>>(
+                             s->lv[0].n, s->ip, s->cU, s->mass, z->U, z->Uprev, iapp, z->g, s->bwork, z->Uprev));
+        HIPCHK(hipGetLastError());
+        rc = pcg_multi<RV>(s, s->bwork, z->Uprev, *o, st, hs);
+    });
+    std::swap(z->U, z->Uprev);
+    std::swap(z->W, z->Wprev);
+    return rc;
+    API_END
+}
+
+int dgmg_apply_multi(dgmg_solver* s, int32_t level, int32_t prec, int32_t nrhs, const double* x, double* y,
+                     void* stream) {
+    API_BEGIN
+    need_multi(s, nrhs);
+    if (!x || !y) fail(DGMG_EINVAL, "null argument");
+    if (level < 0 || level >= s->L) fail(DGMG_EINVAL, "level out of range");
+    if (level == s->L - 1 && s->L > 1) fail(DGMG_EUNSUPPORTED, "the coarsest level is stored factorised");
+    hipStream_t hs = (hipStream_t)stream;
+    DevLevel& L = s->lv[level];
+    const int64_t NR = L.N * nrhs;
+    DISPATCH_R(nrhs, {
+        if (prec == DGMG_PREC_FP64) {
+            launch_apply<double, RV>(s, L, x, y, nullptr, nullptr, hs);
+        } else {
+            if (s->prec != DGMG_PREC_MIXED) fail(DGMG_EINVAL, "no FP32 copy in an FP64 solver");
+            k_cast<double, float><<<blocks_for(NR), kWG, 0, hs>>>(NR, x, nullptr, (float*)L.vx2);
+            launch_apply<float, RV>(s, L, (float*)L.vx2, (float*)L.vr, nullptr, nullptr, hs);
+            k_cast<float, double><<<blocks_for(NR), kWG, 0, hs>>>(NR, (float*)L.vr, nullptr, y);
+        }
+    });
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_vcycle_multi(dgmg_solver* s, int32_t nrhs, const double* r, double* z, void* stream) {
+    API_BEGIN
+    need_multi(s, nrhs);
+    if (!r || !z) fail(DGMG_EINVAL, "null argument");
+    DISPATCH_R(nrhs, apply_vcycle<RV>(s, r, z, (hipStream_t)stream));
+    HIPCHK(hipGetLastError());
+    return DGMG_OK;
     API_END
 }
 
@@ -1167,39 +1390,48 @@ int dgmg_grad_accumulate(dgmg_solver* s, const double* lambda, const double* U, 
     API_END
 }
 
-int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t reps, void* stream,
+int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t nrhs, int32_t reps, void* stream,
                       double* avg_ms) {
     API_BEGIN
     need_device(s);
     if (level < 0 || level >= s->L - 1 || reps < 1) fail(DGMG_EINVAL, "bad level or repetition count");
     if (kind != PK_CHEB_STEP && kind != PK_RESIDUAL) fail(DGMG_EINVAL, "kernel kind not benchmarkable");
+    if (nrhs != 1) need_multi(s, nrhs);
     hipStream_t st = (hipStream_t)stream;
     DevLevel& L = s->lv[level];
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
-    auto run = [&](auto tag) {
+    auto run = [&](auto tag, auto rtag) {
         using T = decltype(tag);
+        constexpr int R = decltype(rtag)::value;
+        const int64_t NR = L.N * R;
         T *x = (T*)L.vx, *r = (T*)L.vr, *d = (T*)L.vd, *d2 = (T*)L.vd2, *x2 = (T*)L.vx2;
         const T* bb = (const T*)L.vb;
-        const T* dinv = largs<T>(L).dinv;
-        // defined inputs: x = d = dinv, r = b
-        k_cast<T, T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, dinv, nullptr, x);
-        k_cast<T, T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, dinv, nullptr, d);
-        k_cast<T, T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, dinv, nullptr, r);
+        // defined inputs
+        k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, x, (T)1e-3);
+        k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, d, (T)1e-3);
+        k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, r, (T)1e-3);
         HIPCHK(hipEventRecord(a, st));
         for (int k = 0; k < reps; ++k) {
             if (kind == PK_CHEB_STEP) {
-                launch_step<T>(s, L, d, x, r, d2, (T)0.5, (T)0.1, 0, st);
+                launch_step<T, R>(s, L, d, x, r, d2, (T)0.5, (T)0.1, 0, st);
                 std::swap(d, d2);
             } else {
-                launch_residual<T>(s, L, x, d, bb ? bb : r, r, d2, (T)0.5, x2, nullptr, st);
+                launch_residual<T, R>(s, L, x, d, bb ? bb : r, r, d2, (T)0.5, x2, nullptr, st);
             }
         }
         HIPCHK(hipEventRecord(b, st));
     };
-    if (s->prec == DGMG_PREC_MIXED) run(float{});
-    else run(double{});
+    using R1 = std::integral_constant<int, 1>;
+    using R8 = std::integral_constant<int, DGMG_MULTI_RHS>;
+    if (s->prec == DGMG_PREC_MIXED) {
+        if (nrhs == 1) run(float{}, R1{});
+        else run(float{}, R8{});
+    } else {
+        if (nrhs == 1) run(double{}, R1{});
+        else run(double{}, R8{});
+    }
     HIPCHK(hipEventSynchronize(b));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, a, b));

@@ -1,0 +1,182 @@
+"""Multi-right-hand-side path (8 columns, column-minor) against the
+single-column path and the FP64 oracle: level applies, V-cycle, PCG with
+per-column scalars and stopping, and the time stepper for 8 simulations that
+differ in their stimulus site.  Cases: a small agglomerated shell (STR
+R-tree, 3D Q1: 8x8 blocks, the matrix-core Chebyshev step) and small grids
+with the other block sizes (2D Q1 4x4, 2D Q2 9x9, 3D Q2 27x27)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from gpu_util import dev, host, need_gpu, rel, say, torch
+from paper_2602_16312_amd import api, problem
+from workloads import make_problem
+from oracle.assemble import system_matrix
+from oracle.stepper import Simulation
+
+pytestmark = pytest.mark.gpu
+R = 8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+_CACHE = {}
+
+
+def case(name):
+    if name not in _CACHE:
+        if name == "shell":
+            pr = make_problem("c4", h=0.09)
+        elif name == "c3":
+            pr = make_problem("c3", n=4)
+        else:
+            pr = make_problem(name, n=16)
+        _CACHE[name] = pr
+    return _CACHE[name]
+
+
+def columns(N, seed, zero_col=None):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((N, R))
+    if zero_col is not None:
+        X[:, zero_col] = 0.0
+    return X
+
+
+CASES = ["shell", "c1", "c2", "c3"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_apply_multi_matches_single_and_oracle(name):
+    pr = case(name)
+    h, s = problem.build(pr, precision="mixed", max_rhs=R)
+    inf = s.info()
+    A0 = system_matrix(pr)[0]
+    for level in range(max(1, inf["n_levels"] - 1)):
+        Nl = inf["n_cells"][level] * inf["b"]
+        X = columns(Nl, 11 + level)
+        for prec in ("fp64", "mixed"):
+            say("apply_multi", name, level, prec)
+            Y = torch.empty(Nl * R, dtype=torch.float64, device="cuda")
+            api.apply_multi(s, level, dev(X.ravel()), Y, precision=prec)
+            Ym = host(Y).reshape(Nl, R)
+            y1 = torch.empty(Nl, dtype=torch.float64, device="cuda")
+            for c in range(R):
+                api.apply(s, level, dev(X[:, c]), y1, precision=prec)
+                assert rel(Ym[:, c], host(y1)) <= (1e-14 if prec == "fp64" else 1e-6), (level, c)
+            if level == 0 and prec == "fp64":
+                assert rel(Ym, A0 @ X) <= 1e-13
+
+
+@pytest.mark.parametrize("name,prec,mfma", [("shell", "fp64", False), ("shell", "mixed", False),
+                                            ("shell", "mixed", True), ("c1", "mixed", False),
+                                            ("c2", "fp64", False), ("c2", "mixed", False),
+                                            ("c3", "mixed", False)])
+def test_vcycle_multi_matches_single(name, prec, mfma):
+    pr = case(name)
+    h, s = problem.build(pr, precision=prec, max_rhs=R, mfma=mfma)
+    N = pr["N"]
+    Rr = columns(N, 5, zero_col=2)
+    say("vcycle_multi", name, prec, mfma)
+    Z = torch.empty(N * R, dtype=torch.float64, device="cuda")
+    api.vcycle_multi(s, dev(Rr.ravel()), Z)
+    Zm = host(Z).reshape(N, R)
+    assert np.all(Zm[:, 2] == 0.0)
+    z1 = torch.empty(N, dtype=torch.float64, device="cuda")
+    for c in range(R):
+        api.vcycle(s, dev(Rr[:, c]), z1)
+        ref = host(z1)
+        if c == 2:
+            continue
+        # FP64: same arithmetic per column; FP32: the matrix cores round
+        # their products differently from the vector FMA chain
+        tol = 1e-13 if prec == "fp64" else (2e-5 if mfma else 1e-6)
+        assert rel(Zm[:, c], ref) <= tol, (c, rel(Zm[:, c], ref))
+
+
+@pytest.mark.parametrize("name,prec,mfma,tol", [("shell", "fp64", False, 1e-10),
+                                                ("shell", "mixed", True, 1e-8),
+                                                ("shell", "mixed", False, 1e-8),
+                                                ("c2", "mixed", False, 1e-8),
+                                                ("c3", "fp64", False, 1e-10)])
+def test_pcg_multi_per_column(name, prec, mfma, tol):
+    pr = case(name)
+    h, s = problem.build(pr, precision=prec, max_rhs=R, mfma=mfma)
+    A0 = system_matrix(pr)[0]
+    N = pr["N"]
+    B = columns(N, 21, zero_col=5)
+    B[:, 6] = 1e6 * B[:, 0]          # scaled copy: same iterations as column 0
+    B[:, 7] = A0 @ np.ones(N)        # smooth solution
+    say("pcg_multi", name, prec, mfma, tol)
+    X = torch.zeros(N * R, dtype=torch.float64, device="cuda")
+    stats = api.pcg_solve_multi(s, dev(B.ravel()), X, tol=tol)
+    Xm = host(X).reshape(N, R)
+    assert all(st["converged"] for st in stats)
+    assert stats[5]["its"] == 0 and np.all(Xm[:, 5] == 0.0)
+    assert stats[6]["its"] == stats[0]["its"]
+    for c in range(R):
+        if c == 5:
+            continue
+        # the stopping test, re-evaluated on the host with the oracle's A_0
+        res = np.linalg.norm(B[:, c] - A0 @ Xm[:, c]) / np.linalg.norm(B[:, c])
+        assert res <= 1.05 * tol, (c, res)
+    # against the single-column solver: same iteration count, same iterate
+    x1 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for c in (0, 3, 7):
+        x1.zero_()
+        st1 = api.pcg_solve(s, dev(B[:, c]), x1, tol=tol)
+        assert abs(st1["its"] - stats[c]["its"]) <= (0 if prec == "fp64" else 1), (c, st1, stats[c])
+        if prec == "fp64":
+            assert rel(Xm[:, c], host(x1)) <= 1e-12
+    # against a direct solve: error within the condition-number bound
+    xd = spla.spsolve(A0.tocsc(), B[:, 7])
+    assert rel(Xm[:, 7], xd) <= 1e4 * tol
+
+
+def multi_state(pr):
+    N, S = pr["N"], pr["S"]
+    U0 = np.repeat(pr["U0"][:, None], R, axis=1).ravel()
+    W0 = np.repeat(pr["W0"].reshape(S, N)[:, :, None], R, axis=2).ravel()
+    return api.State(dev(U0), dev(U0), dev(W0), dev(W0),
+                     torch.empty(N * R, dtype=torch.float64, device="cuda"))
+
+
+def iapp_cols(pr, t):
+    """Applied current of the 8 simulations (one stimulus site each)."""
+    out = np.zeros((pr["N"], R))
+    if t <= pr["stim_tend"] + 1e-12:
+        for c in range(R):
+            out[np.repeat(pr["stim_masks"][c], pr["b"]), c] = pr["stim_amp"]
+    return out
+
+
+@pytest.mark.parametrize("prec,mfma,tol", [("fp64", False, 1e-12), ("mixed", True, 1e-8)])
+def test_time_step_multi_matches_oracle_per_column(prec, mfma, tol):
+    pr = case("shell")
+    steps = 4
+    sim = Simulation(pr)
+    lam = sim.mg.lam if prec == "fp64" else None
+    h, s = problem.build(pr, precision=prec, max_rhs=R, mfma=mfma, lam_override=lam)
+    N, S = pr["N"], pr["S"]
+    st = multi_state(pr)
+    hist, its = [], []
+    for k in range(steps):
+        t = (k + 1) * pr["dt"]
+        say("time_step_multi", prec, mfma, k)
+        stats = api.time_step_multi(s, st, t, iapp=dev(iapp_cols(pr, t).ravel()), tol=tol)
+        assert all(x["converged"] for x in stats)
+        its.append([x["its"] for x in stats])
+        hist.append(host(st.U).reshape(N, R).copy())
+    Wg = host(st.W).reshape(S, N, R)
+    print(f"shell {prec} mfma={mfma}: its per step and column {its}")
+    worst = 0.0
+    for c in range(R):
+        _, ref, ostats = sim.run(steps, 1e-13, iapp_fn=lambda t, c=c: iapp_cols(pr, t)[:, c])
+        for k in range(steps):
+            worst = max(worst, rel(hist[k][:, c], ref[k]))
+    print(f"max rel err vs oracle over columns and steps: {worst:.2e}")
+    assert worst <= (1e-10 if prec == "fp64" else 1e3 * tol)
+    assert np.isfinite(Wg).all()
