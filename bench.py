@@ -26,7 +26,16 @@ WORKLOADS = {
           "3-level agglomerated V-cycle PCG to rel. residual 1e-8",
     "c3": "64^3 Q2 SIPDG monodomain cube, rotating fibres, Bueno-Orovio, "
           "4-level agglomerated V-cycle PCG to rel. residual 1e-8",
+    "c4": "1.0M-hex jittered ellipsoidal shell, Q1, transmural fibres, Bueno-Orovio, "
+          "5-level STR R-tree agglomerated V-cycle PCG to rel. residual 1e-8, apex stimulus",
+    "c4x8": "1.0M-hex jittered ellipsoidal shell, Q1, transmural fibres, Bueno-Orovio, "
+            "5-level STR R-tree agglomerated V-cycle, 8 simulations (8 stimulus sites) "
+            "solved together by 8-column PCG to rel. residual 1e-8 per column",
+    "c5": "gradient of a 64-sensor misfit over 50 steps of the 256x256 Q2 Aliev-Panfilov "
+          "problem w.r.t. 65,536 cell conductivity scalings: forward, checkpointed replay "
+          "and discrete adjoint (FP64, PCG to rel. residual 1e-13)",
 }
+MFMA_F32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -40,17 +49,25 @@ def _stats(v):
     return dict(mean=float(a.mean()), std=float(a.std()), min=int(a.min()), max=int(a.max()))
 
 
-def cheb_step_bytes(info, prec_bytes):
+def cheb_step_bytes(info, prec_bytes, nrhs=1):
     """Algorithmic bytes of one fused Chebyshev step on level 0: every cell
-    and face block once, the adjacency lists, and the vector streams
-    (gather d, x r/w, r r/w, D^-1, new d)."""
+    and face block once, the adjacency lists, and the vector streams of
+    every column (gather d, x r/w, r r/w, new d) plus D^-1 once."""
     b = info["b"]
     n, nf = info["n_cells"][0], info["n_faces"][0]
     N = n * b
     blocks = (n + nf) * b * b * prec_bytes
     adjacency = 4 * (n + 1) + 2 * 2 * 4 * nf
-    vectors = 7 * prec_bytes * N
+    vectors = (6 * nrhs + 1) * prec_bytes * N
     return blocks + adjacency + vectors
+
+
+def cheb_step_flops(info, nrhs):
+    """Multiply-adds of the block products of one Chebyshev step, as flops:
+    each stored block is used twice for a face (both orientations)."""
+    b = info["b"]
+    n, nf = info["n_cells"][0], info["n_faces"][0]
+    return 2.0 * (n + 2 * nf) * b * b * nrhs
 
 
 def profiled_traffic():
@@ -70,41 +87,60 @@ def profiled_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def _iapp(pr, t):
+def _iapp(pr, t, nrhs):
+    """Nodal applied current at time t: one column, or one column per
+    stimulus site (column-minor), or None when no stimulus is on."""
+    import numpy as np
     from workloads.configs import iapp_nodal
-    a = iapp_nodal(pr, t)
-    return a if a.any() else None
+    if nrhs == 1:
+        a = iapp_nodal(pr, t)
+        return a if a.any() else None
+    if t > pr["stim_tend"] + 1e-12:
+        return None
+    a = np.zeros((pr["N"], nrhs))
+    for c in range(nrhs):
+        a[np.repeat(pr["stim_masks"][c], pr["b"]), c] = pr["stim_amp"]
+    return a.ravel()
 
 
-def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None):
+def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None, nrhs=1, mfma=False,
+            fine_layout="auto"):
     import numpy as np
     import torch
     from paper_2602_16312_amd import api, problem
 
     t0 = time.perf_counter()
-    h, s = problem.build(pr, precision=precision)
+    h, s = problem.build(pr, precision=precision, max_rhs=nrhs, mfma=mfma,
+                         fine_layout=fine_layout)
     setup_s = time.perf_counter() - t0
     log(f"{precision}: setup {setup_s:.1f} s")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-    st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()),
-                   dev(pr["W0"].ravel()),
-                   torch.empty(pr["N"], dtype=torch.float64, device="cuda"))
-    # applied current per step, uploaded before the timed region
-    ia = {}
+    N, S = pr["N"], pr["S"]
+    U0 = np.repeat(pr["U0"][:, None], nrhs, axis=1).ravel()
+    W0 = np.repeat(pr["W0"].reshape(S, N)[:, :, None], nrhs, axis=2).ravel()
+    st = api.State(dev(U0), dev(U0), dev(W0), dev(W0),
+                   torch.empty(N * nrhs, dtype=torch.float64, device="cuda"))
+    step = api.time_step if nrhs == 1 else api.time_step_multi
+    # applied current per step, uploaded before the timed region (identical
+    # vectors share one device copy)
+    ia, cache = {}, {}
     for k in range(1, warmup + 2 * steps + 1):
-        a = _iapp(pr, k * pr["dt"])
-        ia[k] = None if a is None else dev(a)
+        a = _iapp(pr, k * pr["dt"], nrhs)
+        key = None if a is None else hash(a.tobytes())
+        if key not in cache:
+            cache[key] = None if a is None else dev(a)
+        ia[k] = cache[key]
     k = 0
     for _ in range(warmup):
         k += 1
-        api.time_step(s, st, k * pr["dt"], iapp=ia[k], tol=tol)
+        step(s, st, k * pr["dt"], iapp=ia[k], tol=tol)
     torch.cuda.synchronize()
     its = []
     t0 = time.perf_counter()
     for _ in range(steps):
         k += 1
-        r = api.time_step(s, st, k * pr["dt"], iapp=ia[k], tol=tol)
-        its.append(r["its"])
+        r = step(s, st, k * pr["dt"], iapp=ia[k], tol=tol)
+        its.append(r["its"] if nrhs == 1 else max(c["its"] for c in r))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     U = st.U.cpu().numpy()
@@ -117,11 +153,66 @@ def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None):
         api.profile_begin(s, profile_kind, 0)
         for _ in range(steps):
             k += 1
-            api.time_step(s, st, k * pr["dt"], iapp=ia[k], tol=tol)
+            step(s, st, k * pr["dt"], iapp=ia[k], tol=tol)
         n, ms = api.profile_end(s)
-        b2b = api.kernel_bench(s, profile_kind, 0, 200)
+        b2b = api.kernel_bench(s, profile_kind, 0, 200, nrhs=nrhs)
         prof = dict(launches=n, in_run_ms=ms / max(1, n), back_to_back_ms=b2b)
     return dict(wall=wall, its=its, setup_s=setup_s, info=s.info(), prof=prof, U=U)
+
+
+def run_adjoint(args):
+    """Times forward + backward of the sensor-misfit gradient (set-up included)
+    and compares loss and gradient with the stored FP64 oracle values."""
+    import numpy as np
+    import torch
+    from paper_2602_16312_amd.adjoint import sensor_misfit_loss
+    from workloads import make_problem
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "c5_adjoint.json")))
+    pr = make_problem("c5")
+    steps, tol = g["steps"], g["tol"]
+    targets = torch.tensor(np.array(g["targets"]), dtype=torch.float64, device="cuda")
+    runs = []
+    for k in range(args.warmup + args.steps):
+        s = torch.ones(pr["n_cells"], dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = sensor_misfit_loss(s, pr, targets, steps, tol=tol, checkpoint=10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if k >= args.warmup:
+            runs.append((t1 - t0, t2 - t1))
+        log(f"adjoint run {k}: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s")
+    grad = s.grad.cpu().numpy()
+    fwd = float(np.mean([r[0] for r in runs]))
+    bwd = float(np.mean([r[1] for r in runs]))
+    gn = g["grad_norm"]
+    rng = np.random.default_rng(g["dir_seed"])
+    dir_err = 0.0
+    for k in range(len(g["grad_dot_dirs"])):
+        d = rng.standard_normal(pr["n_cells"])
+        d /= np.linalg.norm(d)
+        dir_err = max(dir_err, abs(float(grad @ d) - g["grad_dot_dirs"][k]) / gn)
+    cells = np.array(g["sample_cells"])
+    out = {
+        "metric": METRIC, "value": pr["N"] * steps / (fwd + bwd), "unit": "DoFs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": (fwd + bwd) / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c5"], "n_dofs": int(pr["N"]), "time_steps": steps,
+                   "checkpoint_every": 10, "tol": tol,
+                   "value_is": "DoFs x time steps / (forward + backward seconds), set-up included"},
+        "forward_s": fwd, "backward_s": bwd,
+        "loss_rel_err_vs_oracle": abs(loss.item() - g["loss"]) / g["loss"],
+        "grad_rel_err_vs_oracle": {
+            "at_64_cells": float(np.abs(grad[cells] - np.array(g["grad_at_cells"])).max() / gn),
+            "projections_16_dirs": dir_err,
+            "norm": abs(float(np.linalg.norm(grad)) - gn) / gn},
+        "roofline": None,
+    }
+    print(json.dumps(out))
 
 
 def cpu_baseline(pr, tol, nsteps):
@@ -151,8 +242,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
-                    help="c2: 256x256 Q2 (default bench line); c3: 64^3 Q2 cube")
+    ap.add_argument("--workload", default="c2", choices=list(WORKLOADS),
+                    help="c2: 256x256 Q2 (default bench line); c3: 64^3 Q2 cube; "
+                         "c4: 1.0M-hex Q1 shell; c4x8: the shell with 8 simulations")
+    ap.add_argument("--fine-layout", default="auto", choices=["auto", "tile_ell", "axis_ell"],
+                    help="device storage of the fine operator (auto: each face block once)")
+    ap.add_argument("--no-mfma", action="store_true",
+                    help="c4x8: keep the 8-column Chebyshev step on the vector ALUs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -172,24 +268,36 @@ def main():
         print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "launches": 5}))
         return
 
+    if args.workload == "c5":
+        run_adjoint(args)
+        return
     from workloads import make_problem
-    pr = make_problem(args.workload)
-    res = run_gpu(pr, "mixed", args.steps, args.warmup, args.tol, profile_kind="cheb_step")
+    nrhs = 8 if args.workload == "c4x8" else 1
+    mfma = nrhs > 1 and not args.no_mfma
+    pr = make_problem("c4" if args.workload == "c4x8" else args.workload)
+    res = run_gpu(pr, "mixed", args.steps, args.warmup, args.tol, profile_kind="cheb_step",
+                  nrhs=nrhs, mfma=mfma, fine_layout=args.fine_layout)
     ms = res["wall"] / args.steps * 1e3
-    value = pr["N"] / (res["wall"] / args.steps)
+    value = pr["N"] * nrhs / (res["wall"] / args.steps)
     info = res["info"]
     prof = res["prof"]
     per_launch_s = prof["back_to_back_ms"] / 1e3
-    alg = cheb_step_bytes(info, 4)
+    alg = cheb_step_bytes(info, 4, nrhs)
     b_ = info["b"]
     achieved = alg / per_launch_s / 1e9
+    if nrhs == 1:
+        kname = f"k_cheb_step<float,{b_},{'axis' if info['fine_layout'] == 'axis_ell' else 'tile'}-ELL> (level 0)"
+    elif mfma:
+        kname = f"k_cheb_step_mfma8<{info['fine_layout']}> (level 0, 8 columns, v_mfma_f32_4x4x1f32)"
+    else:
+        kname = f"k_cheb_step_m<float,{b_},8,{info['fine_layout']}> (level 0, 8 columns)"
     out = {
         "metric": METRIC, "value": value, "unit": "DoFs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
-                   "n_dofs": int(pr["N"]), "cells_per_level": info["n_cells"],
+                   "n_dofs": int(pr["N"]), "rhs": nrhs, "cells_per_level": info["n_cells"],
                    "precision": "mixed: FP32 V-cycle, FP64 PCG and coarse solve",
                    "dt": pr["dt"], "tol": args.tol},
         "iters": _stats(res["its"]),
@@ -197,14 +305,20 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic() if args.workload == "c2" else None,
-                     "kernel": f"k_cheb_step<float,{b_}> (level 0)",
+                     "kernel": kname,
                      "alg_bytes_per_launch": alg, "avg_launch_us": per_launch_s * 1e6,
                      "avg_launch_us_in_run": prof["in_run_ms"] * 1e3,
                      "launches_in_run": prof["launches"]},
     }
+    if nrhs > 1:
+        fl = cheb_step_flops(info, nrhs) / per_launch_s / 1e12
+        out["roofline"]["mfma" if mfma else "valu"] = {
+            "achieved_tflops": fl, "peak_tflops": MFMA_F32_PEAK_TFLOPS,
+            "utilisation": fl / MFMA_F32_PEAK_TFLOPS}
     if not args.no_fp64:
-        r64 = run_gpu(pr, "fp64", args.steps, args.warmup, args.tol)
-        out["fp64"] = {"value": pr["N"] / (r64["wall"] / args.steps),
+        r64 = run_gpu(pr, "fp64", args.steps, args.warmup, args.tol, nrhs=nrhs,
+                      fine_layout=args.fine_layout)
+        out["fp64"] = {"value": pr["N"] * nrhs / (r64["wall"] / args.steps),
                        "ms_per_step": r64["wall"] / args.steps * 1e3,
                        "iters": _stats(r64["its"])}
         out["mixed_vs_fp64_rel_diff"] = float(np.abs(res["U"] - r64["U"]).max()

@@ -137,7 +137,12 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * max_rhs (0 or 1: single right-hand side; DGMG_MULTI_RHS: also size every
  * work vector for that many columns, enabling the *_multi calls).  mfma = 1
  * runs the FP32 Chebyshev step of 8-column solves with 8x8 blocks (3D Q1)
- * on the matrix cores (v_mfma_f32_4x4x1f32); 0 keeps it on the vector ALUs. */
+ * on the matrix cores (v_mfma_f32_4x4x1f32); 0 keeps it on the vector ALUs.
+ * fine_layout selects the device storage of the fine operator: AUTO and
+ * AXIS_ELL store every face block once (per cell: its block and the blocks
+ * of its upper faces along each axis; lower faces are read transposed from
+ * the neighbour), TILE_ELL stores each face block twice, oriented for both
+ * cells, as on the agglomerated levels. */
 typedef struct {
     int32_t cheb_degree;
     int32_t cheb_sweeps;
@@ -150,7 +155,10 @@ typedef struct {
     int32_t adjoint;
     int32_t max_rhs;
     int32_t mfma;
+    int32_t fine_layout;
 } dgmg_mg_opts;
+
+enum { DGMG_LAYOUT_AUTO = 0, DGMG_LAYOUT_TILE_ELL = 1, DGMG_LAYOUT_AXIS_ELL = 2 };
 
 /* Number of columns of the multi-right-hand-side calls. */
 enum { DGMG_MULTI_RHS = 8 };
@@ -176,6 +184,7 @@ typedef struct {
     double op_complexity;
     double t_assembly, t_hierarchy, t_transfer, t_galerkin, t_smoother, t_coarse, t_upload;
     int64_t device_bytes;
+    int32_t fine_layout;   /* DGMG_LAYOUT_TILE_ELL or DGMG_LAYOUT_AXIS_ELL as used */
 } dgmg_solver_info;
 int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info);
 

@@ -54,7 +54,7 @@ class MGOpts(C.Structure):
                 ("smooth_range", C.c_double), ("lam_override", dp),
                 ("precision", C.c_int32), ("device_setup", C.c_int32),
                 ("adjoint", C.c_int32), ("max_rhs", C.c_int32),
-                ("mfma", C.c_int32)]
+                ("mfma", C.c_int32), ("fine_layout", C.c_int32)]
 
 
 class SolverInfo(C.Structure):
@@ -70,7 +70,8 @@ class SolverInfo(C.Structure):
                 ("t_assembly", C.c_double), ("t_hierarchy", C.c_double),
                 ("t_transfer", C.c_double), ("t_galerkin", C.c_double),
                 ("t_smoother", C.c_double), ("t_coarse", C.c_double),
-                ("t_upload", C.c_double), ("device_bytes", C.c_int64)]
+                ("t_upload", C.c_double), ("device_bytes", C.c_int64),
+                ("fine_layout", C.c_int32)]
 
 
 class PCGOpts(C.Structure):

@@ -13,6 +13,7 @@ from . import _ffi as F
 MODELS = {"fhn": 0, "ap": 1, "bo": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 TOL_MODES = {"rel_r0": 0, "rel_b": 1, "abs": 2}
+LAYOUTS = {"auto": 0, "tile_ell": 1, "axis_ell": 2}
 
 
 def _dptr(a):
@@ -118,7 +119,8 @@ class Solver:
                                  transfer=i.t_transfer, galerkin=i.t_galerkin,
                                  smoother=i.t_smoother, coarse=i.t_coarse,
                                  upload=i.t_upload),
-                    device_bytes=i.device_bytes)
+                    device_bytes=i.device_bytes,
+                    fine_layout={1: "tile_ell", 2: "axis_ell"}.get(i.fine_layout, "none"))
 
     def export_level(self, level):
         """Host copies of a level's FP64 operator and transfer blocks."""
@@ -148,7 +150,7 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
                  bdf=2, cell_scale=None, precision="fp64", cheb_degree=3,
                  cheb_sweeps=3, lanczos_steps=20, lam_safety=1.2,
                  smooth_range=20.0, lam_override=None, device_setup=True, adjoint=False,
-                 max_rhs=1, mfma=False):
+                 max_rhs=1, mfma=False, fine_layout="auto"):
     """dgmg_setup_levels: assembly, Galerkin hierarchy, smoother, coarse factor."""
     d = F.Disc(p, 0 if penalty[0] == "paper" else 1,
                float(penalty[1]) if len(penalty) > 1 else 0.0)
@@ -166,7 +168,7 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
         keep.append(lam)
     mg = F.MGOpts(cheb_degree, cheb_sweeps, lanczos_steps, lam_safety, smooth_range,
                   lo, PRECISIONS[precision], 1 if device_setup else 0, 1 if adjoint else 0,
-                  int(max_rhs), 1 if mfma else 0)
+                  int(max_rhs), 1 if mfma else 0, LAYOUTS[fine_layout])
     s = C.c_void_p()
     F.check(F.lib().dgmg_setup_levels(hier.handle, C.byref(d), C.byref(ph), C.byref(mg),
                                       C.byref(s)))

@@ -15,6 +15,16 @@
 //    stored twice (once per side): reading a single stored copy transposed
 //    from the other side costs more in cache-line traffic than the second
 //    copy costs in bytes on this hardware;
+//  * "axis-ELL" (fine level of a conforming quad/hex mesh, where every cell
+//    has at most one face neighbour per axis direction): tile t holds 1 + d
+//    slots at a fixed stride -- the cell blocks and, per axis a, the block
+//    U_a(c) = A[c, up_a(c)] of the face on the cell's upper a-side (zero if
+//    none), interleaved as above.  Each face block is stored once.  The
+//    lower a-face of cell c is U_a(lo_a(c)) read transposed: thread (c, i)
+//    reads column i of that block, B contiguous values at
+//    ((tile0*(1+d) + 1 + a)*B + i)*TR + lc0*B; consecutive cells have
+//    consecutive lower neighbours, so a wave's reads stay within a few
+//    cache lines per column plane;
 //  * prolongation blocks use the same interleaving with one slot per tile.
 // Workgroups are mapped XCD-aware: the 8 XCDs receive consecutive workgroup
 // ids round-robin, so tile = (id % 8) * per + id / 8 gives each XCD a
@@ -38,12 +48,20 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 
 template <typename T>
 struct LevelArgs {
-    const T* __restrict__ vals;            // tile-ELL blocks
-    const int32_t* __restrict__ slot_ptr;  // ntiles + 1
-    const int32_t* __restrict__ snb;       // (slot, cell in tile) -> column cell
+    const T* __restrict__ vals;            // tile-ELL or axis-ELL blocks
+    const int32_t* __restrict__ slot_ptr;  // tile-ELL: ntiles + 1
+    const int32_t* __restrict__ snb;       // tile-ELL: (slot, cell in tile) -> column cell
     const T* __restrict__ dinv;
     int32_t n;
+    const int32_t* __restrict__ up;        // axis-ELL: [d][n] upper neighbour (itself if none)
+    const int32_t* __restrict__ lo;        // axis-ELL: [d][n] lower neighbour (-1 if none)
 };
+
+// spatial dimension of a block size (Q1..Q3 in 2D: 4, 9, 16; in 3D: 8, 27, 64)
+template <int B>
+constexpr int dim_of() {
+    return (B == 8 || B == 27 || B == 64) ? 3 : 2;
+}
 
 template <typename T, int B>
 struct Tile {
@@ -108,6 +126,67 @@ __device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int 
     return acc;
 }
 
+// The same row product on the axis-ELL layout: the 1 + d own slots (cell
+// block, upper faces) in groups as above, then each lower face as the
+// transposed column of the neighbour's stored block.
+template <typename T, int B, bool VB>
+__device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int lc, int cell,
+                                          const T* __restrict__ va, const T* __restrict__ vb) {
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>(), NS = 1 + D;
+    constexpr int G = slot_group<B>() < NS ? slot_group<B>() : NS;
+    const int i = threadIdx.x - lc * B;
+    const T* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + threadIdx.x;
+    T acc = 0;
+#pragma unroll
+    for (int g = 0; g < NS; g += G) {
+        int nbq[G];
+        T a[G][B], v[G][B];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int sl = min(g + q, NS - 1);
+            nbq[q] = sl == 0 ? cell : L.up[(size_t)(sl - 1) * L.n + cell];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const T* As = A + (size_t)min(g + q, NS - 1) * B * TR;
+#pragma unroll
+            for (int j = 0; j < B; ++j) a[q][j] = As[(size_t)j * TR];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) gather_group<T, B, VB>(va, vb, nbq[q], v[q]);
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if (g + q < NS) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc += a[q][j] * v[q][j];
+            }
+    }
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        const int c0 = L.lo[(size_t)ax * L.n + cell];
+        if (c0 >= 0) {
+            const int t0 = c0 / TC, l0 = c0 - t0 * TC;
+            const T* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + i) * TR + (size_t)l0 * B;
+            T a[B], v[B];
+#pragma unroll
+            for (int r = 0; r < B; ++r) a[r] = At[r];
+            gather_group<T, B, VB>(va, vb, c0, v);
+#pragma unroll
+            for (int r = 0; r < B; ++r) acc += a[r] * v[r];
+        }
+    }
+    return acc;
+}
+
+template <typename T, int B, bool VB, bool AX>
+__device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int tile, int lc, int cell,
+                                       const T* __restrict__ va, const T* __restrict__ vb) {
+    if constexpr (AX)
+        return ax_row_apply<T, B, VB>(L, tile, lc, cell, va, vb);
+    else
+        return ell_row_apply<T, B, VB>(L, tile, lc, va, vb);
+}
+
 // Workgroup sum of a double into partial[blockIdx.x] (deterministic order).
 __device__ __forceinline__ void wg_sum_store(double v, double* partial) {
     __shared__ double red[kWG / 64];
@@ -132,14 +211,14 @@ __device__ __forceinline__ void wg_sum_store(double v, double* partial) {
     const int t = cell * B + (threadIdx.x - lc * B);
 
 // y = A va; optional partial of dot(w, y).
-template <typename T, int B>
+template <typename T, int B, bool AX>
 __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restrict__ va,
                                                T* __restrict__ y,
                                                const T* __restrict__ w, double* __restrict__ partial) {
     DGMG_TILE_THREAD(T, B)
     double contrib = 0.0;
     if (active) {
-        const T a = ell_row_apply<T, B, false>(L, tile, lc, va, nullptr);
+        const T a = row_apply<T, B, false, AX>(L, tile, lc, cell, va, nullptr);
         y[t] = a;
         if (w) contrib = (double)w[t] * (double)a;
     }
@@ -150,7 +229,7 @@ __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restri
 // xout = va + vb, partial of ||r||^2, and restriction partials
 // rp[cell, j] = sum_i P_cell(i, j) r[cell, i] (P in tile-interleaved layout)
 // for the coarse correction.  r may be null when only rp is wanted.
-template <typename T, int B, bool VB>
+template <typename T, int B, bool VB, bool AX>
 __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __restrict__ va,
                                                   const T* __restrict__ vb, const T* __restrict__ rhs,
                                                   T* __restrict__ r, T* __restrict__ d, T c1,
@@ -160,7 +239,7 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
     double contrib = 0.0;
     T rr = 0;
     if (active) {
-        const T a = ell_row_apply<T, B, VB>(L, tile, lc, va, vb);
+        const T a = row_apply<T, B, VB, AX>(L, tile, lc, cell, va, vb);
         rr = rhs[t] - a;
         if (r) r[t] = rr;
         if (d) d[t] = L.dinv[t] * rr * c1;
@@ -188,13 +267,13 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
 
 // One inner Chebyshev step (gather vector d):
 //   x += d (x = d when assign), r -= A d, dn = cd * d + cr * dinv * r.
-template <typename T, int B>
+template <typename T, int B, bool AX>
 __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __restrict__ d,
                                                    T* __restrict__ x, T* __restrict__ r,
                                                    T* __restrict__ dn, T cd, T cr, int assign) {
     DGMG_TILE_THREAD(T, B)
     if (!active) return;
-    const T a = ell_row_apply<T, B, false>(L, tile, lc, d, nullptr);
+    const T a = row_apply<T, B, false, AX>(L, tile, lc, cell, d, nullptr);
     const T dt = d[t];
     x[t] = assign ? dt : x[t] + dt;
     const T rr = r[t] - a;
@@ -270,10 +349,8 @@ __global__ __launch_bounds__(kWG) void k_prolong_add(int32_t n, const int32_t* _
 
 // ------------------------------------------------------------ coarse
 // x = Ainv r with the dense symmetric FP64 coarse inverse (row-major): each
-// wave owns kCoarseRowsPerWave rows and reads them with coalesced loads; r is
-// staged in LDS chunk by chunk (converted to FP64) and shared by the
-// workgroup's 4 waves.
-constexpr int kCoarseRowsPerWave = 2;
+// wave owns one row and reads it with coalesced loads; r is staged in LDS
+// chunk by chunk (converted to FP64) and shared by the workgroup's 4 waves.
 constexpr int kCoarseChunk = 4096;
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(kWG) void k_coarse_solve(int32_t n, const double* __restrict__ Ainv,
@@ -281,34 +358,31 @@ __global__ __launch_bounds__(kWG) void k_coarse_solve(int32_t n, const double* _
                                                       Tout* __restrict__ x) {
     __shared__ double rs[kCoarseChunk];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row0 = (blockIdx.x * (kWG / 64) + wave) * kCoarseRowsPerWave;
-    double acc[kCoarseRowsPerWave];
-#pragma unroll
-    for (int k = 0; k < kCoarseRowsPerWave; ++k) acc[k] = 0.0;
+    const int row = blockIdx.x * (kWG / 64) + wave;
+    // four independent partial sums per lane keep four loads in flight;
+    // column c goes to sum (c / 64) % 4 (chunks are multiples of 256)
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c0 = 0; c0 < n; c0 += kCoarseChunk) {
         const int len = min(kCoarseChunk, n - c0);
         __syncthreads();
         for (int k = threadIdx.x; k < len; k += kWG) rs[k] = (double)r[c0 + k];
         __syncthreads();
+        if (row < n) {
+            const double* a = Ainv + (size_t)row * n + c0;
+            int c = lane;
+            for (; c + 192 < len; c += 256) {
 #pragma unroll
-        for (int k = 0; k < kCoarseRowsPerWave; ++k) {
-            const int row = row0 + k;
-            if (row < n) {
-                const double* a = Ainv + (size_t)row * n + c0;
-                double s = 0.0;
-                for (int c = lane; c < len; c += 64) s += a[c] * rs[c];
-                acc[k] += s;
+                for (int u = 0; u < 4; ++u) s[u] += a[c + 64 * u] * rs[c + 64 * u];
             }
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                if (c + 64 * u < len) s[u] += a[c + 64 * u] * rs[c + 64 * u];
         }
     }
+    double v = (s[0] + s[1]) + (s[2] + s[3]);
 #pragma unroll
-    for (int k = 0; k < kCoarseRowsPerWave; ++k) {
-        double s = acc[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        const int row = row0 + k;
-        if (lane == 0 && row < n) x[row] = (Tout)s;
-    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0 && row < n) x[row] = (Tout)v;
 }
 
 // ------------------------------------------------------------ vectors

@@ -41,6 +41,53 @@ __device__ __forceinline__ void ell_row_apply_m(const LevelArgs<T>& L, int tile,
     }
 }
 
+// Axis-ELL variant: own slots, then the lower faces read transposed.
+template <typename T, int B, int R, bool VB>
+__device__ __forceinline__ void ax_row_apply_m(const LevelArgs<T>& L, int tile, int lc, int cell,
+                                               const T* __restrict__ va, const T* __restrict__ vb,
+                                               T* acc) {
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>(), NS = 1 + D;
+    const int i = threadIdx.x - lc * B;
+    const T* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + threadIdx.x;
+    auto accumulate = [&](const T* a, int nb) {
+        const T* x = va + (size_t)nb * B * R;
+        const T* y = VB ? vb + (size_t)nb * B * R : nullptr;
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T v = VB ? x[j * R + r] + y[j * R + r] : x[j * R + r];
+                acc[r] += a[j] * v;
+            }
+    };
+    for (int s = 0; s < NS; ++s) {
+        const int nb = s == 0 ? cell : L.up[(size_t)(s - 1) * L.n + cell];
+        T a[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+        accumulate(a, nb);
+    }
+    for (int ax = 0; ax < D; ++ax) {
+        const int c0 = L.lo[(size_t)ax * L.n + cell];
+        if (c0 < 0) continue;
+        const int t0 = c0 / TC, l0 = c0 - t0 * TC;
+        const T* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + i) * TR + (size_t)l0 * B;
+        T a[B];
+#pragma unroll
+        for (int r = 0; r < B; ++r) a[r] = At[r];
+        accumulate(a, c0);
+    }
+}
+
+template <typename T, int B, int R, bool VB, bool AX>
+__device__ __forceinline__ void row_apply_m(const LevelArgs<T>& L, int tile, int lc, int cell,
+                                            const T* __restrict__ va, const T* __restrict__ vb, T* acc) {
+    if constexpr (AX)
+        ax_row_apply_m<T, B, R, VB>(L, tile, lc, cell, va, vb, acc);
+    else
+        ell_row_apply_m<T, B, R, VB>(L, tile, lc, va, vb, acc);
+}
+
 // Workgroup sums of R doubles into partial[blockIdx.x * R + r].
 template <int R>
 __device__ __forceinline__ void wg_sum_store_m(const double* v, double* partial) {
@@ -64,7 +111,7 @@ __device__ __forceinline__ void wg_sum_store_m(const double* v, double* partial)
 }
 
 // y = A va; optional per-column partial of dot(w, y).
-template <typename T, int B, int R>
+template <typename T, int B, int R, bool AX>
 __global__ __launch_bounds__(kWG) void k_apply_m(LevelArgs<T> L, const T* __restrict__ va,
                                                  T* __restrict__ y, const T* __restrict__ w,
                                                  double* __restrict__ partial) {
@@ -76,7 +123,7 @@ __global__ __launch_bounds__(kWG) void k_apply_m(LevelArgs<T> L, const T* __rest
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0;
-        ell_row_apply_m<T, B, R, false>(L, tile, lc, va, nullptr, acc);
+        row_apply_m<T, B, R, false, AX>(L, tile, lc, cell, va, nullptr, acc);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             y[(size_t)t * R + r] = acc[r];
@@ -89,7 +136,7 @@ __global__ __launch_bounds__(kWG) void k_apply_m(LevelArgs<T> L, const T* __rest
 // Residual per column r = rhs - A (va + vb) with the same optional epilogues
 // as the single-column kernel (d, xout, per-column ||r||^2, restriction
 // partials).
-template <typename T, int B, int R, bool VB>
+template <typename T, int B, int R, bool VB, bool AX>
 __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __restrict__ va,
                                                     const T* __restrict__ vb, const T* __restrict__ rhs,
                                                     T* __restrict__ r, T* __restrict__ d, T c1,
@@ -107,7 +154,7 @@ __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __r
         T acc[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) acc[q] = 0;
-        ell_row_apply_m<T, B, R, VB>(L, tile, lc, va, vb, acc);
+        row_apply_m<T, B, R, VB, AX>(L, tile, lc, cell, va, vb, acc);
         const T di = L.dinv[t];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -145,7 +192,7 @@ __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __r
 }
 
 // One inner Chebyshev step on R columns (VALU).
-template <typename T, int B, int R>
+template <typename T, int B, int R, bool AX>
 __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __restrict__ d,
                                                      T* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ dn, T cd, T cr, int assign) {
@@ -154,7 +201,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __
     T acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = 0;
-    ell_row_apply_m<T, B, R, false>(L, tile, lc, d, nullptr, acc);
+    row_apply_m<T, B, R, false, AX>(L, tile, lc, cell, d, nullptr, acc);
     const T di = L.dinv[t];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -169,11 +216,14 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __
 
 // The same Chebyshev step for FP32 8x8 blocks and 8 columns on the matrix
 // cores: per wave 8 cells x 8 rows; v_mfma_f32_4x4x1f32 (16 blocks of 4x4)
-// with block = (cell, half of the rows) takes the tile-ELL value of the
+// with block = (cell, half of the rows) takes the stored value of the
 // lane's (cell, row) as its A operand (lane 4*blk + i supplies row i) and
 // the gathered column values as B (lane 4*blk + j supplies column j of one
 // half of the right-hand sides).  Lane 4*blk + j then holds rows
-// 4*half + 0..3 of right-hand side 4*rh + j.
+// 4*half + 0..3 of right-hand side 4*rh + j.  On the axis-ELL layout the
+// lower faces contribute the transposed stored block (A operand = column of
+// the neighbour's block, zero where the cell has no lower neighbour).
+template <bool AX>
 __global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, const float* __restrict__ d,
                                                          float* __restrict__ x, float* __restrict__ r,
                                                          float* __restrict__ dn, float cd, float cr,
@@ -181,19 +231,15 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, con
     constexpr int B = 8, R = 8, TC = Tile<float, 8>::TC, TR = Tile<float, 8>::TR;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
-    const int lc = threadIdx.x / B;                 // cell in tile of the A operand lane
+    const int lc = threadIdx.x / B;                 // cell in tile of this lane
+    const int row = threadIdx.x - lc * B;
     const int cell0 = tile * TC;
-    const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;
-    const float* __restrict__ A = L.vals + (size_t)s0 * B * TR + threadIdx.x;
-    const int32_t* __restrict__ nbp = L.snb + (size_t)s0 * TC + lc;
+    const int mycell = min(cell0 + lc, L.n - 1);    // padding lanes reuse a valid cell
     const int jj = lane & 3;                        // B operand / result column in block
     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    for (int s = 0; s < ns; ++s) {
-        const int nb = nbp[(size_t)s * TC];
-        float a[B], b0[B], b1[B];
-#pragma unroll
-        for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+    auto mma = [&](const float* a, int nb) {
         const float* xv = d + (size_t)nb * B * R;
+        float b0[B], b1[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             b0[j] = xv[j * R + jj];
@@ -203,6 +249,38 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, con
         for (int j = 0; j < B; ++j) {
             acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[j], b0[j], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[j], b1[j], acc1, 0, 0, 0);
+        }
+    };
+    if constexpr (AX) {
+        constexpr int NS = 4;
+        const float* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + threadIdx.x;
+        for (int s = 0; s < NS; ++s) {
+            const int nb = s == 0 ? mycell : L.up[(size_t)(s - 1) * L.n + mycell];
+            float a[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+            mma(a, nb);
+        }
+        for (int ax = 0; ax < 3; ++ax) {
+            const int c0 = L.lo[(size_t)ax * L.n + mycell];
+            const int cs = c0 >= 0 ? c0 : mycell;
+            const int t0 = cs / TC, l0 = cs - t0 * TC;
+            const float* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + row) * TR + (size_t)l0 * B;
+            float a[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) a[q] = c0 >= 0 ? At[q] : 0.f;
+            mma(a, cs);
+        }
+    } else {
+        const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;
+        const float* __restrict__ A = L.vals + (size_t)s0 * B * TR + threadIdx.x;
+        const int32_t* __restrict__ nbp = L.snb + (size_t)s0 * TC + lc;
+        for (int s = 0; s < ns; ++s) {
+            const int nb = nbp[(size_t)s * TC];
+            float a[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+            mma(a, nb);
         }
     }
     // lane (4*blk + jj) holds rows 4*(blk&1) + 0..3 of cell (threadIdx.x/64)*8 + blk/2
@@ -279,7 +357,8 @@ __global__ __launch_bounds__(kWG) void k_prolong_add_m(int32_t n, const int32_t*
     for (int q = 0; q < R; ++q) x[(size_t)t * R + q] += acc[q];
 }
 
-// X = Ainv Rhs for R columns (row-per-wave, right-hand sides staged in LDS).
+// X = Ainv Rhs for R columns (row-per-wave, right-hand sides staged in LDS),
+// each column summed in the single-column kernel's order.
 constexpr int kCoarseChunkM = 512;
 template <typename Tin, typename Tout, int R>
 __global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const double* __restrict__ Ainv,
@@ -287,40 +366,45 @@ __global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const double*
                                                         Tout* __restrict__ x) {
     __shared__ double rs[kCoarseChunkM * R];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row0 = (blockIdx.x * (kWG / 64) + wave) * kCoarseRowsPerWave;
-    double acc[kCoarseRowsPerWave][R];
+    const int row = blockIdx.x * (kWG / 64) + wave;
+    double s[4][R];
 #pragma unroll
-    for (int k = 0; k < kCoarseRowsPerWave; ++k)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int q = 0; q < R; ++q) acc[k][q] = 0.0;
+        for (int q = 0; q < R; ++q) s[u][q] = 0.0;
     for (int c0 = 0; c0 < n; c0 += kCoarseChunkM) {
         const int len = min(kCoarseChunkM, n - c0);
         __syncthreads();
         for (int k = threadIdx.x; k < len * R; k += kWG) rs[k] = (double)rin[(size_t)c0 * R + k];
         __syncthreads();
+        if (row < n) {
+            const double* a = Ainv + (size_t)row * n + c0;
+            int c = lane;
+            for (; c + 192 < len; c += 256) {
 #pragma unroll
-        for (int k = 0; k < kCoarseRowsPerWave; ++k) {
-            const int row = row0 + k;
-            if (row < n) {
-                const double* a = Ainv + (size_t)row * n + c0;
-                for (int c = lane; c < len; c += 64) {
-                    const double av = a[c];
+                for (int u = 0; u < 4; ++u) {
+                    const double av = a[c + 64 * u];
 #pragma unroll
-                    for (int q = 0; q < R; ++q) acc[k][q] += av * rs[c * R + q];
+                    for (int q = 0; q < R; ++q) s[u][q] += av * rs[(c + 64 * u) * R + q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int cc = c + 64 * u;
+                if (cc < len) {
+                    const double av = a[cc];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) s[u][q] += av * rs[cc * R + q];
                 }
             }
         }
     }
 #pragma unroll
-    for (int k = 0; k < kCoarseRowsPerWave; ++k) {
-        const int row = row0 + k;
+    for (int q = 0; q < R; ++q) {
+        double v = (s[0][q] + s[1][q]) + (s[2][q] + s[3][q]);
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            double s = acc[k][q];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-            if (lane == 0 && row < n) x[(size_t)row * R + q] = (Tout)s;
-        }
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0 && row < n) x[(size_t)row * R + q] = (Tout)v;
     }
 }
 

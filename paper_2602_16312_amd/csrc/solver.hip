@@ -44,6 +44,10 @@ void set_last_error(const std::string& m) { g_last_error = m; }
             fail(DGMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
     } while (0)
 
+#define DISPATCH_AX(axval, ...)                                                        \
+    if (axval) { constexpr bool AXV = true; __VA_ARGS__; }                             \
+    else { constexpr bool AXV = false; __VA_ARGS__; }
+
 #define DISPATCH_B(bval, ...)                                                          \
     switch (bval) {                                                                    \
         case 4: { constexpr int BV = 4; __VA_ARGS__; } break;                          \
@@ -68,6 +72,8 @@ struct DevLevel {
     int32_t n = 0, nf = 0;
     int64_t N = 0;
     int32_t *slot_ptr = nullptr, *snb = nullptr;          // tile-ELL structure
+    bool ax = false;                                       // axis-ELL layout instead
+    int32_t *up = nullptr, *lo = nullptr;                  // axis-ELL neighbours
     int32_t *child_ptr = nullptr, *child_list = nullptr;  // children on level l-1
     int32_t* parent = nullptr;                             // parent on level l+1
     double *vals64 = nullptr, *dinv64 = nullptr, *P64 = nullptr;
@@ -86,6 +92,8 @@ struct dgmg_solver {
     int dim = 0, p = 0, b = 0, L = 0, prec = 0, S = 1, bdf = 2;
     int cheb_k = 3, cheb_s = 3;
     int max_rhs = 1, mfma = 0;
+    int fine_layout = 0;              // DGMG_LAYOUT_*
+    std::vector<int> axis0;           // axis of every fine face (face order of ops[0])
     int64_t N = 0;
     bool on_device = false;
     std::vector<DevLevel> lv;
@@ -177,11 +185,11 @@ template <typename T>
 static LevelArgs<T> largs(const DevLevel& L);
 template <>
 LevelArgs<double> largs<double>(const DevLevel& L) {
-    return {L.vals64, L.slot_ptr, L.snb, L.dinv64, L.n};
+    return {L.vals64, L.slot_ptr, L.snb, L.dinv64, L.n, L.up, L.lo};
 }
 template <>
 LevelArgs<float> largs<float>(const DevLevel& L) {
-    return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n};
+    return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n, L.up, L.lo};
 }
 template <typename T>
 static const T* Pof(const DevLevel& L);
@@ -235,61 +243,71 @@ template <typename T, int R = 1>
 static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, const T* w,
                          double* partial, hipStream_t st) {
     ProfScope ps(s, PK_APPLY, level_index(s, L), st);
-    if constexpr (R == 1) {
-        DISPATCH_B(s->b, k_apply<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w, partial));
-    } else {
-        DISPATCH_B(s->b, k_apply_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w,
-                                                                                   partial));
-    }
+    DISPATCH_AX(L.ax, {
+        if constexpr (R == 1) {
+            DISPATCH_B(s->b, k_apply<T, BV, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w,
+                                                                                        partial));
+        } else {
+            DISPATCH_B(s->b, k_apply_m<T, BV, R, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y,
+                                                                                            w, partial));
+        }
+    });
 }
 template <typename T, int R = 1>
 static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, const T* rhs,
                             T* r, T* d, T c1, T* xout, double* partial, hipStream_t st,
                             const T* P = nullptr, T* rp = nullptr) {
     ProfScope ps(s, PK_RESIDUAL, level_index(s, L), st);
-    if constexpr (R == 1) {
-        if (vb) {
-            DISPATCH_B(s->b, k_residual<T, BV, true><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+    DISPATCH_AX(L.ax, {
+        if constexpr (R == 1) {
+            if (vb) {
+                DISPATCH_B(s->b, k_residual<T, BV, true, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+            } else {
+                DISPATCH_B(s->b, k_residual<T, BV, false, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+            }
         } else {
-            DISPATCH_B(s->b, k_residual<T, BV, false><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+            if (vb) {
+                DISPATCH_B(s->b, k_residual_m<T, BV, R, true, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+            } else {
+                DISPATCH_B(s->b, k_residual_m<T, BV, R, false, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+            }
         }
-    } else {
-        if (vb) {
-            DISPATCH_B(s->b, k_residual_m<T, BV, R, true><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
-        } else {
-            DISPATCH_B(s->b, k_residual_m<T, BV, R, false><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                 largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
-        }
-    }
+    });
 }
 template <typename T, int R = 1>
 static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* r, T* dn, T cd, T cr,
                         int assign, hipStream_t st) {
     ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
-    if constexpr (R == 1) {
-        DISPATCH_B(s->b, k_cheb_step<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r, dn, cd,
-                                                                                  cr, assign));
-    } else {
-        if constexpr (std::is_same<T, float>::value && R == 8) {
-            if (s->mfma && s->b == 8) {
-                k_cheb_step_mfma8<<<tiles_for<float, 8>(L), kWG, 0, st>>>(largs<float>(L), d, x, r, dn, cd, cr,
-                                                                         assign);
-                return;
+    DISPATCH_AX(L.ax, {
+        if constexpr (R == 1) {
+            DISPATCH_B(s->b, k_cheb_step<T, BV, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r,
+                                                                                           dn, cd, cr, assign));
+        } else {
+            bool done = false;
+            if constexpr (std::is_same<T, float>::value && R == 8) {
+                if (s->mfma && s->b == 8) {
+                    k_cheb_step_mfma8<AXV><<<tiles_for<float, 8>(L), kWG, 0, st>>>(largs<float>(L), d, x, r, dn,
+                                                                                  cd, cr, assign);
+                    done = true;
+                }
+            }
+            if (!done) {
+                DISPATCH_B(s->b, k_cheb_step_m<T, BV, R, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                     largs<T>(L), d, x, r, dn, cd, cr, assign));
             }
         }
-        DISPATCH_B(s->b, k_cheb_step_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r, dn,
-                                                                                       cd, cr, assign));
-    }
+    });
 }
 
 template <typename T, int R = 1>
 static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
     const int n = (int)s->nc_dofs;
     ProfScope ps(s, PK_COARSE, s->L - 1, st);
-    const int rows_per_wg = (kWG / 64) * kCoarseRowsPerWave;
+    const int rows_per_wg = kWG / 64;   // one row per wave
     if constexpr (R == 1)
         k_coarse_solve<T, T><<<(n + rows_per_wg - 1) / rows_per_wg, kWG, 0, st>>>(n, s->Ainv, rc, xc);
     else
@@ -637,6 +655,46 @@ static TileEll build_tile_ell(const BlockOp& A) {
     return E;
 }
 
+// Axis-ELL layout of the fine operator (see kernels.hpp): per tile of TC
+// cells, slot 0 the cell blocks and slot 1 + a the block A[c, up_a(c)] of the
+// face on the upper a-side of each cell; up/lo map every cell to its upper /
+// lower neighbour along each axis.  Faces are (plus = lower cell, minus =
+// upper cell, axis) as found on the conforming mesh.
+struct AxisEll {
+    std::vector<int32_t> up, lo;
+    std::vector<double> vals;
+};
+static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, int d) {
+    const int b = A.b, TC = kWG / b, TR = TC * b, NS = 1 + d;
+    const int64_t n = A.n, ntiles = (n + TC - 1) / TC;
+    if ((int64_t)axis.size() != A.nf) fail(DGMG_EINVAL, "face axis list does not match the operator");
+    AxisEll E;
+    E.vals.assign((size_t)ntiles * NS * b * TR, 0.0);
+    E.up.resize((size_t)d * n);
+    E.lo.assign((size_t)d * n, -1);
+    for (int a = 0; a < d; ++a)
+        for (int64_t c = 0; c < n; ++c) E.up[(size_t)a * n + c] = (int32_t)c;
+    auto put = [&](int64_t c, int slot, const double* blk) {
+        const int64_t t = c / TC;
+        const int lc = (int)(c - t * TC);
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j)
+                E.vals[(((size_t)t * NS + slot) * b + j) * TR + (size_t)lc * b + i] = blk[(size_t)i * b + j];
+    };
+    for (int64_t c = 0; c < n; ++c) put(c, 0, &A.diag[(size_t)c * b * b]);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        const int64_t p = A.fc[2 * f], m = A.fc[2 * f + 1];
+        const int a = axis[f];
+        if (a < 0 || a >= d) fail(DGMG_EINVAL, "bad face axis");
+        if (E.up[(size_t)a * n + p] != p || E.lo[(size_t)a * n + m] != -1)
+            fail(DGMG_EUNSUPPORTED, "two faces on one side of a cell");
+        E.up[(size_t)a * n + p] = (int32_t)m;
+        E.lo[(size_t)a * n + m] = (int32_t)p;
+        put(p, 1 + a, &A.fblk[(size_t)f * b * b]);
+    }
+    return E;
+}
+
 // prolongation blocks (row-major per fine entity) in tile-interleaved layout
 template <typename T>
 static std::vector<T> interleave_P(const std::vector<double>& P, int b, int64_t n) {
@@ -706,7 +764,21 @@ static void upload_level(dgmg_solver* s, int l) {
     for (int64_t K = 0; K < A.n; ++K)
         for (int i = 0; i < b; ++i) dinv[K * b + i] = 1.0 / A.diag[((size_t)K * b + i) * b + i];
     const bool last = (l == s->L - 1);
-    if (!last || s->L == 1) {
+    // the fine level of a conforming mesh is stored once per face (axis-ELL)
+    // unless the caller asks for the tile-ELL layout everywhere
+    const bool ax = l == 0 && s->fine_layout != DGMG_LAYOUT_TILE_ELL && !s->axis0.empty();
+    if (ax) {
+        AxisEll E = build_axis_ell(A, s->axis0, s->dim);
+        L.ax = true;
+        L.up = s->upload(E.up);
+        L.lo = s->upload(E.lo);
+        L.vals64 = s->upload(E.vals);
+        L.dinv64 = s->upload(dinv);
+        if (s->prec == DGMG_PREC_MIXED) {
+            L.vals32 = s->upload(convert<float>(E.vals));
+            L.dinv32 = s->upload(convert<float>(dinv));
+        }
+    } else if (!last || s->L == 1) {
         TileEll E = build_tile_ell(A);
         L.slot_ptr = s->upload(E.slot_ptr);
         L.snb = s->upload(E.snb);
@@ -983,6 +1055,9 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         fail(DGMG_EINVAL, "max_rhs must be 0, 1 or DGMG_MULTI_RHS");
     s->max_rhs = mg->max_rhs > 1 ? mg->max_rhs : 1;
     s->mfma = mg->mfma ? 1 : 0;
+    if (mg->fine_layout < DGMG_LAYOUT_AUTO || mg->fine_layout > DGMG_LAYOUT_AXIS_ELL)
+        fail(DGMG_EINVAL, "unknown fine_layout");
+    s->fine_layout = mg->fine_layout;
     s->N = h->n_cells * re.b;
     s->S = ph->model == DGMG_MODEL_BO ? 3 : 1;
     s->parents = h->parent;
@@ -998,6 +1073,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
 
     double t0 = now_s();
     Faces F = find_faces(*h);
+    s->axis0 = F.axis;
     s->ops.resize(s->L);
     AdjointBlocks adj;
     const bool want_adj = mg->adjoint != 0;
@@ -1115,6 +1191,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     }
     s->info.t_upload = now_s() - t6;
     s->info.device_bytes = s->dev_bytes;
+    s->info.fine_layout = s->on_device ? (s->lv[0].ax ? DGMG_LAYOUT_AXIS_ELL : DGMG_LAYOUT_TILE_ELL) : 0;
     *out = guard.release();
     return DGMG_OK;
     API_END

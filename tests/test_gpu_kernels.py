@@ -19,13 +19,13 @@ SIZES = [("c1", 32, {}), ("c2", 64, {}), ("c2", 36, {"p": 3, "group": [3]}),
          ("c3", 8, {}), ("c3", 6, {"p": 1, "group": [3]})]
 
 
-def _setup(name, n, kw, precision="fp64", lam=True):
+def _setup(name, n, kw, precision="fp64", lam=True, layout="auto"):
     pr = make_problem(name, n=n, **kw)
     A0, M, A, cM = system_matrix(pr)
     oh = oracle_hierarchy(pr)
     mg = VCycle(A0, oh["P"])
     h, s = problem.build(pr, precision=precision,
-                         lam_override=mg.lam if lam else None)
+                         lam_override=mg.lam if lam else None, fine_layout=layout)
     return pr, mg, h, s
 
 
@@ -34,31 +34,34 @@ def _gpu():
     need_gpu()
 
 
+@pytest.mark.parametrize("layout", ["auto", "tile_ell"])
 @pytest.mark.parametrize("name,n,kw", SIZES)
-def test_apply_all_levels(name, n, kw):
-    pr, mg, h, s = _setup(name, n, kw, precision="mixed")
+def test_apply_all_levels(name, n, kw, layout):
+    pr, mg, h, s = _setup(name, n, kw, precision="mixed", layout=layout)
+    assert s.info()["fine_layout"] == ("axis_ell" if layout == "auto" else "tile_ell")
     rng = np.random.default_rng(1)
     for l in range(len(mg.A) - 1):
         x = rng.standard_normal(mg.A[l].shape[0])
         ref = mg.A[l] @ x
         y = torch.empty(len(x), dtype=torch.float64, device="cuda")
-        say("apply", name, n, kw, "level", l, "fp64")
+        say("apply", name, n, kw, layout, "level", l, "fp64")
         api.apply(s, l, dev(x), y, "fp64")
         assert rel(host(y), ref) <= 1e-13
-        say("apply", name, n, kw, "level", l, "fp32")
+        say("apply", name, n, kw, layout, "level", l, "fp32")
         api.apply(s, l, dev(x), y, "mixed")
         assert rel(host(y), ref) <= 2e-6
 
 
+@pytest.mark.parametrize("layout", ["auto", "tile_ell"])
 @pytest.mark.parametrize("name,n,kw", SIZES[:4])
-def test_vcycle_operator(name, n, kw):
+def test_vcycle_operator(name, n, kw, layout):
     rng = np.random.default_rng(2)
     for prec, tol in (("fp64", 1e-11), ("mixed", 2e-5)):
-        pr, mg, h, s = _setup(name, n, kw, precision=prec)
+        pr, mg, h, s = _setup(name, n, kw, precision=prec, layout=layout)
         r = rng.standard_normal(pr["N"])
         ref = mg(r)
         z = torch.empty(pr["N"], dtype=torch.float64, device="cuda")
-        say("vcycle", name, n, kw, prec)
+        say("vcycle", name, n, kw, prec, layout)
         api.vcycle(s, dev(r), z)
         assert rel(host(z), ref) <= tol, prec
 
