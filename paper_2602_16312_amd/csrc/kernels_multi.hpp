@@ -88,6 +88,11 @@ __device__ __forceinline__ void row_apply_m(const LevelArgs<T>& L, int tile, int
         ell_row_apply_m<T, B, R, VB>(L, tile, lc, va, vb, acc);
 }
 
+template <bool AX, bool VB>
+__device__ __forceinline__ void mfma8_tile_product(const LevelArgs<float>& L, int tile,
+                                                   const float* __restrict__ va,
+                                                   const float* __restrict__ vb, float* acc);
+
 // Workgroup sums of R doubles into partial[blockIdx.x * R + r].
 template <int R>
 __device__ __forceinline__ void wg_sum_store_m(const double* v, double* partial) {
@@ -124,10 +129,16 @@ __global__ __launch_bounds__(kWG) void k_apply_m(LevelArgs<T> L, const T* __rest
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0;
         row_apply_m<T, B, R, false, AX>(L, tile, lc, cell, va, nullptr, acc);
+        T* yp = y + (size_t)t * R;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            y[(size_t)t * R + r] = acc[r];
-            if (w) contrib[r] = (double)w[(size_t)t * R + r] * (double)acc[r];
+        for (int r = 0; r < R; ++r) yp[r] = acc[r];
+        if (w) {
+            const T* wp = w + (size_t)t * R;
+            T wv[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) wv[r] = wp[r];
+#pragma unroll
+            for (int r = 0; r < R; ++r) contrib[r] = (double)wv[r] * (double)acc[r];
         }
     }
     if (partial) wg_sum_store_m<R>(contrib, partial);
@@ -136,7 +147,7 @@ __global__ __launch_bounds__(kWG) void k_apply_m(LevelArgs<T> L, const T* __rest
 // Residual per column r = rhs - A (va + vb) with the same optional epilogues
 // as the single-column kernel (d, xout, per-column ||r||^2, restriction
 // partials).
-template <typename T, int B, int R, bool VB, bool AX>
+template <typename T, int B, int R, bool VB, bool AX, bool MF = false>
 __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __restrict__ va,
                                                     const T* __restrict__ vb, const T* __restrict__ rhs,
                                                     T* __restrict__ r, T* __restrict__ d, T c1,
@@ -150,20 +161,38 @@ __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __r
         contrib[q] = 0.0;
         rr[q] = 0;
     }
-    if (active) {
-        T acc[R];
+    T acc[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] = 0;
-        row_apply_m<T, B, R, VB, AX>(L, tile, lc, cell, va, vb, acc);
+    for (int q = 0; q < R; ++q) acc[q] = 0;
+    if constexpr (MF) mfma8_tile_product<AX, VB>(L, tile, va, vb, acc);   // whole workgroup
+    if (active) {
+        // own rows first (all loads of a kind issued together), then the product
+        const size_t k0 = (size_t)t * R;
+        T bv[R], xs[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) bv[q] = rhs[k0 + q];
+        if (xout) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) xs[q] = VB ? va[k0 + q] + vb[k0 + q] : va[k0 + q];
+        }
+        if constexpr (!MF) row_apply_m<T, B, R, VB, AX>(L, tile, lc, cell, va, vb, acc);
         const T di = L.dinv[t];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const size_t k = (size_t)t * R + q;
-            rr[q] = rhs[k] - acc[q];
-            if (r) r[k] = rr[q];
-            if (d) d[k] = di * rr[q] * c1;
-            if (xout) xout[k] = VB ? va[k] + vb[k] : va[k];
+            rr[q] = bv[q] - acc[q];
             contrib[q] = (double)rr[q] * (double)rr[q];
+        }
+        if (r) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) r[k0 + q] = rr[q];
+        }
+        if (d) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) d[k0 + q] = di * rr[q] * c1;
+        }
+        if (xout) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) xout[k0 + q] = xs[q];
         }
     }
     if (P) {
@@ -191,6 +220,37 @@ __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __r
     if (partial) wg_sum_store_m<R>(contrib, partial);
 }
 
+// Epilogue of the Chebyshev step for one row t and its R columns: x += d
+// (x = d when assign), r -= A d, dn = cd d + cr dinv r.  Each array's R
+// contiguous entries are loaded together (vector loads) before any store.
+template <typename T, int R>
+__device__ __forceinline__ void cheb_epilogue_m(const LevelArgs<T>& L, int t, const T* acc,
+                                                const T* __restrict__ d, T* __restrict__ x,
+                                                T* __restrict__ r, T* __restrict__ dn, T cd, T cr,
+                                                int assign) {
+    const size_t k0 = (size_t)t * R;
+    T dv[R], rv[R], xv[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) dv[q] = d[k0 + q];
+#pragma unroll
+    for (int q = 0; q < R; ++q) rv[q] = r[k0 + q];
+    if (!assign) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) xv[q] = x[k0 + q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) xv[q] = 0;
+    }
+    const T di = L.dinv[t];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const T rr = rv[q] - acc[q];
+        x[k0 + q] = xv[q] + dv[q];
+        r[k0 + q] = rr;
+        dn[k0 + q] = cd * dv[q] + cr * di * rr;
+    }
+}
+
 // One inner Chebyshev step on R columns (VALU).
 template <typename T, int B, int R, bool AX>
 __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __restrict__ d,
@@ -202,48 +262,44 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = 0;
     row_apply_m<T, B, R, false, AX>(L, tile, lc, cell, d, nullptr, acc);
-    const T di = L.dinv[t];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const size_t k = (size_t)t * R + q;
-        const T dt = d[k];
-        x[k] = assign ? dt : x[k] + dt;
-        const T rr = r[k] - acc[q];
-        r[k] = rr;
-        dn[k] = cd * dt + cr * di * rr;
-    }
+    cheb_epilogue_m<T, R>(L, t, acc, d, x, r, dn, cd, cr, assign);
 }
 
-// The same Chebyshev step for FP32 8x8 blocks and 8 columns on the matrix
-// cores: per wave 8 cells x 8 rows; v_mfma_f32_4x4x1f32 (16 blocks of 4x4)
-// with block = (cell, half of the rows) takes the stored value of the
-// lane's (cell, row) as its A operand (lane 4*blk + i supplies row i) and
-// the gathered column values as B (lane 4*blk + j supplies column j of one
-// half of the right-hand sides).  Lane 4*blk + j then holds rows
-// 4*half + 0..3 of right-hand side 4*rh + j.  On the axis-ELL layout the
-// lower faces contribute the transposed stored block (A operand = column of
-// the neighbour's block, zero where the cell has no lower neighbour).
-template <bool AX>
-__global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, const float* __restrict__ d,
-                                                         float* __restrict__ x, float* __restrict__ r,
-                                                         float* __restrict__ dn, float cd, float cr,
-                                                         int assign) {
+// A (va + vb) for a whole tile of FP32 8x8 blocks and 8 columns on the
+// matrix cores; every thread of the workgroup must call it.  Per wave 8
+// cells x 8 rows; v_mfma_f32_4x4x1f32 (16 blocks of 4x4) with block =
+// (cell, half of the rows) takes the stored value of the lane's (cell, row)
+// as its A operand (lane 4*blk + i supplies row i) and the gathered column
+// values as B (lane 4*blk + j supplies column j of one half of the
+// right-hand sides); lane 4*blk + j then holds rows 4*half + 0..3 of
+// right-hand side 4*rh + j, which LDS hands to the thread of each row
+// (acc[0..7] = the row's 8 columns).  On the axis-ELL layout the lower faces
+// contribute the transposed stored block (A operand = column of the
+// neighbour's block, zero where the cell has no lower neighbour).
+template <bool AX, bool VB>
+__device__ __forceinline__ void mfma8_tile_product(const LevelArgs<float>& L, int tile,
+                                                   const float* __restrict__ va,
+                                                   const float* __restrict__ vb, float* acc) {
     constexpr int B = 8, R = 8, TC = Tile<float, 8>::TC, TR = Tile<float, 8>::TR;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
-    const int lc = threadIdx.x / B;                 // cell in tile of this lane
+    const int lc = threadIdx.x / B;
     const int row = threadIdx.x - lc * B;
     const int cell0 = tile * TC;
     const int mycell = min(cell0 + lc, L.n - 1);    // padding lanes reuse a valid cell
     const int jj = lane & 3;                        // B operand / result column in block
     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     auto mma = [&](const float* a, int nb) {
-        const float* xv = d + (size_t)nb * B * R;
+        const float* xv = va + (size_t)nb * B * R;
+        const float* yv = VB ? vb + (size_t)nb * B * R : nullptr;
         float b0[B], b1[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             b0[j] = xv[j * R + jj];
             b1[j] = xv[j * R + 4 + jj];
+            if constexpr (VB) {
+                b0[j] += yv[j * R + jj];
+                b1[j] += yv[j * R + 4 + jj];
+            }
         }
 #pragma unroll
         for (int j = 0; j < B; ++j) {
@@ -283,26 +339,36 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, con
             mma(a, nb);
         }
     }
-    // lane (4*blk + jj) holds rows 4*(blk&1) + 0..3 of cell (threadIdx.x/64)*8 + blk/2
-    const int blk = lane >> 2;
-    const int cell = cell0 + (threadIdx.x >> 6) * 8 + (blk >> 1);
-    if (cell >= L.n) return;
-    const int row0 = 4 * (blk & 1);
+    __shared__ float ys[kWG * R];
+    {
+        const int blk = lane >> 2;
+        const int rbase = ((threadIdx.x >> 6) * 8 + (blk >> 1)) * B + 4 * (blk & 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int t = cell * B + row0 + i;
-        const float di = L.dinv[t];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const size_t k = (size_t)t * R + 4 * h + jj;
-            const float av = h ? acc1[i] : acc0[i];
-            const float dt = d[k];
-            x[k] = assign ? dt : x[k] + dt;
-            const float rr = r[k] - av;
-            r[k] = rr;
-            dn[k] = cd * dt + cr * di * rr;
+        for (int i = 0; i < 4; ++i) {
+            ys[(rbase + i) * R + jj] = acc0[i];
+            ys[(rbase + i) * R + 4 + jj] = acc1[i];
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = ys[threadIdx.x * R + q];
+}
+
+// The Chebyshev step for FP32 8x8 blocks and 8 columns with the block
+// product on the matrix cores.
+template <bool AX>
+__global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, const float* __restrict__ d,
+                                                         float* __restrict__ x, float* __restrict__ r,
+                                                         float* __restrict__ dn, float cd, float cr,
+                                                         int assign) {
+    constexpr int B = 8, R = 8;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int lc = threadIdx.x / B;
+    const int cell = tile * Tile<float, 8>::TC + lc;
+    float acc[R];
+    mfma8_tile_product<AX, false>(L, tile, d, nullptr, acc);
+    if (cell >= L.n) return;
+    cheb_epilogue_m<float, R>(L, cell * B + (threadIdx.x - lc * B), acc, d, x, r, dn, cd, cr, assign);
 }
 
 // First sweep from x = 0 on R columns: r = b, d = dinv * b * c1.
@@ -353,8 +419,12 @@ __global__ __launch_bounds__(kWG) void k_prolong_add_m(int32_t n, const int32_t*
 #pragma unroll
         for (int q = 0; q < R; ++q) acc[q] += p * (w ? v[j * R + q] + w[j * R + q] : v[j * R + q]);
     }
+    T* xp = x + (size_t)t * R;
+    T xv[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) x[(size_t)t * R + q] += acc[q];
+    for (int q = 0; q < R; ++q) xv[q] = xp[q];
+#pragma unroll
+    for (int q = 0; q < R; ++q) xp[q] = xv[q] + acc[q];
 }
 
 // X = Ainv Rhs for R columns (row-per-wave, right-hand sides staged in LDS),
@@ -408,16 +478,44 @@ __global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const double*
     }
 }
 
-// per-column partial dots of RHS-minor vectors
+// Pointwise kernels on N x R column-minor vectors: workgroup g covers the
+// kWG*R consecutive entries starting at g*kWG*R; thread x handles entries
+// x + q*kWG (q < R), all in column x % R, so every load instruction of a
+// wave is contiguous and each thread accumulates a single column.
+
+// Column sums of one value per thread (column threadIdx.x % R) into
+// partial[blockIdx.x * R + c].
+template <int R>
+__device__ __forceinline__ void wg_colsum_store(double v, double* partial) {
+    __shared__ double red[kWG / 64][R];
+#pragma unroll
+    for (int off = 32; off >= R; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane < R) red[wv][lane] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+        double s = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k][threadIdx.x];
+        partial[(size_t)blockIdx.x * R + threadIdx.x] = s;
+    }
+}
+
+// per-column partial dots of column-minor vectors
 template <int R>
 __global__ __launch_bounds__(kWG) void k_dot_m(int64_t N, const double* __restrict__ a,
                                                const double* __restrict__ b, double* __restrict__ partial) {
-    // thread handles DoF t (all R columns)
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    double v[R];
+    const int64_t NR = N * R, base = (int64_t)blockIdx.x * kWG * R + threadIdx.x;
+    double av[R], bv[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = t < N ? a[t * R + q] * b[t * R + q] : 0.0;
-    wg_sum_store_m<R>(v, partial);
+    for (int q = 0; q < R; ++q) {
+        const int64_t k = base + (int64_t)q * kWG;
+        av[q] = k < NR ? a[k] : 0.0;
+        bv[q] = k < NR ? b[k] : 0.0;
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) v += av[q] * bv[q];
+    wg_colsum_store<R>(v, partial);
 }
 
 // Column sums of R partials into sc[slot*R + r]; mode 1/2 as the single
@@ -425,32 +523,39 @@ __global__ __launch_bounds__(kWG) void k_dot_m(int64_t N, const double* __restri
 template <int R>
 __global__ __launch_bounds__(kWG) void k_finalize_m(int32_t np, const double* __restrict__ partial,
                                                     double* __restrict__ sc, int slot, int mode) {
-    __shared__ double red[kWG];
-    for (int q = 0; q < R; ++q) {
-        double s = 0.0;
-        for (int k = threadIdx.x; k < np; k += kWG) s += partial[(size_t)k * R + q];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = kWG / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const double v = red[0];
-            if (mode == 0) {
-                sc[slot * R + q] = v;
-            } else {
-                const double g = sc[1 * R + q];
-                sc[4 * R + q] = g != 0.0 ? (mode == 1 ? v : v - sc[5 * R + q]) / g : 0.0;
-                sc[slot * R + q] = v;
-                sc[1 * R + q] = v;
-            }
+    __shared__ double red[kWG][R + 1];
+    double s[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) s[q] = 0.0;
+    for (int k = threadIdx.x; k < np; k += kWG) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) s[q] += partial[(size_t)k * R + q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) red[threadIdx.x][q] = s[q];
+    __syncthreads();
+    for (int w = kWG / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) red[threadIdx.x][q] += red[threadIdx.x + w][q];
         }
         __syncthreads();
     }
+    if ((int)threadIdx.x < R) {
+        const int q = threadIdx.x;
+        const double v = red[0][q];
+        if (mode == 0) {
+            sc[slot * R + q] = v;
+        } else {
+            const double g = sc[1 * R + q];
+            sc[4 * R + q] = g != 0.0 ? (mode == 1 ? v : v - sc[5 * R + q]) / g : 0.0;
+            sc[slot * R + q] = v;
+            sc[1 * R + q] = v;
+        }
+    }
 }
 
-// x += alpha_r p, r -= alpha_r q for active columns; per-column ||r||^2.
+// x += alpha_c p, r -= alpha_c q for active columns c; per-column ||r||^2.
 template <int R>
 __global__ __launch_bounds__(kWG) void k_update_xr_m(int64_t N, const double* __restrict__ sc,
                                                      const int* __restrict__ active,
@@ -458,21 +563,31 @@ __global__ __launch_bounds__(kWG) void k_update_xr_m(int64_t N, const double* __
                                                      const double* __restrict__ q,
                                                      double* __restrict__ x, double* __restrict__ r,
                                                      double* __restrict__ partial) {
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    double v[R];
+    const int64_t NR = N * R, base = (int64_t)blockIdx.x * kWG * R + threadIdx.x;
+    const int c = threadIdx.x % R;
+    const double alpha = active[c] ? sc[1 * R + c] / sc[2 * R + c] : 0.0;
+    double pv[R], qv[R], xv[R], rv[R];
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-        v[c] = 0.0;
-        if (t < N) {
-            const size_t k = (size_t)t * R + c;
-            const double alpha = active[c] ? sc[1 * R + c] / sc[2 * R + c] : 0.0;
-            x[k] += alpha * p[k];
-            const double rn = r[k] - alpha * q[k];
+    for (int u = 0; u < R; ++u) {
+        const int64_t k = base + (int64_t)u * kWG;
+        const bool in = k < NR;
+        pv[u] = in ? p[k] : 0.0;
+        qv[u] = in ? q[k] : 0.0;
+        xv[u] = in ? x[k] : 0.0;
+        rv[u] = in ? r[k] : 0.0;
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int64_t k = base + (int64_t)u * kWG;
+        const double rn = rv[u] - alpha * qv[u];
+        if (k < NR) {
+            x[k] = xv[u] + alpha * pv[u];
             r[k] = rn;
-            v[c] = rn * rn;
+            v += rn * rn;
         }
     }
-    wg_sum_store_m<R>(v, partial);
+    wg_colsum_store<R>(v, partial);
 }
 
 template <int R>

@@ -268,12 +268,26 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
                                      largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
             }
         } else {
-            if (vb) {
-                DISPATCH_B(s->b, k_residual_m<T, BV, R, true, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
-            } else {
-                DISPATCH_B(s->b, k_residual_m<T, BV, R, false, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+            bool done = false;
+            if constexpr (std::is_same<T, float>::value && R == 8) {
+                if (s->mfma && s->b == 8) {
+                    if (vb)
+                        k_residual_m<float, 8, 8, true, AXV, true><<<tiles_for<float, 8>(L), kWG, 0, st>>>(
+                            largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp);
+                    else
+                        k_residual_m<float, 8, 8, false, AXV, true><<<tiles_for<float, 8>(L), kWG, 0, st>>>(
+                            largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp);
+                    done = true;
+                }
+            }
+            if (!done) {
+                if (vb) {
+                    DISPATCH_B(s->b, k_residual_m<T, BV, R, true, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                         largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+                } else {
+                    DISPATCH_B(s->b, k_residual_m<T, BV, R, false, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                         largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+                }
             }
         }
     });
