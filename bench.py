@@ -70,19 +70,36 @@ def cheb_step_flops(info, nrhs):
     return 2.0 * (n + 2 * nf) * b * b * nrhs
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+COUNTER_FILES = {
+    "c2": "k_cheb_step_f32_b9_c2_counters.md",
+    "c3": "k_cheb_step_f32_b27_c3_counters.md",
+    "c4": "k_cheb_step_f32_b8_c4_counters.md",
+    "c4x8": "k_cheb_step_mfma8_c4x8_counters.md",
+}
+
+
+def kernel_source_sha():
+    """sha256 over the device kernel sources (the counters are only valid for
+    the kernels they were taken on)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cheb_step_f32_b9_c2_counters.md")
-    src = os.path.join(ROOT, "paper_2602_16312_amd", "csrc", "kernels.hpp")
+    h = hashlib.sha256()
+    for name in ("kernels.hpp", "kernels_multi.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2602_16312_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when there is none or the kernel sources changed since
+    it was taken."""
+    if workload not in COUNTER_FILES:
+        return None
     try:
-        txt = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        txt = open(os.path.join(ROOT, "profiles", COUNTER_FILES[workload])).read()
     except OSError:
         return None
     vals = dict(l.split(": ", 1) for l in txt.splitlines() if ": " in l and not l.startswith(" "))
-    if vals.get("kernel_source_sha256", "").strip() != sha:
+    if vals.get("kernel_source_sha256", "").strip() != kernel_source_sha():
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -304,7 +321,7 @@ def main():
         "setup_s": res["setup_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic() if args.workload == "c2" else None,
+                     "traffic": profiled_traffic(args.workload),
                      "kernel": kname,
                      "alg_bytes_per_launch": alg, "avg_launch_us": per_launch_s * 1e6,
                      "avg_launch_us_in_run": prof["in_run_ms"] * 1e3,
