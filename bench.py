@@ -232,6 +232,69 @@ def run_adjoint(args):
     print(json.dumps(out))
 
 
+def _its_stats(pr, precision, tol, tol_mode, **mg):
+    """Runs pr's time steps through the library; PCG iteration statistics."""
+    import numpy as np
+    import torch
+    from paper_2602_16312_amd import api, problem
+    t0 = time.perf_counter()
+    h, s = problem.build(pr, precision=precision, **mg)
+    setup = time.perf_counter() - t0
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()), dev(pr["W0"].ravel()),
+                   torch.empty(pr["N"], dtype=torch.float64, device="cuda"))
+    on = _iapp(pr, pr["dt"], 1)
+    on = None if on is None else dev(on)
+    its = []
+    t0 = time.perf_counter()
+    for k in range(pr["steps"]):
+        t = (k + 1) * pr["dt"]
+        r = api.time_step(s, st, t, iapp=on if t <= pr["stim_tend"] + 1e-12 else None,
+                          tol=tol, tol_mode=tol_mode)
+        if not r["converged"]:
+            raise RuntimeError(f"step {k} did not converge: {r}")
+        its.append(r["its"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = s.info()
+    return dict(its=_stats(its), levels=info["n_cells"], n_dofs=int(pr["N"]), setup_s=setup,
+                ms_per_step=wall / pr["steps"] * 1e3, u_max=float(st.U.max()))
+
+
+def run_sweep(kind, precision):
+    """Iteration-count sweeps in the shape of the paper's tables: "e1" the
+    two-dimensional FitzHugh-Nagumo test for p = 1..4 (iterations per step
+    over T = 0.4 s); "levels" and "dt" on a 125k-hex shell (number of
+    multigrid levels; time step)."""
+    from workloads import make_problem
+    rows = []
+    if kind == "e1":
+        for p in (1, 2, 3, 4):
+            pr = make_problem("e1", p=p)
+            r = _its_stats(pr, precision, pr["tol"], pr["tol_mode"])
+            r.update(p=p)
+            rows.append(r)
+            log(f"e1 p={p}: {r['its']}")
+        desc = ("128x128 Q1-Q4 FitzHugh-Nagumo, shock on [0.4,0.6]^2, dt 1e-4 s, 4000 steps, "
+                "PCG to absolute residual 1e-14, 3 grid-grouped levels (4x4)")
+    elif kind in ("levels", "dt"):
+        cases = ([(1, 3, 0.05), (1, 4, 0.05), (1, 5, 0.05), (2, 4, 0.05), (2, 5, 0.05)]
+                 if kind == "levels" else
+                 [(p, 5, dt) for p in (1, 2) for dt in (0.5, 0.1, 0.05)])
+        for p, L, dt in cases:
+            pr = make_problem("c4", h=0.0294, p=p, agglo=("rtree_str", 8, L), dt=dt,
+                              steps=int(round(5.0 / dt)))
+            r = _its_stats(pr, precision, 1e-8, "rel_r0")
+            r.update(p=p, n_levels=L, dt=dt)
+            rows.append(r)
+            log(f"{kind} p={p} L={L} dt={dt}: {r['its']}")
+        desc = ("125k-hex shell (h 0.0294), Bueno-Orovio, apex stimulus, STR levels, 5 ms of "
+                "simulated time, PCG to relative residual 1e-8")
+    else:
+        raise SystemExit(f"unknown sweep {kind}")
+    print(json.dumps({"sweep": kind, "precision": precision, "workload": desc, "rows": rows}))
+
+
 def cpu_baseline(pr, tol, nsteps):
     from oracle.stepper import Simulation
     log("cpu baseline: oracle setup")
@@ -264,6 +327,9 @@ def main():
                          "c4: 1.0M-hex Q1 shell; c4x8: the shell with 8 simulations")
     ap.add_argument("--fine-layout", default="auto", choices=["auto", "tile_ell", "axis_ell"],
                     help="device storage of the fine operator (auto: each face block once)")
+    ap.add_argument("--sweep", choices=["e1", "levels", "dt"],
+                    help="print PCG iteration statistics of a sweep instead of the bench line")
+    ap.add_argument("--sweep-precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-mfma", action="store_true",
                     help="c4x8: keep the 8-column Chebyshev step on the vector ALUs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -285,6 +351,9 @@ def main():
         print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "launches": 5}))
         return
 
+    if args.sweep:
+        run_sweep(args.sweep, args.sweep_precision)
+        return
     if args.workload == "c5":
         run_adjoint(args)
         return

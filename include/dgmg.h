@@ -97,7 +97,8 @@ int dgmg_hierarchy_parents(const dgmg_hierarchy* h, int32_t level, int64_t* out)
 void dgmg_destroy_hierarchy(dgmg_hierarchy* h);
 
 enum { DGMG_PENALTY_PAPER = 0, DGMG_PENALTY_FIXED = 1 };
-/* Discretisation (section 3): tensor Q_p, 1 <= p <= 3.  Penalty on an
+/* Discretisation (section 3): tensor Q_p, 1 <= p <= 4 in 2D, 1 <= p <= 3 in
+ * 3D.  Penalty on an
  * interior face: sigma = eta_F * mean(n^T D+ n, n^T D- n) with
  * eta_F = c p(p+1) mean(|F|/|K+|, |F|/|K-|) (PAPER; c = `eta` if > 0, else
  * the paper's c = 1) or eta_F = `eta` (FIXED). */

@@ -18,6 +18,7 @@ struct Error {
 void set_last_error(const std::string& msg);
 
 // ---------------------------------------------------------------- reference
+constexpr int kMaxQ = 5;                      // points per direction, p <= 4
 struct RefElement {
     int d = 0, p = 0, q = 0, b = 0;          // q = p + 1 points per direction
     std::vector<double> nodes;                // Gauss-Lobatto nodes on [0,1]

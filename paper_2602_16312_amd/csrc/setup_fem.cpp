@@ -24,7 +24,11 @@ static std::vector<double> gauss_lobatto_01(int p) {
         const double s = std::sqrt(0.2);
         return {0.0, 0.5 * (1.0 - s), 0.5 * (1.0 + s), 1.0};
     }
-    fail(DGMG_EUNSUPPORTED, "polynomial degree must be 1, 2 or 3");
+    if (p == 4) {
+        const double s = std::sqrt(3.0 / 7.0);
+        return {0.0, 0.5 * (1.0 - s), 0.5, 0.5 * (1.0 + s), 1.0};
+    }
+    fail(DGMG_EUNSUPPORTED, "polynomial degree must be 1 to 4");
 }
 
 // n-point Gauss-Legendre rule on [0,1]: Newton iteration on P_n from the
@@ -92,6 +96,7 @@ void RefElement::init(int dim, int deg) {
     d = dim;
     p = deg;
     q = p + 1;
+    if (q > kMaxQ || (dim == 3 && p > 3)) fail(DGMG_EUNSUPPORTED, "polynomial degree must be 1 to 4 (2D) or 1 to 3 (3D)");
     nodes = gauss_lobatto_01(p);
     gauss_legendre_01(q, gx, gw);
     b = 1;
@@ -116,7 +121,7 @@ void RefElement::init(int dim, int deg) {
 }
 
 void tensor_eval(const RefElement& re, const double* xi, double* phi, double* grad) {
-    double v[3][4], dv[3][4];
+    double v[3][kMaxQ], dv[3][kMaxQ];
     for (int k = 0; k < re.d; ++k) lagrange1d(re.nodes, xi[k], v[k], dv[k]);
     for (int i = 0; i < re.b; ++i) {
         int idx[3] = {0, 0, 0};

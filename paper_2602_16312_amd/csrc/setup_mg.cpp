@@ -72,7 +72,7 @@ void prolongation_blocks(const Hierarchy& h, const RefElement& re, int level,
                 for (int k = 0; k < d; ++k)
                     x[k] = lo_l[(size_t)e * d + k] + xi[k] * (hi_l[(size_t)e * d + k] - lo_l[(size_t)e * d + k]);
             }
-            double l1[3][4];
+            double l1[3][kMaxQ];
             for (int k = 0; k < d; ++k) {
                 const double a = lo_c[(size_t)K * d + k], w = hi_c[(size_t)K * d + k] - a;
                 lagrange1d(re.nodes, (x[k] - a) / w, l1[k], nullptr);

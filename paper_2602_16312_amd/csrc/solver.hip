@@ -54,6 +54,7 @@ void set_last_error(const std::string& m) { g_last_error = m; }
         case 8: { constexpr int BV = 8; __VA_ARGS__; } break;                          \
         case 9: { constexpr int BV = 9; __VA_ARGS__; } break;                          \
         case 16: { constexpr int BV = 16; __VA_ARGS__; } break;                        \
+        case 25: { constexpr int BV = 25; __VA_ARGS__; } break;                        \
         case 27: { constexpr int BV = 27; __VA_ARGS__; } break;                        \
         case 64: { constexpr int BV = 64; __VA_ARGS__; } break;                        \
         default: fail(DGMG_EUNSUPPORTED, "unsupported block size");                    \

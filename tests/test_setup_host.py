@@ -29,7 +29,7 @@ def dense_level(ex):
 
 
 CASES = [("c1", 8, {}), ("c2", 16, {}), ("c2", 32, {"p": 1}), ("c3", 4, {}),
-         ("c1", 8, {"bdf": 1})]
+         ("c1", 8, {"bdf": 1}), ("c2", 8, {"p": 3, "group": [4]}), ("c2", 8, {"p": 4, "group": [4]})]
 
 
 @pytest.mark.parametrize("name,n,kw", CASES)

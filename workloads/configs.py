@@ -72,6 +72,16 @@ CONFIGS = {
                steps=20, model="bo", params=[BO_EPI[k] for k in BO_PARAM_NAMES],
                penalty=("paper", 2.0), ic="rest",
                stim=("sites", 0.15, 0.3, 3.0, 2604, 8), tol=1e-8),
+    # the paper's two-dimensional test (section 6, first experiment): 128x128
+    # unit square, FitzHugh-Nagumo with the appendix parameters (SI units),
+    # electric shock on [0.4, 0.6]^2 for t <= 1 ms, T = 0.4 s, dt = 1e-4 s,
+    # PCG stopped at absolute residual 1e-14; three grid-grouped levels
+    # stand in for the unstated hierarchy
+    "e1": dict(dim=2, n=128, p=1, jitter=0.0, seed=None, group=[4, 4],
+               sigma=("iso", 0.12), chi=1e5, Cm=1e-2, dt=1e-4, steps=4000,
+               model="fhn", params=[19.5, 0.013, 40.0, 0.1],
+               penalty=("paper",), ic="rest", stim=("box", 0.4, 0.6, 2e6, 1e-3),
+               tol=1e-14, tol_mode="abs"),
     # adjoint problem: mesh and physics of c2, 50 steps
     "c5": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
                sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=50,
@@ -185,6 +195,9 @@ def make_problem(name, n=None, steps=None, **overrides):
     if cfg["stim"] is not None and cfg["stim"][0] == "corner_block":
         _, edge, stim_amp, stim_tend = cfg["stim"]
         stim_mask = np.all(cen < edge, axis=1)
+    elif cfg["stim"] is not None and cfg["stim"][0] == "box":
+        _, lo, hi, stim_amp, stim_tend = cfg["stim"]
+        stim_mask = np.all((cen > lo) & (cen < hi), axis=1)
     prob = dict(cfg)
     prob.update(name=name, xyz=xyz, cell_vtx=cells, n_cells=nc, b=b, N=N,
                 S=S, D_cell=_conductivity(cfg["sigma"], cen, dim),

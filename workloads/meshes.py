@@ -14,7 +14,7 @@ import numpy as np
 
 
 def gl_nodes_1d(p):
-    """Gauss-Lobatto points on [0, 1] for degree p <= 3 (interpolation nodes
+    """Gauss-Lobatto points on [0, 1] for degree p <= 4 (interpolation nodes
     used to place initial values; p <= 2 coincides with equispaced)."""
     if p == 1:
         return np.array([0.0, 1.0])
@@ -23,7 +23,10 @@ def gl_nodes_1d(p):
     if p == 3:
         s = np.sqrt(1.0 / 5.0)
         return np.array([0.0, 0.5 * (1.0 - s), 0.5 * (1.0 + s), 1.0])
-    raise ValueError("p must be 1, 2 or 3")
+    if p == 4:
+        s = np.sqrt(3.0 / 7.0)
+        return np.array([0.0, 0.5 * (1.0 - s), 0.5, 0.5 * (1.0 + s), 1.0])
+    raise ValueError("p must be 1 to 4")
 
 
 def structured_mesh(dim, n, jitter=0.0, seed=None, lo=0.0, hi=1.0):
