@@ -96,3 +96,17 @@ def test_str_hierarchy_and_shell_levels_match_oracle():
         Al = dense_level(s.export_level(l))
         assert abs(Al - mg.A[l]).max() <= 1e-12 * abs(mg.A[l]).max(), l
     assert 1.1 < info["op_complexity"] < 1.4
+
+
+def test_paper_2d_test_dof_counts():
+    """The paper's two-dimensional test (128x128 quadrilaterals, Q1-Q4) set up
+    by the library has exactly the DoF counts of the paper's table dofs_2D."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_dof_counts.json")))
+    table = g["fine_meshes"][0]
+    assert table["cells"] == 128 * 128
+    for p in (1, 2, 3, 4):
+        pr = make_problem("e1", p=p)
+        h, s = problem.build(pr, device_setup=False)
+        assert s.info()["n_dofs"] == table["dofs"][str(p)]
