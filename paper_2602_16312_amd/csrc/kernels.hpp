@@ -267,18 +267,28 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
 
 // One inner Chebyshev step (gather vector d):
 //   x += d (x = d when assign), r -= A d, dn = cd * d + cr * dinv * r.
+// On the last step of a sweep (last != 0) the sweep's final correction is
+// applied at once: x = (x + d) + dn, and r, dn are not stored (the next
+// sweep starts from the true residual).
 template <typename T, int B, bool AX>
 __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __restrict__ d,
                                                    T* __restrict__ x, T* __restrict__ r,
-                                                   T* __restrict__ dn, T cd, T cr, int assign) {
+                                                   T* __restrict__ dn, T cd, T cr, int assign,
+                                                   int last) {
     DGMG_TILE_THREAD(T, B)
     if (!active) return;
     const T a = row_apply<T, B, false, AX>(L, tile, lc, cell, d, nullptr);
     const T dt = d[t];
-    x[t] = assign ? dt : x[t] + dt;
+    const T x1 = assign ? dt : x[t] + dt;
     const T rr = r[t] - a;
-    r[t] = rr;
-    dn[t] = cd * dt + cr * L.dinv[t] * rr;
+    const T dnew = cd * dt + cr * L.dinv[t] * rr;
+    if (last) {
+        x[t] = x1 + dnew;
+    } else {
+        x[t] = x1;
+        r[t] = rr;
+        dn[t] = dnew;
+    }
 }
 
 // First sweep from x = 0: r = b, d = dinv * b * c1.

@@ -227,7 +227,7 @@ template <typename T, int R>
 __device__ __forceinline__ void cheb_epilogue_m(const LevelArgs<T>& L, int t, const T* acc,
                                                 const T* __restrict__ d, T* __restrict__ x,
                                                 T* __restrict__ r, T* __restrict__ dn, T cd, T cr,
-                                                int assign) {
+                                                int assign, int last) {
     const size_t k0 = (size_t)t * R;
     T dv[R], rv[R], xv[R];
 #pragma unroll
@@ -242,6 +242,16 @@ __device__ __forceinline__ void cheb_epilogue_m(const LevelArgs<T>& L, int t, co
         for (int q = 0; q < R; ++q) xv[q] = 0;
     }
     const T di = L.dinv[t];
+    if (last) {
+        // the sweep's final correction applied at once (as the single-column step)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const T rr = rv[q] - acc[q];
+            const T dnew = cd * dv[q] + cr * di * rr;
+            x[k0 + q] = (xv[q] + dv[q]) + dnew;
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const T rr = rv[q] - acc[q];
@@ -255,14 +265,15 @@ __device__ __forceinline__ void cheb_epilogue_m(const LevelArgs<T>& L, int t, co
 template <typename T, int B, int R, bool AX>
 __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __restrict__ d,
                                                      T* __restrict__ x, T* __restrict__ r,
-                                                     T* __restrict__ dn, T cd, T cr, int assign) {
+                                                     T* __restrict__ dn, T cd, T cr, int assign,
+                                                     int last) {
     DGMG_TILE_THREAD(T, B)
     if (!active) return;
     T acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = 0;
     row_apply_m<T, B, R, false, AX>(L, tile, lc, cell, d, nullptr, acc);
-    cheb_epilogue_m<T, R>(L, t, acc, d, x, r, dn, cd, cr, assign);
+    cheb_epilogue_m<T, R>(L, t, acc, d, x, r, dn, cd, cr, assign, last);
 }
 
 // A (va + vb) for a whole tile of FP32 8x8 blocks and 8 columns on the
@@ -360,7 +371,7 @@ template <bool AX>
 __global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, const float* __restrict__ d,
                                                          float* __restrict__ x, float* __restrict__ r,
                                                          float* __restrict__ dn, float cd, float cr,
-                                                         int assign) {
+                                                         int assign, int last) {
     constexpr int B = 8, R = 8;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int lc = threadIdx.x / B;
@@ -368,7 +379,8 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_mfma8(LevelArgs<float> L, con
     float acc[R];
     mfma8_tile_product<AX, false>(L, tile, d, nullptr, acc);
     if (cell >= L.n) return;
-    cheb_epilogue_m<float, R>(L, cell * B + (threadIdx.x - lc * B), acc, d, x, r, dn, cd, cr, assign);
+    cheb_epilogue_m<float, R>(L, cell * B + (threadIdx.x - lc * B), acc, d, x, r, dn, cd, cr, assign,
+                              last);
 }
 
 // First sweep from x = 0 on R columns: r = b, d = dinv * b * c1.

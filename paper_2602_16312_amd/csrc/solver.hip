@@ -8,8 +8,9 @@
 // and the coarsest level is solved exactly with the FP64 inverse of its
 // Cholesky-factorised operator.  Chebyshev (Saad's preconditioned Chebyshev
 // acceleration, D = diag(A_l)) restarts s times from the true residual; the
-// last "x += d" of a sweep is carried as a pending correction and fused into
-// the next kernel that reads x.
+// sweep's last step also applies its final "x += d" (for degree 1 that
+// correction is carried as pending and fused into the next kernel that
+// reads x).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -295,24 +296,25 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
 }
 template <typename T, int R = 1>
 static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* r, T* dn, T cd, T cr,
-                        int assign, hipStream_t st) {
+                        int assign, int last, hipStream_t st) {
     ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
     DISPATCH_AX(L.ax, {
         if constexpr (R == 1) {
             DISPATCH_B(s->b, k_cheb_step<T, BV, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r,
-                                                                                           dn, cd, cr, assign));
+                                                                                           dn, cd, cr, assign,
+                                                                                           last));
         } else {
             bool done = false;
             if constexpr (std::is_same<T, float>::value && R == 8) {
                 if (s->mfma && s->b == 8) {
                     k_cheb_step_mfma8<AXV><<<tiles_for<float, 8>(L), kWG, 0, st>>>(largs<float>(L), d, x, r, dn,
-                                                                                  cd, cr, assign);
+                                                                                  cd, cr, assign, last);
                     done = true;
                 }
             }
             if (!done) {
                 DISPATCH_B(s->b, k_cheb_step_m<T, BV, R, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                     largs<T>(L), d, x, r, dn, cd, cr, assign));
+                                     largs<T>(L), d, x, r, dn, cd, cr, assign, last));
             }
         }
     });
@@ -365,18 +367,24 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
         double rho = 1.0 / sigma1;
         for (int i = 1; i < s->cheb_k; ++i) {
             const double rn = 1.0 / (2.0 * sigma1 - rho);
-            launch_step<T, R>(s, L, d, x, r, d2, (T)(rn * rho), (T)(2.0 * rn / delta), xzero ? 1 : 0, st);
+            // the last step of the sweep also applies the sweep's final
+            // correction x += d (it needs only the row's own new d)
+            const int last = i == s->cheb_k - 1;
+            launch_step<T, R>(s, L, d, x, r, d2, (T)(rn * rho), (T)(2.0 * rn / delta), xzero ? 1 : 0, last,
+                              st);
             xzero = false;
-            std::swap(d, d2);
+            if (!last) std::swap(d, d2);
             rho = rn;
         }
-        pending = true;
+        // degree 1: the correction from the residual kernel stays pending and
+        // is applied by the next kernel that reads x
+        pending = s->cheb_k == 1;
     };
     for (int k = 0; k < s->cheb_s; ++k) sweep();
-    // residual for the coarse correction (materialising the pending update),
+    // residual for the coarse correction (materialising a pending update),
     // with the per-cell restriction partials P_e^T r_e in its epilogue
     DevLevel& C = s->lv[l + 1];
-    T* rp = d2;   // free: the pending d is consumed here
+    T* rp = d2;   // free: no step result or pending correction lives there
     if (pending) {
         launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, (T*)nullptr, (T*)nullptr, c1, x2,
                               nullptr, st, Pof<T>(L), rp);
@@ -384,9 +392,11 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
         xzero = false;
         pending = false;
     } else {
-        // no smoothing: x = 0 and r = b
-        k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, x, (T)0);
-        xzero = false;
+        if (xzero) {
+            // no smoothing: x = 0 and r = b
+            k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, x, (T)0);
+            xzero = false;
+        }
         launch_residual<T, R>(s, L, x, (const T*)nullptr, b, (T*)nullptr, (T*)nullptr, c1, (T*)nullptr,
                               nullptr, st, Pof<T>(L), rp);
     }
@@ -1507,7 +1517,7 @@ int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t nrhs,
         HIPCHK(hipEventRecord(a, st));
         for (int k = 0; k < reps; ++k) {
             if (kind == PK_CHEB_STEP) {
-                launch_step<T, R>(s, L, d, x, r, d2, (T)0.5, (T)0.1, 0, st);
+                launch_step<T, R>(s, L, d, x, r, d2, (T)0.5, (T)0.1, 0, 0, st);
                 std::swap(d, d2);
             } else {
                 launch_residual<T, R>(s, L, x, d, bb ? bb : r, r, d2, (T)0.5, x2, nullptr, st);

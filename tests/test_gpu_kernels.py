@@ -66,6 +66,26 @@ def test_vcycle_operator(name, n, kw, layout):
         assert rel(host(z), ref) <= tol, prec
 
 
+@pytest.mark.parametrize("degree,sweeps", [(1, 2), (2, 1), (3, 0), (4, 2)])
+def test_vcycle_smoother_settings(degree, sweeps):
+    """Chebyshev degree and sweep count other than (3, 3): degree 1 keeps the
+    sweep's correction pending, degree >= 2 applies it in the last step, no
+    sweeps reduces the cycle to P A_c^-1 P^T on every level."""
+    pr = make_problem("c2", n=32)
+    A0 = system_matrix(pr)[0]
+    oh = oracle_hierarchy(pr)
+    mg = VCycle(A0, oh["P"], degree=degree, sweeps=sweeps)
+    r = np.random.default_rng(4).standard_normal(pr["N"])
+    ref = mg(r)
+    for prec, tol in (("fp64", 1e-11), ("mixed", 2e-5)):
+        h, s = problem.build(pr, precision=prec, lam_override=mg.lam, cheb_degree=degree,
+                             cheb_sweeps=sweeps)
+        z = torch.empty(pr["N"], dtype=torch.float64, device="cuda")
+        say("vcycle settings", degree, sweeps, prec)
+        api.vcycle(s, dev(r), z)
+        assert rel(host(z), ref) <= tol, (degree, sweeps, prec)
+
+
 def test_mass_blocks():
     pr = make_problem("c2", n=32)
     h, s = problem.build(pr)

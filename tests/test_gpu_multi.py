@@ -97,6 +97,22 @@ def test_vcycle_multi_matches_single(name, prec, mfma):
         assert rel(Zm[:, c], ref) <= tol, (c, rel(Zm[:, c], ref))
 
 
+@pytest.mark.parametrize("degree", [1, 2])
+def test_vcycle_multi_other_degrees(degree):
+    pr = case("shell")
+    h, s = problem.build(pr, precision="mixed", max_rhs=R, mfma=True, cheb_degree=degree)
+    N = pr["N"]
+    Rr = columns(N, 7)
+    say("vcycle_multi degree", degree)
+    Z = torch.empty(N * R, dtype=torch.float64, device="cuda")
+    api.vcycle_multi(s, dev(Rr.ravel()), Z)
+    Zm = host(Z).reshape(N, R)
+    z1 = torch.empty(N, dtype=torch.float64, device="cuda")
+    for c in (0, 5):
+        api.vcycle(s, dev(Rr[:, c]), z1)
+        assert rel(Zm[:, c], host(z1)) <= 2e-5, (degree, c)
+
+
 @pytest.mark.parametrize("name,prec,mfma,tol", [("shell", "fp64", False, 1e-10),
                                                 ("shell", "mixed", True, 1e-8),
                                                 ("shell", "mixed", False, 1e-8),
