@@ -143,7 +143,10 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * AXIS_ELL store every face block once (per cell: its block and the blocks
  * of its upper faces along each axis; lower faces are read transposed from
  * the neighbour), TILE_ELL stores each face block twice, oriented for both
- * cells, as on the agglomerated levels. */
+ * cells, as on the agglomerated levels.  MATRIX_FREE (meshes of identical
+ * axis-aligned boxes only, single-column calls only; DGMG_EUNSUPPORTED
+ * otherwise) stores no fine-level operator: the cell, face and mass terms
+ * are evaluated by sum factorisation from the per-cell conductivity. */
 typedef struct {
     int32_t cheb_degree;
     int32_t cheb_sweeps;
@@ -159,7 +162,8 @@ typedef struct {
     int32_t fine_layout;
 } dgmg_mg_opts;
 
-enum { DGMG_LAYOUT_AUTO = 0, DGMG_LAYOUT_TILE_ELL = 1, DGMG_LAYOUT_AXIS_ELL = 2 };
+enum { DGMG_LAYOUT_AUTO = 0, DGMG_LAYOUT_TILE_ELL = 1, DGMG_LAYOUT_AXIS_ELL = 2,
+       DGMG_LAYOUT_MATRIX_FREE = 3 };
 
 /* Number of columns of the multi-right-hand-side calls. */
 enum { DGMG_MULTI_RHS = 8 };
@@ -185,7 +189,7 @@ typedef struct {
     double op_complexity;
     double t_assembly, t_hierarchy, t_transfer, t_galerkin, t_smoother, t_coarse, t_upload;
     int64_t device_bytes;
-    int32_t fine_layout;   /* DGMG_LAYOUT_TILE_ELL or DGMG_LAYOUT_AXIS_ELL as used */
+    int32_t fine_layout;   /* DGMG_LAYOUT_TILE_ELL, _AXIS_ELL or _MATRIX_FREE as used */
 } dgmg_solver_info;
 int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info);
 

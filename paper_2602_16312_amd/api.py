@@ -13,7 +13,7 @@ from . import _ffi as F
 MODELS = {"fhn": 0, "ap": 1, "bo": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 TOL_MODES = {"rel_r0": 0, "rel_b": 1, "abs": 2}
-LAYOUTS = {"auto": 0, "tile_ell": 1, "axis_ell": 2}
+LAYOUTS = {"auto": 0, "tile_ell": 1, "axis_ell": 2, "matrix_free": 3}
 
 
 def _dptr(a):
@@ -120,7 +120,8 @@ class Solver:
                                  smoother=i.t_smoother, coarse=i.t_coarse,
                                  upload=i.t_upload),
                     device_bytes=i.device_bytes,
-                    fine_layout={1: "tile_ell", 2: "axis_ell"}.get(i.fine_layout, "none"))
+                    fine_layout={1: "tile_ell", 2: "axis_ell", 3: "matrix_free"}.get(i.fine_layout,
+                                                                                    "none"))
 
     def export_level(self, level):
         """Host copies of a level's FP64 operator and transfer blocks."""

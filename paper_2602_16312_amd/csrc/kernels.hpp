@@ -46,6 +46,25 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// Constants of the matrix-free fine level on identical axis-aligned boxes:
+// 1D tables on [0,1] (Q = p + 1 Lobatto nodes, Q Gauss points) and the box
+// geometry; D points to the per-cell packed (scaled) conductivity.
+constexpr int kMfMaxQ = 5;
+template <typename T>
+struct MfConst {
+    T Ig[kMfMaxQ * kMfMaxQ];   // Ig[g*Q + j] = l_j(gauss_g)
+    T Dg[kMfMaxQ * kMfMaxQ];   // Dg[g*Q + j] = l_j'(gauss_g)
+    T Ev[2 * kMfMaxQ];         // Ev[e*Q + j] = l_j(e), e = 0, 1
+    T Ed[2 * kMfMaxQ];         // Ed[e*Q + j] = l_j'(e)
+    T gw[kMfMaxQ];             // Gauss weights on [0,1]
+    T hinv[3];                 // 1 / h_k
+    T vol;                     // |K|
+    T area[3];                 // |F| of a face normal to axis k
+    T eta[3];                  // penalty factor of a face normal to axis k
+    T cM;                      // mass coefficient of A_0
+    const T* D;                // per cell: packed symmetric D (d(d+1)/2 values)
+};
+
 template <typename T>
 struct LevelArgs {
     const T* __restrict__ vals;            // tile-ELL or axis-ELL blocks
@@ -55,6 +74,7 @@ struct LevelArgs {
     int32_t n;
     const int32_t* __restrict__ up;        // axis-ELL: [d][n] upper neighbour (itself if none)
     const int32_t* __restrict__ lo;        // axis-ELL: [d][n] lower neighbour (-1 if none)
+    MfConst<T> mf;                         // matrix-free fine level (layout 2)
 };
 
 // spatial dimension of a block size (Q1..Q3 in 2D: 4, 9, 16; in 3D: 8, 27, 64)
@@ -178,13 +198,28 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int l
     return acc;
 }
 
-template <typename T, int B, bool VB, bool AX>
-__device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int tile, int lc, int cell,
+template <typename T, int B, bool VB>
+__device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cell, bool active,
+                                          const T* __restrict__ va, const T* __restrict__ vb);
+
+// Operator layouts of a level: tile-ELL, axis-ELL, matrix-free boxes.
+enum { LY_TILE = 0, LY_AXIS = 1, LY_MF = 2 };
+
+// (A (va + vb)) at the thread's row for layout LY.  The matrix-free product
+// synchronises the workgroup, so every thread calls this; rows of inactive
+// threads are not used.
+template <typename T, int B, bool VB, int LY>
+__device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int tile, int lc, int cell, bool active,
                                        const T* __restrict__ va, const T* __restrict__ vb) {
-    if constexpr (AX)
-        return ax_row_apply<T, B, VB>(L, tile, lc, cell, va, vb);
-    else
-        return ell_row_apply<T, B, VB>(L, tile, lc, va, vb);
+    if constexpr (LY == LY_MF) {
+        return mf_row_apply<T, B, VB>(L, lc, cell, active, va, vb);
+    } else {
+        if (!active) return T(0);
+        if constexpr (LY == LY_AXIS)
+            return ax_row_apply<T, B, VB>(L, tile, lc, cell, va, vb);
+        else
+            return ell_row_apply<T, B, VB>(L, tile, lc, va, vb);
+    }
 }
 
 // Workgroup sum of a double into partial[blockIdx.x] (deterministic order).
@@ -211,14 +246,14 @@ __device__ __forceinline__ void wg_sum_store(double v, double* partial) {
     const int t = cell * B + (threadIdx.x - lc * B);
 
 // y = A va; optional partial of dot(w, y).
-template <typename T, int B, bool AX>
+template <typename T, int B, int LY>
 __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restrict__ va,
                                                T* __restrict__ y,
                                                const T* __restrict__ w, double* __restrict__ partial) {
     DGMG_TILE_THREAD(T, B)
     double contrib = 0.0;
+    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, va, nullptr);
     if (active) {
-        const T a = row_apply<T, B, false, AX>(L, tile, lc, cell, va, nullptr);
         y[t] = a;
         if (w) contrib = (double)w[t] * (double)a;
     }
@@ -229,7 +264,7 @@ __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restri
 // xout = va + vb, partial of ||r||^2, and restriction partials
 // rp[cell, j] = sum_i P_cell(i, j) r[cell, i] (P in tile-interleaved layout)
 // for the coarse correction.  r may be null when only rp is wanted.
-template <typename T, int B, bool VB, bool AX>
+template <typename T, int B, bool VB, int LY>
 __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __restrict__ va,
                                                   const T* __restrict__ vb, const T* __restrict__ rhs,
                                                   T* __restrict__ r, T* __restrict__ d, T c1,
@@ -238,8 +273,8 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
     DGMG_TILE_THREAD(T, B)
     double contrib = 0.0;
     T rr = 0;
+    const T a = row_apply<T, B, VB, LY>(L, tile, lc, cell, active, va, vb);
     if (active) {
-        const T a = row_apply<T, B, VB, AX>(L, tile, lc, cell, va, vb);
         rr = rhs[t] - a;
         if (r) r[t] = rr;
         if (d) d[t] = L.dinv[t] * rr * c1;
@@ -270,14 +305,14 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
 // On the last step of a sweep (last != 0) the sweep's final correction is
 // applied at once: x = (x + d) + dn, and r, dn are not stored (the next
 // sweep starts from the true residual).
-template <typename T, int B, bool AX>
+template <typename T, int B, int LY>
 __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __restrict__ d,
                                                    T* __restrict__ x, T* __restrict__ r,
                                                    T* __restrict__ dn, T cd, T cr, int assign,
                                                    int last) {
     DGMG_TILE_THREAD(T, B)
+    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, d, nullptr);
     if (!active) return;
-    const T a = row_apply<T, B, false, AX>(L, tile, lc, cell, d, nullptr);
     const T dt = d[t];
     const T x1 = assign ? dt : x[t] + dt;
     const T rr = r[t] - a;

@@ -31,6 +31,7 @@
 #include "ionic.hpp"
 #include "kernels.hpp"
 #include "kernels_multi.hpp"
+#include "kernels_mf.hpp"
 
 namespace dgmg {
 
@@ -45,9 +46,13 @@ void set_last_error(const std::string& m) { g_last_error = m; }
             fail(DGMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
     } while (0)
 
-#define DISPATCH_AX(axval, ...)                                                        \
-    if (axval) { constexpr bool AXV = true; __VA_ARGS__; }                             \
-    else { constexpr bool AXV = false; __VA_ARGS__; }
+// level layout: LYV (LY_TILE, LY_AXIS, LY_MF) and AXV (axis-ELL) as constants
+#define DISPATCH_LY(lyval, ...)                                                        \
+    switch (lyval) {                                                                   \
+        case LY_TILE: { constexpr int LYV = LY_TILE; constexpr bool AXV = false; __VA_ARGS__; } break; \
+        case LY_AXIS: { constexpr int LYV = LY_AXIS; constexpr bool AXV = true; __VA_ARGS__; } break;  \
+        default: { constexpr int LYV = LY_MF; constexpr bool AXV = false; __VA_ARGS__; } break;        \
+    }
 
 #define DISPATCH_B(bval, ...)                                                          \
     switch (bval) {                                                                    \
@@ -75,6 +80,9 @@ struct DevLevel {
     int64_t N = 0;
     int32_t *slot_ptr = nullptr, *snb = nullptr;          // tile-ELL structure
     bool ax = false;                                       // axis-ELL layout instead
+    bool mf = false;                                       // matrix-free boxes (fine level)
+    MfConst<double> mf64{};
+    MfConst<float> mf32{};
     int32_t *up = nullptr, *lo = nullptr;                  // axis-ELL neighbours
     int32_t *child_ptr = nullptr, *child_list = nullptr;  // children on level l-1
     int32_t* parent = nullptr;                             // parent on level l+1
@@ -95,6 +103,11 @@ struct dgmg_solver {
     int cheb_k = 3, cheb_s = 3;
     int max_rhs = 1, mfma = 0;
     int fine_layout = 0;              // DGMG_LAYOUT_*
+    // matrix-free fine level on identical boxes: extents, packed scaled D,
+    // mass coefficient and penalty factors per axis
+    double mf_h[3] = {0, 0, 0};
+    double mf_cM = 0.0, mf_eta[3] = {0, 0, 0};
+    std::vector<double> mf_D;
     std::vector<int> axis0;           // axis of every fine face (face order of ops[0])
     int64_t N = 0;
     bool on_device = false;
@@ -187,12 +200,13 @@ template <typename T>
 static LevelArgs<T> largs(const DevLevel& L);
 template <>
 LevelArgs<double> largs<double>(const DevLevel& L) {
-    return {L.vals64, L.slot_ptr, L.snb, L.dinv64, L.n, L.up, L.lo};
+    return {L.vals64, L.slot_ptr, L.snb, L.dinv64, L.n, L.up, L.lo, L.mf64};
 }
 template <>
 LevelArgs<float> largs<float>(const DevLevel& L) {
-    return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n, L.up, L.lo};
+    return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n, L.up, L.lo, L.mf32};
 }
+static int level_ly(const DevLevel& L) { return L.mf ? LY_MF : (L.ax ? LY_AXIS : LY_TILE); }
 template <typename T>
 static const T* Pof(const DevLevel& L);
 template <>
@@ -245,10 +259,12 @@ template <typename T, int R = 1>
 static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, const T* w,
                          double* partial, hipStream_t st) {
     ProfScope ps(s, PK_APPLY, level_index(s, L), st);
-    DISPATCH_AX(L.ax, {
+    DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
-            DISPATCH_B(s->b, k_apply<T, BV, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w,
+            DISPATCH_B(s->b, k_apply<T, BV, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w,
                                                                                         partial));
+        } else if constexpr (LYV == LY_MF) {
+            fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
             DISPATCH_B(s->b, k_apply_m<T, BV, R, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y,
                                                                                             w, partial));
@@ -260,15 +276,17 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
                             T* r, T* d, T c1, T* xout, double* partial, hipStream_t st,
                             const T* P = nullptr, T* rp = nullptr) {
     ProfScope ps(s, PK_RESIDUAL, level_index(s, L), st);
-    DISPATCH_AX(L.ax, {
+    DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
             if (vb) {
-                DISPATCH_B(s->b, k_residual<T, BV, true, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                DISPATCH_B(s->b, k_residual<T, BV, true, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
                                      largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
             } else {
-                DISPATCH_B(s->b, k_residual<T, BV, false, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                DISPATCH_B(s->b, k_residual<T, BV, false, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
                                      largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
             }
+        } else if constexpr (LYV == LY_MF) {
+            fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
             bool done = false;
             if constexpr (std::is_same<T, float>::value && R == 8) {
@@ -298,11 +316,13 @@ template <typename T, int R = 1>
 static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* r, T* dn, T cd, T cr,
                         int assign, int last, hipStream_t st) {
     ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
-    DISPATCH_AX(L.ax, {
+    DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
-            DISPATCH_B(s->b, k_cheb_step<T, BV, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r,
+            DISPATCH_B(s->b, k_cheb_step<T, BV, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r,
                                                                                            dn, cd, cr, assign,
                                                                                            last));
+        } else if constexpr (LYV == LY_MF) {
+            fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
             bool done = false;
             if constexpr (std::is_same<T, float>::value && R == 8) {
@@ -778,6 +798,66 @@ static double* device_spd_inverse(dgmg_solver* s, const std::vector<double>& a, 
     return d;
 }
 
+// Identical axis-aligned boxes: every cell's corners are X_0 + sum_k bit_k h_k e_k
+// with the same h (relative tolerance 1e-12).  Returns false otherwise.
+static bool uniform_boxes(const Hierarchy& h, double* ext) {
+    const int d = h.dim, nc = 1 << d;
+    double scale = 0.0;
+    for (double v : h.xyz) scale = std::max(scale, std::fabs(v));
+    const double tol = 1e-12 * std::max(1.0, scale);
+    for (int k = 0; k < d; ++k) {
+        const int64_t v0 = h.cells[0], v1 = h.cells[(size_t)1 << k];
+        ext[k] = h.xyz[(size_t)v1 * d + k] - h.xyz[(size_t)v0 * d + k];
+        if (!(ext[k] > 0)) return false;
+    }
+    for (int64_t c = 0; c < h.n_cells; ++c) {
+        const int64_t* cv = &h.cells[(size_t)c * nc];
+        const double* x0 = &h.xyz[(size_t)cv[0] * d];
+        for (int corner = 1; corner < nc; ++corner) {
+            const double* xc = &h.xyz[(size_t)cv[corner] * d];
+            for (int k = 0; k < d; ++k) {
+                const double want = x0[k] + (((corner >> k) & 1) ? ext[k] : 0.0);
+                if (std::fabs(xc[k] - want) > tol) return false;
+            }
+        }
+    }
+    return true;
+}
+
+// 1D tables and geometry constants of the matrix-free fine level.
+template <typename T>
+static MfConst<T> mf_constants(const dgmg_solver* s, const RefElement& re, const T* dev_D) {
+    MfConst<T> C{};
+    const int Q = re.q;
+    std::vector<double> v(Q), dv(Q);
+    for (int g = 0; g < Q; ++g) {
+        lagrange1d(re.nodes, re.gx[g], v.data(), dv.data());
+        for (int j = 0; j < Q; ++j) {
+            C.Ig[g * Q + j] = (T)v[j];
+            C.Dg[g * Q + j] = (T)dv[j];
+        }
+        C.gw[g] = (T)re.gw[g];
+    }
+    for (int e = 0; e < 2; ++e) {
+        lagrange1d(re.nodes, (double)e, v.data(), dv.data());
+        for (int j = 0; j < Q; ++j) {
+            C.Ev[e * Q + j] = (T)v[j];
+            C.Ed[e * Q + j] = (T)dv[j];
+        }
+    }
+    double vol = 1.0;
+    for (int k = 0; k < s->dim; ++k) vol *= s->mf_h[k];
+    C.vol = (T)vol;
+    for (int k = 0; k < s->dim; ++k) {
+        C.hinv[k] = (T)(1.0 / s->mf_h[k]);
+        C.area[k] = (T)(vol / s->mf_h[k]);
+        C.eta[k] = (T)s->mf_eta[k];
+    }
+    C.cM = (T)s->mf_cM;
+    C.D = dev_D;
+    return C;
+}
+
 static void upload_level(dgmg_solver* s, int l) {
     const BlockOp& A = s->ops[l];
     DevLevel& L = s->lv[l];
@@ -791,8 +871,23 @@ static void upload_level(dgmg_solver* s, int l) {
     const bool last = (l == s->L - 1);
     // the fine level of a conforming mesh is stored once per face (axis-ELL)
     // unless the caller asks for the tile-ELL layout everywhere
-    const bool ax = l == 0 && s->fine_layout != DGMG_LAYOUT_TILE_ELL && !s->axis0.empty();
-    if (ax) {
+    const bool mf = l == 0 && s->fine_layout == DGMG_LAYOUT_MATRIX_FREE;
+    const bool ax = l == 0 && !mf && s->fine_layout != DGMG_LAYOUT_TILE_ELL && !s->axis0.empty();
+    if (mf) {
+        // neighbours as in the axis-ELL layout; no operator values are stored
+        AxisEll E = build_axis_ell(A, s->axis0, s->dim);
+        L.mf = true;
+        L.up = s->upload(E.up);
+        L.lo = s->upload(E.lo);
+        L.dinv64 = s->upload(dinv);
+        RefElement re;
+        re.init(s->dim, s->p);
+        L.mf64 = mf_constants<double>(s, re, s->upload(s->mf_D));
+        if (s->prec == DGMG_PREC_MIXED) {
+            L.dinv32 = s->upload(convert<float>(dinv));
+            L.mf32 = mf_constants<float>(s, re, s->upload(convert<float>(s->mf_D)));
+        }
+    } else if (ax) {
         AxisEll E = build_axis_ell(A, s->axis0, s->dim);
         L.ax = true;
         L.up = s->upload(E.up);
@@ -1080,8 +1175,10 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         fail(DGMG_EINVAL, "max_rhs must be 0, 1 or DGMG_MULTI_RHS");
     s->max_rhs = mg->max_rhs > 1 ? mg->max_rhs : 1;
     s->mfma = mg->mfma ? 1 : 0;
-    if (mg->fine_layout < DGMG_LAYOUT_AUTO || mg->fine_layout > DGMG_LAYOUT_AXIS_ELL)
+    if (mg->fine_layout < DGMG_LAYOUT_AUTO || mg->fine_layout > DGMG_LAYOUT_MATRIX_FREE)
         fail(DGMG_EINVAL, "unknown fine_layout");
+    if (mg->fine_layout == DGMG_LAYOUT_MATRIX_FREE && mg->max_rhs > 1)
+        fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
     s->fine_layout = mg->fine_layout;
     s->N = h->n_cells * re.b;
     s->S = ph->model == DGMG_MODEL_BO ? 3 : 1;
@@ -1105,6 +1202,20 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     if (want_adj && ph->model == DGMG_MODEL_BO)
         fail(DGMG_EUNSUPPORTED, "the adjoint is implemented for the FHN and Aliev-Panfilov models");
     assemble_fine(*h, F, re, *disc, *ph, cM, s->ops[0], s->mass_h, want_adj ? &adj : nullptr);
+    if (s->fine_layout == DGMG_LAYOUT_MATRIX_FREE) {
+        if (!uniform_boxes(*h, s->mf_h))
+            fail(DGMG_EUNSUPPORTED, "the matrix-free fine level needs identical axis-aligned box cells");
+        s->mf_cM = cM;
+        for (int k = 0; k < s->dim; ++k)
+            s->mf_eta[k] = disc->penalty_mode == DGMG_PENALTY_FIXED
+                               ? disc->eta
+                               : (disc->eta > 0 ? disc->eta : 1.0) * disc->p * (disc->p + 1) / s->mf_h[k];
+        const int np = s->dim * (s->dim + 1) / 2;
+        s->mf_D.assign(ph->D_cell, ph->D_cell + (size_t)h->n_cells * np);
+        if (ph->cell_scale)
+            for (int64_t c = 0; c < h->n_cells; ++c)
+                for (int k = 0; k < np; ++k) s->mf_D[(size_t)c * np + k] *= ph->cell_scale[c];
+    }
     double t1 = now_s();
     s->info.t_assembly = t1 - t0;
     // boxes and prolongations
@@ -1216,7 +1327,9 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     }
     s->info.t_upload = now_s() - t6;
     s->info.device_bytes = s->dev_bytes;
-    s->info.fine_layout = s->on_device ? (s->lv[0].ax ? DGMG_LAYOUT_AXIS_ELL : DGMG_LAYOUT_TILE_ELL) : 0;
+    s->info.fine_layout = !s->on_device ? 0
+                          : s->lv[0].mf ? DGMG_LAYOUT_MATRIX_FREE
+                          : s->lv[0].ax ? DGMG_LAYOUT_AXIS_ELL : DGMG_LAYOUT_TILE_ELL;
     *out = guard.release();
     return DGMG_OK;
     API_END
