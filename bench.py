@@ -51,11 +51,15 @@ def _stats(v):
 
 def cheb_step_bytes(info, prec_bytes, nrhs=1):
     """Algorithmic bytes of one fused Chebyshev step on level 0: every cell
-    and face block once, the adjacency lists, and the vector streams of
-    every column (gather d, x r/w, r r/w, new d) plus D^-1 once."""
+    and face block once (matrix-free: the packed conductivity of every cell
+    instead), the adjacency lists, and the vector streams of every column
+    (gather d, x r/w, r r/w, new d) plus D^-1 once."""
     b = info["b"]
     n, nf = info["n_cells"][0], info["n_faces"][0]
     N = n * b
+    if info.get("fine_layout") == "matrix_free":
+        d = info["dim"]
+        return n * (d * (d + 1) // 2) * prec_bytes + 2 * d * 4 * n + (6 * nrhs + 1) * prec_bytes * N
     blocks = (n + nf) * b * b * prec_bytes
     adjacency = 4 * (n + 1) + 2 * 2 * 4 * nf
     vectors = (6 * nrhs + 1) * prec_bytes * N
@@ -261,7 +265,7 @@ def _its_stats(pr, precision, tol, tol_mode, **mg):
                 ms_per_step=wall / pr["steps"] * 1e3, u_max=float(st.U.max()))
 
 
-def run_sweep(kind, precision):
+def run_sweep(kind, precision, fine_layout="auto"):
     """Iteration-count sweeps in the shape of the paper's tables: "e1" the
     two-dimensional FitzHugh-Nagumo test for p = 1..4 (iterations per step
     over T = 0.4 s); "levels" and "dt" on a 125k-hex shell (number of
@@ -271,7 +275,7 @@ def run_sweep(kind, precision):
     if kind == "e1":
         for p in (1, 2, 3, 4):
             pr = make_problem("e1", p=p)
-            r = _its_stats(pr, precision, pr["tol"], pr["tol_mode"])
+            r = _its_stats(pr, precision, pr["tol"], pr["tol_mode"], fine_layout=fine_layout)
             r.update(p=p)
             rows.append(r)
             log(f"e1 p={p}: {r['its']}")
@@ -292,7 +296,8 @@ def run_sweep(kind, precision):
                 "simulated time, PCG to relative residual 1e-8")
     else:
         raise SystemExit(f"unknown sweep {kind}")
-    print(json.dumps({"sweep": kind, "precision": precision, "workload": desc, "rows": rows}))
+    print(json.dumps({"sweep": kind, "precision": precision, "fine_layout": fine_layout,
+                      "workload": desc, "rows": rows}))
 
 
 def cpu_baseline(pr, tol, nsteps):
@@ -325,8 +330,10 @@ def main():
     ap.add_argument("--workload", default="c2", choices=list(WORKLOADS),
                     help="c2: 256x256 Q2 (default bench line); c3: 64^3 Q2 cube; "
                          "c4: 1.0M-hex Q1 shell; c4x8: the shell with 8 simulations")
-    ap.add_argument("--fine-layout", default="auto", choices=["auto", "tile_ell", "axis_ell"],
-                    help="device storage of the fine operator (auto: each face block once)")
+    ap.add_argument("--fine-layout", default="auto",
+                    choices=["auto", "tile_ell", "axis_ell", "matrix_free"],
+                    help="device storage of the fine operator (auto: each face block once; "
+                         "matrix_free: sum factorisation, meshes of identical boxes only)")
     ap.add_argument("--sweep", choices=["e1", "levels", "dt"],
                     help="print PCG iteration statistics of a sweep instead of the bench line")
     ap.add_argument("--sweep-precision", default="fp64", choices=["fp64", "mixed"])
@@ -352,7 +359,7 @@ def main():
         return
 
     if args.sweep:
-        run_sweep(args.sweep, args.sweep_precision)
+        run_sweep(args.sweep, args.sweep_precision, args.fine_layout)
         return
     if args.workload == "c5":
         run_adjoint(args)
@@ -372,7 +379,7 @@ def main():
     b_ = info["b"]
     achieved = alg / per_launch_s / 1e9
     if nrhs == 1:
-        kname = f"k_cheb_step<float,{b_},{'axis' if info['fine_layout'] == 'axis_ell' else 'tile'}-ELL> (level 0)"
+        kname = f"k_cheb_step<float,{b_},{info['fine_layout']}> (level 0)"
     elif mfma:
         kname = f"k_cheb_step_mfma8<{info['fine_layout']}> (level 0, 8 columns, v_mfma_f32_4x4x1f32)"
     else:

@@ -139,11 +139,13 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * work vector for that many columns, enabling the *_multi calls).  mfma = 1
  * runs the FP32 Chebyshev step of 8-column solves with 8x8 blocks (3D Q1)
  * on the matrix cores (v_mfma_f32_4x4x1f32); 0 keeps it on the vector ALUs.
- * fine_layout selects the device storage of the fine operator: AUTO and
- * AXIS_ELL store every face block once (per cell: its block and the blocks
- * of its upper faces along each axis; lower faces are read transposed from
- * the neighbour), TILE_ELL stores each face block twice, oriented for both
- * cells, as on the agglomerated levels.  MATRIX_FREE (meshes of identical
+ * fine_layout selects the device storage of the fine operator: AXIS_ELL
+ * stores every face block once (per cell: its block and the blocks of its
+ * upper faces along each axis; lower faces are read transposed from the
+ * neighbour), TILE_ELL stores each face block twice, oriented for both
+ * cells, as on the agglomerated levels; AUTO takes MATRIX_FREE for p >= 2 on
+ * meshes of identical boxes with max_rhs <= 1, AXIS_ELL otherwise.
+ * MATRIX_FREE (meshes of identical
  * axis-aligned boxes only, single-column calls only; DGMG_EUNSUPPORTED
  * otherwise) stores no fine-level operator: the cell, face and mass terms
  * are evaluated by sum factorisation from the per-cell conductivity. */

@@ -54,8 +54,7 @@ template <typename T>
 struct MfConst {
     T Ig[kMfMaxQ * kMfMaxQ];   // Ig[g*Q + j] = l_j(gauss_g)
     T Dg[kMfMaxQ * kMfMaxQ];   // Dg[g*Q + j] = l_j'(gauss_g)
-    T Ev[2 * kMfMaxQ];         // Ev[e*Q + j] = l_j(e), e = 0, 1
-    T Ed[2 * kMfMaxQ];         // Ed[e*Q + j] = l_j'(e)
+    T Ed[2 * kMfMaxQ];         // Ed[e*Q + j] = l_j'(e), e = 0, 1 (l_j(e) is 0 or 1: Lobatto ends)
     T gw[kMfMaxQ];             // Gauss weights on [0,1]
     T hinv[3];                 // 1 / h_k
     T vol;                     // |K|
@@ -483,11 +482,13 @@ __global__ __launch_bounds__(kWG) void k_finalize(int32_t np, const double* __re
 }
 
 // x += alpha p; r -= alpha q with alpha = sc[1] / sc[2]; partial ||r||^2.
+// When rb is set it also receives the new residual in FP32 (the next
+// V-cycle's right-hand side in mixed precision).
 __global__ __launch_bounds__(kWG) void k_update_xr(int64_t N, const double* __restrict__ sc,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ q,
                                                    double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, float* __restrict__ rb) {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
     const double alpha = sc[1] / sc[2];
     double v = 0.0;
@@ -495,7 +496,23 @@ __global__ __launch_bounds__(kWG) void k_update_xr(int64_t N, const double* __re
         x[t] += alpha * p[t];
         const double rn = r[t] - alpha * q[t];
         r[t] = rn;
+        if (rb) rb[t] = (float)rn;
         v = rn * rn;
+    }
+    wg_sum_store(v, partial);
+}
+
+// z = a (+ b) in FP64 (the V-cycle's result) with the partials of (r, z).
+template <typename Tin>
+__global__ __launch_bounds__(kWG) void k_cast_dot(int64_t N, const Tin* __restrict__ a,
+                                                  const Tin* __restrict__ b, double* __restrict__ z,
+                                                  const double* __restrict__ r, double* __restrict__ partial) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (t < N) {
+        const double zz = b ? (double)a[t] + (double)b[t] : (double)a[t];
+        z[t] = zz;
+        v = r[t] * zz;
     }
     wg_sum_store(v, partial);
 }

@@ -152,6 +152,9 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const int s1 = t1 == 0 ? 1 : Q;
             const int s2 = D == 3 ? (t2 == 1 ? Q : Q * Q) : 0;
             const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
+            // Lobatto nodes contain both ends, so a trace is the face layer of
+            // nodes (layer 0 or Q-1); the normal derivative needs every layer
+            const int lK = eK * (Q - 1), lN = eN * (Q - 1);
             T uK = 0, uN = 0, nK = 0, nN = 0, p1K = 0, p1N = 0, p2K = 0, p2N = 0;
             for (int j2 = 0; j2 < (D == 3 ? Q : 1); ++j2) {
                 const T i2 = D == 3 ? C.Ig[g2 * Q + j2] : T(1);
@@ -160,21 +163,22 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
                     const T tI = C.Ig[g1 * Q + j1] * i2;
                     const T t1d = C.Dg[g1 * Q + j1] * i2;
                     const T t2d = C.Ig[g1 * Q + j1] * e2;
+                    const int J0 = j1 * s1 + j2 * s2;
+                    T dnK = 0, dnN = 0;
 #pragma unroll
                     for (int ja = 0; ja < Q; ++ja) {
-                        const int J = ja * sa + j1 * s1 + j2 * s2;
-                        const T xK = xs[lc][J], xN = xn[lc][f][J];
-                        const T vK = C.Ev[eK * Q + ja], vN = C.Ev[eN * Q + ja];
-                        const T dK = C.Ed[eK * Q + ja], dN = C.Ed[eN * Q + ja];
-                        uK += vK * tI * xK;
-                        uN += vN * tI * xN;
-                        nK += dK * tI * xK;
-                        nN += dN * tI * xN;
-                        p1K += vK * t1d * xK;
-                        p1N += vN * t1d * xN;
-                        p2K += vK * t2d * xK;
-                        p2N += vN * t2d * xN;
+                        dnK += C.Ed[eK * Q + ja] * xs[lc][J0 + ja * sa];
+                        dnN += C.Ed[eN * Q + ja] * xn[lc][f][J0 + ja * sa];
                     }
+                    const T vK = xs[lc][J0 + lK * sa], vN = xn[lc][f][J0 + lN * sa];
+                    uK += tI * vK;
+                    uN += tI * vN;
+                    nK += tI * dnK;
+                    nN += tI * dnN;
+                    p1K += t1d * vK;
+                    p1N += t1d * vN;
+                    p2K += t2d * vK;
+                    p2N += t2d * vN;
                 }
             }
             T wK = Dk[lc][pk<D>(a, a)] * C.hinv[a] * nK + Dk[lc][pk<D>(a, t1)] * C.hinv[t1] * p1K;
@@ -195,7 +199,9 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         }
     }
     __syncthreads();
-    // ---- phase 3: test against the thread's basis function I = i
+    // ---- phase 3: test against the thread's basis function I = i (direct
+    // sums; with the loops unrolled the compiler keeps the 1D table entries
+    // in registers, which measured faster than factorising the sums)
     T y = 0;
     if (slot) {
         const int ik[3] = {i % Q, (i / Q) % Q, D == 3 ? i / (Q * Q) : 0};
@@ -224,7 +230,8 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         for (int f = 0; f < NF; ++f) {
             const int a = f >> 1, eK = f & 1;
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-            const T vI = C.Ev[eK * Q + ik[a]], dI = C.Ed[eK * Q + ik[a]];
+            const T vI = ik[a] == eK * (Q - 1) ? T(1) : T(0);   // trace of a Lobatto basis function
+            const T dI = C.Ed[eK * Q + ik[a]];
             for (int qf = 0; qf < QF; ++qf) {
                 const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
                 const T tI = C.Ig[g1 * Q + ik[t1]] * (D == 3 ? C.Ig[g2 * Q + ik[t2]] : T(1));

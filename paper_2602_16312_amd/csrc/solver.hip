@@ -452,21 +452,32 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     *dres = pending ? d : nullptr;
 }
 
-// z = V(r), r and z FP64 of length N x R (column-minor).
+// z = V(r), r and z FP64 of length N x R (column-minor).  Single column:
+// `rb_ready` says that the FP32 copy of r is already in the level-0 right-hand
+// side (written by the PCG update), and a non-null `rz_partial` makes the exit
+// cast also write the partials of (r, z).
 template <int R = 1>
-static void apply_vcycle(dgmg_solver* s, const double* r, double* z, hipStream_t st) {
+static void apply_vcycle(dgmg_solver* s, const double* r, double* z, hipStream_t st, bool rb_ready = false,
+                         double* rz_partial = nullptr) {
     DevLevel& L0 = s->lv[0];
     const int64_t NR = s->N * R;
     if (s->prec == DGMG_PREC_FP64) {
         L0.vb = (void*)r;
         double *x, *d;
         vcycle<double, R>(s, 0, st, &x, &d);
-        k_cast<double, double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z);
+        if (R == 1 && rz_partial)
+            k_cast_dot<double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z, r, rz_partial);
+        else
+            k_cast<double, double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z);
     } else {
-        k_cast<double, float><<<blocks_for(NR), kWG, 0, st>>>(NR, r, nullptr, (float*)L0.vb);
+        if (!(R == 1 && rb_ready))
+            k_cast<double, float><<<blocks_for(NR), kWG, 0, st>>>(NR, r, nullptr, (float*)L0.vb);
         float *x, *d;
         vcycle<float, R>(s, 0, st, &x, &d);
-        k_cast<float, double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z);
+        if (R == 1 && rz_partial)
+            k_cast_dot<float><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z, r, rz_partial);
+        else
+            k_cast<float, double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z);
     }
 }
 
@@ -508,10 +519,12 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
     k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 1, 0);
     k_update_p<<<nb, kWG, 0, st>>>(N, s->sc, s->z, s->pv, 1);
     int its = 0;
+    // mixed precision: the update also writes the FP32 right-hand side of the next V-cycle
+    float* rb = s->prec == DGMG_PREC_MIXED ? (float*)L0.vb : nullptr;
     while (its < o.max_it) {
         launch_apply<double>(s, L0, s->pv, s->q, s->pv, s->partial, st);
         k_finalize<<<1, kWG, 0, st>>>(nt, s->partial, s->sc, 2, 0);
-        k_update_xr<<<nb, kWG, 0, st>>>(N, s->sc, s->pv, s->q, x, s->r, s->partial);
+        k_update_xr<<<nb, kWG, 0, st>>>(N, s->sc, s->pv, s->q, x, s->r, s->partial, rb);
         k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 0, 0);
         read_scalars(s, st);
         ++its;
@@ -528,13 +541,16 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
             stats->converged = 1;
             return DGMG_OK;
         }
-        if (o.flexible) std::swap(s->z, s->zold);
-        apply_vcycle(s, s->r, s->z, st);
         if (o.flexible) {
+            std::swap(s->z, s->zold);
+            apply_vcycle(s, s->r, s->z, st, true);
             k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->zold, s->partial);
             k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 5, 0);
+            k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
+        } else {
+            // z = V(r) with the partials of (r, z) from the exit cast
+            apply_vcycle(s, s->r, s->z, st, true, s->partial);
         }
-        k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
         k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 3, o.flexible ? 2 : 1);
         k_update_p<<<nb, kWG, 0, st>>>(N, s->sc, s->z, s->pv, 0);
     }
@@ -840,10 +856,7 @@ static MfConst<T> mf_constants(const dgmg_solver* s, const RefElement& re, const
     }
     for (int e = 0; e < 2; ++e) {
         lagrange1d(re.nodes, (double)e, v.data(), dv.data());
-        for (int j = 0; j < Q; ++j) {
-            C.Ev[e * Q + j] = (T)v[j];
-            C.Ed[e * Q + j] = (T)dv[j];
-        }
+        for (int j = 0; j < Q; ++j) C.Ed[e * Q + j] = (T)dv[j];
     }
     double vol = 1.0;
     for (int k = 0; k < s->dim; ++k) vol *= s->mf_h[k];
@@ -1202,6 +1215,10 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     if (want_adj && ph->model == DGMG_MODEL_BO)
         fail(DGMG_EUNSUPPORTED, "the adjoint is implemented for the FHN and Aliev-Panfilov models");
     assemble_fine(*h, F, re, *disc, *ph, cM, s->ops[0], s->mass_h, want_adj ? &adj : nullptr);
+    // AUTO: matrix-free on meshes of identical boxes for p >= 2 (single-column
+    // solvers), the axis-ELL blocks otherwise
+    if (s->fine_layout == DGMG_LAYOUT_AUTO && s->p >= 2 && s->max_rhs == 1 && uniform_boxes(*h, s->mf_h))
+        s->fine_layout = DGMG_LAYOUT_MATRIX_FREE;
     if (s->fine_layout == DGMG_LAYOUT_MATRIX_FREE) {
         if (!uniform_boxes(*h, s->mf_h))
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level needs identical axis-aligned box cells");

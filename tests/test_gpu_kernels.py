@@ -34,11 +34,11 @@ def _gpu():
     need_gpu()
 
 
-@pytest.mark.parametrize("layout", ["auto", "tile_ell"])
+@pytest.mark.parametrize("layout", ["axis_ell", "tile_ell"])
 @pytest.mark.parametrize("name,n,kw", SIZES)
 def test_apply_all_levels(name, n, kw, layout):
     pr, mg, h, s = _setup(name, n, kw, precision="mixed", layout=layout)
-    assert s.info()["fine_layout"] == ("axis_ell" if layout == "auto" else "tile_ell")
+    assert s.info()["fine_layout"] == layout
     rng = np.random.default_rng(1)
     for l in range(len(mg.A) - 1):
         x = rng.standard_normal(mg.A[l].shape[0])
@@ -52,7 +52,7 @@ def test_apply_all_levels(name, n, kw, layout):
         assert rel(host(y), ref) <= 2e-6
 
 
-@pytest.mark.parametrize("layout", ["auto", "tile_ell"])
+@pytest.mark.parametrize("layout", ["auto", "axis_ell", "tile_ell"])
 @pytest.mark.parametrize("name,n,kw", SIZES[:4])
 def test_vcycle_operator(name, n, kw, layout):
     rng = np.random.default_rng(2)

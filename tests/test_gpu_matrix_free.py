@@ -83,6 +83,17 @@ def test_time_series_matches_oracle():
         assert rel(host(st.U), ref[k]) <= 1e-10, k
 
 
+def test_auto_layout_choice():
+    cases = [("c3", dict(n=4), "matrix_free"), ("c1", dict(n=8), "axis_ell"),
+             ("c2", dict(n=8), "axis_ell")]
+    for name, kw, want in cases:
+        pr = make_problem(name, **kw)
+        h, s = problem.build(pr)
+        assert s.info()["fine_layout"] == want, name
+    h, s = problem.build(make_problem("c3", n=4), max_rhs=8)
+    assert s.info()["fine_layout"] == "axis_ell"
+
+
 def test_rejects_meshes_that_are_not_boxes():
     pr = make_problem("c2", n=8)         # jittered
     with pytest.raises(DGMGError):
