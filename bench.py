@@ -36,6 +36,7 @@ WORKLOADS = {
           "and discrete adjoint (FP64, PCG to rel. residual 1e-13)",
 }
 MFMA_F32_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -76,7 +77,7 @@ def cheb_step_flops(info, nrhs):
 
 COUNTER_FILES = {
     "c2": "k_cheb_step_f32_b9_c2_counters.md",
-    "c3": "k_cheb_step_f32_b27_c3_counters.md",
+    "c3": "k_cheb_step_mf_f32_b27_c3_counters.md",
     "c4": "k_cheb_step_f32_b8_c4_counters.md",
     "c4x8": "k_cheb_step_mfma8_c4x8_counters.md",
 }
@@ -92,20 +93,25 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def profiled_traffic(workload):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when there is none or the kernel sources changed since
-    it was taken."""
+def profiled_counters(workload):
+    """Values of the committed counter summary of the dominant kernel
+    (traffic_bytes_per_launch, flops_per_launch), or {} when there is none or
+    the kernel sources changed since it was taken."""
     if workload not in COUNTER_FILES:
-        return None
+        return {}
     try:
         txt = open(os.path.join(ROOT, "profiles", COUNTER_FILES[workload])).read()
     except OSError:
-        return None
+        return {}
     vals = dict(l.split(": ", 1) for l in txt.splitlines() if ": " in l and not l.startswith(" "))
     if vals.get("kernel_source_sha256", "").strip() != kernel_source_sha():
-        return None
-    return float(vals["traffic_bytes_per_launch"])
+        return {}
+    return {k: float(vals[k]) for k in ("traffic_bytes_per_launch", "flops_per_launch") if k in vals}
+
+
+def profiled_traffic(workload):
+    """HBM bytes per launch of the dominant kernel, or None (see profiled_counters)."""
+    return profiled_counters(workload).get("traffic_bytes_per_launch")
 
 
 def _iapp(pr, t, nrhs):
@@ -403,6 +409,14 @@ def main():
                      "avg_launch_us_in_run": prof["in_run_ms"] * 1e3,
                      "launches_in_run": prof["launches"]},
     }
+    if info["fine_layout"] == "matrix_free":
+        # the sum-factorised kernel trades bytes for arithmetic: its FP32
+        # vector work (counted by rocprofv3) against the FP32 vector peak
+        fl = profiled_counters(args.workload).get("flops_per_launch")
+        out["roofline"]["alu"] = None if fl is None else {
+            "flops_per_launch": fl, "achieved_tflops": fl / per_launch_s / 1e12,
+            "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+            "frac": fl / per_launch_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
     if nrhs > 1:
         fl = cheb_step_flops(info, nrhs) / per_launch_s / 1e12
         out["roofline"]["mfma" if mfma else "valu"] = {

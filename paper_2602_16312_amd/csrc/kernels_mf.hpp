@@ -16,7 +16,10 @@
 //        f_val = (-s/2 (w_K + w_N) + sigma (u_K - u_N)) w,
 //        f_con = -s/2 (u_K - u_N) w   (tested against n.D_K grad v),
 //      with s = +1 when the neighbour is on the cell's upper side;
-//   3. thread I integrates all of them against its basis function.
+//   2b. per face and tangential node pair, the face fluxes are integrated
+//      against the tangential factors of the test functions;
+//   3. thread I integrates the cell terms against its basis function and
+//      adds the face terms times its normal factor.
 // Included by solver.hip after kernels.hpp.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -62,6 +65,7 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     __shared__ T Dn[TC][NF][D];                       // row a of the neighbour's D
     __shared__ T fq[TC][B][D + 1];
     __shared__ T ff[TC][NF][QF][D + 1];
+    __shared__ T fT[TC][NF][QF][2];                   // face fluxes integrated tangentially
     __shared__ int hasn[TC][NF];                      // face has a neighbour
     const int i = threadIdx.x - lc * B;
     const bool slot = lc < TC;                        // thread maps to a (possibly padded) cell slot
@@ -199,6 +203,30 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         }
     }
     __syncthreads();
+    // ---- phase 2b: per face and tangential node pair m = (m1, m2), the face
+    // fluxes integrated against the tangential factors of the test functions:
+    // fT[.][0] = sum_q (f_val tI + f_con_t1 t1' + f_con_t2 t2'), fT[.][1] =
+    // sum_q f_con_a tI; a test function then needs only its normal factor
+    if (slot) {
+        for (int it = i; it < NF * QF; it += B) {
+            const int f = it / QF, m = it - f * QF;
+            const int a = f >> 1;
+            const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+            const int m1 = m % Q, m2 = D == 3 ? m / Q : 0;
+            T sv = 0, sn = 0;
+            for (int qf = 0; qf < QF; ++qf) {
+                const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
+                const T i1 = C.Ig[g1 * Q + m1], i2 = D == 3 ? C.Ig[g2 * Q + m2] : T(1);
+                const T* F = ff[lc][f][qf];
+                sv += F[0] * i1 * i2 + F[1 + t1] * C.Dg[g1 * Q + m1] * i2;
+                if (D == 3) sv += F[1 + t2] * i1 * C.Dg[g2 * Q + m2];
+                sn += F[1 + a] * i1 * i2;
+            }
+            fT[lc][f][m][0] = sv;
+            fT[lc][f][m][1] = sn;
+        }
+    }
+    __syncthreads();
     // ---- phase 3: test against the thread's basis function I = i (direct
     // sums; with the loops unrolled the compiler keeps the 1D table entries
     // in registers, which measured faster than factorising the sums)
@@ -230,17 +258,10 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         for (int f = 0; f < NF; ++f) {
             const int a = f >> 1, eK = f & 1;
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-            const T vI = ik[a] == eK * (Q - 1) ? T(1) : T(0);   // trace of a Lobatto basis function
-            const T dI = C.Ed[eK * Q + ik[a]];
-            for (int qf = 0; qf < QF; ++qf) {
-                const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
-                const T tI = C.Ig[g1 * Q + ik[t1]] * (D == 3 ? C.Ig[g2 * Q + ik[t2]] : T(1));
-                const T t1d = C.Dg[g1 * Q + ik[t1]] * (D == 3 ? C.Ig[g2 * Q + ik[t2]] : T(1));
-                const T* F = ff[lc][f][qf];
-                T acc = F[0] * vI * tI + F[1 + a] * dI * tI + F[1 + t1] * vI * t1d;
-                if (D == 3) acc += F[1 + t2] * vI * C.Ig[g1 * Q + ik[t1]] * C.Dg[g2 * Q + ik[t2]];
-                y += acc;
-            }
+            const int m = ik[t1] + (D == 3 ? Q * ik[t2] : 0);
+            // normal factor: trace (0 or 1 at the Lobatto ends) and derivative
+            if (ik[a] == eK * (Q - 1)) y += fT[lc][f][m][0];
+            y += C.Ed[eK * Q + ik[a]] * fT[lc][f][m][1];
         }
     }
     return y;
