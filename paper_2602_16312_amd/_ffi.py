@@ -54,7 +54,8 @@ class MGOpts(C.Structure):
                 ("smooth_range", C.c_double), ("lam_override", dp),
                 ("precision", C.c_int32), ("device_setup", C.c_int32),
                 ("adjoint", C.c_int32), ("max_rhs", C.c_int32),
-                ("mfma", C.c_int32), ("fine_layout", C.c_int32)]
+                ("mfma", C.c_int32), ("fine_layout", C.c_int32),
+                ("setup_on_device", C.c_int32)]
 
 
 class SolverInfo(C.Structure):

@@ -123,21 +123,23 @@ class Solver:
                     fine_layout={1: "tile_ell", 2: "axis_ell", 3: "matrix_free"}.get(i.fine_layout,
                                                                                     "none"))
 
-    def export_level(self, level):
-        """Host copies of a level's FP64 operator and transfer blocks."""
+    def export_level(self, level, blocks=True):
+        """Host copies of a level's FP64 operator and transfer blocks
+        (blocks=False: the prolongation, parents and face list only)."""
         inf = self.info()
         b = inf["b"]
         n = inf["n_cells"][level]
         nf = inf["n_faces"][level]
-        diag = np.empty((n, b, b))
+        diag = np.empty((n, b, b)) if blocks else None
         fc = np.empty((nf, 2), dtype=np.int64)
-        fb = np.empty((nf, b, b))
+        fb = np.empty((nf, b, b)) if blocks else None
         last = level == inf["n_levels"] - 1
         P = None if last else np.empty((n, b, b))
         par = None if last else np.empty(n, dtype=np.int64)
         F.check(F.lib().dgmg_export_level(
-            self._s, level, diag.ctypes.data_as(F.dp), fc.ctypes.data_as(F.i64p),
-            fb.ctypes.data_as(F.dp), None if P is None else P.ctypes.data_as(F.dp),
+            self._s, level, None if diag is None else diag.ctypes.data_as(F.dp),
+            fc.ctypes.data_as(F.i64p), None if fb is None else fb.ctypes.data_as(F.dp),
+            None if P is None else P.ctypes.data_as(F.dp),
             None if par is None else par.ctypes.data_as(F.i64p)))
         return dict(diag=diag, face_cells=fc, face_blocks=fb, P=P, parents=par)
 
@@ -151,8 +153,12 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
                  bdf=2, cell_scale=None, precision="fp64", cheb_degree=3,
                  cheb_sweeps=3, lanczos_steps=20, lam_safety=1.2,
                  smooth_range=20.0, lam_override=None, device_setup=True, adjoint=False,
-                 max_rhs=1, mfma=False, fine_layout="auto"):
-    """dgmg_setup_levels: assembly, Galerkin hierarchy, smoother, coarse factor."""
+                 max_rhs=1, mfma=False, fine_layout="auto", setup="host"):
+    """dgmg_setup_levels: assembly, Galerkin hierarchy, smoother, coarse factor.
+    setup = "device" computes the prolongations, Galerkin products and Lanczos
+    estimates on the GPU, "host" on the CPU."""
+    if setup not in ("host", "device"):
+        raise ValueError("setup must be 'host' or 'device'")
     d = F.Disc(p, 0 if penalty[0] == "paper" else 1,
                float(penalty[1]) if len(penalty) > 1 else 0.0)
     D_cell, Dp = _dptr(D_cell)
@@ -169,7 +175,8 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
         keep.append(lam)
     mg = F.MGOpts(cheb_degree, cheb_sweeps, lanczos_steps, lam_safety, smooth_range,
                   lo, PRECISIONS[precision], 1 if device_setup else 0, 1 if adjoint else 0,
-                  int(max_rhs), 1 if mfma else 0, LAYOUTS[fine_layout])
+                  int(max_rhs), 1 if mfma else 0, LAYOUTS[fine_layout],
+                  1 if setup == "device" else 0)
     s = C.c_void_p()
     F.check(F.lib().dgmg_setup_levels(hier.handle, C.byref(d), C.byref(ph), C.byref(mg),
                                       C.byref(s)))

@@ -15,7 +15,7 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wno-unused-function",
           "-Wno-unused-result"]
 HOST_SOURCES = ["setup_fem.cpp", "setup_mg.cpp"]
-HIP_SOURCES = ["solver.hip"]
+HIP_SOURCES = ["solver.hip", "setup_dev.hip"]
 
 
 def _run(cmd):

@@ -83,10 +83,52 @@ void prolongation_blocks(const Hierarchy& h, const RefElement& re, int level,
                          const std::vector<double>& lo_c, const std::vector<double>& hi_c,
                          std::vector<double>& P);
 void level_boxes(const Hierarchy& h, int level, std::vector<double>& lo, std::vector<double>& hi);
+// Integer structure of A_{l+1} = P^T A_l P: the coarse face list (plus =
+// smaller coarse id) and, per coarse entity t (cells 0..n_coarse-1, then
+// faces), the fine contributions item[ptr[t]..ptr[t+1]) in summation order,
+// each (source << 2) | mode: mode 0 = P_e^T A_ee P_e of fine cell e = source;
+// for fine face f = source with T = P_{e+}^T A_f P_{e-}: 1 = T, 2 = T^T,
+// 3 = T + T^T (a face between two children of one agglomerate).
+struct GalerkinPlan {
+    std::vector<int64_t> ptr, item;
+};
+void galerkin_plan(const BlockOp& A, const std::vector<int64_t>& parent, int64_t n_coarse,
+                   BlockOp& Ac, GalerkinPlan& plan);
 void galerkin(const BlockOp& A, const std::vector<double>& P, const std::vector<int64_t>& parent,
               int64_t n_coarse, BlockOp& Ac);
 void host_apply(const BlockOp& A, const double* x, double* y);
+// per-cell face lists: faces of cell K are code[ptr[K]..ptr[K+1]),
+// code = face << 1 | (K is the minus side)
+void cell_face_lists(const BlockOp& A, std::vector<int64_t>& ptr, std::vector<int64_t>& code);
 double lanczos_theta_max(const BlockOp& A, int steps);
+// Largest eigenvalue of the symmetric tridiagonal matrix (a, off-diagonal bt).
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& bt);
+// Lanczos start vector: v_i = frac((i+1) * golden ratio conjugate) - 1/2, normalised
+void lanczos_start(int64_t n, std::vector<double>& v);
+
+// Device set-up (prolongation blocks, Galerkin products and Lanczos
+// estimates on the GPU); holds its device buffers until destroyed.
+class DeviceSetup {
+  public:
+    DeviceSetup(const Hierarchy& h, const RefElement& re);
+    ~DeviceSetup();
+    DeviceSetup(const DeviceSetup&) = delete;
+    DeviceSetup& operator=(const DeviceSetup&) = delete;
+    // P_l (level l -> l+1 blocks) on the device; host copy into P
+    void prolongation(int level, const std::vector<double>& lo_l, const std::vector<double>& hi_l,
+                      const std::vector<double>& lo_c, const std::vector<double>& hi_c,
+                      std::vector<double>& P);
+    // uploads the fine operator A_0
+    void set_fine(const BlockOp& A0);
+    // A_{l+1} = P_l^T A_l P_l on the device (needs A_l and P_l there); host copy into Ac
+    void galerkin(int level, const BlockOp& A, BlockOp& Ac);
+    // largest Ritz value of `steps` Lanczos steps on D^-1/2 A_l D^-1/2 (device A_l)
+    double lanczos_theta_max(int level, const BlockOp& A, int steps);
+
+  private:
+    struct Impl;
+    Impl* im;
+};
 // dense coarse operator, in-place lower Cholesky and explicit inverse
 void dense_from_blocks(const BlockOp& A, std::vector<double>& dense);
 void cholesky_inverse(std::vector<double>& a, int64_t n);

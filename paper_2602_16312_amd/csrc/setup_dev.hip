@@ -1,0 +1,453 @@
+// Device part of the set-up: the prolongation blocks (section 5.1, tensor
+// Lagrange bases on the agglomerates' bounding boxes), the blockwise Galerkin
+// products A_{l+1} = P^T A_l P (section 5.1, eq. inherited_matrices) and the
+// Lanczos estimate of the largest eigenvalue of D^-1 A_l that sets the
+// Chebyshev interval (section 6).  The host supplies the integer structure
+// (coarse face lists and the ordered contribution lists of every coarse
+// block); every floating-point operation of these phases runs here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace dgmg {
+namespace {
+
+#define DSCHK(expr)                                                                        \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            fail(DGMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+constexpr int kSW = 256;   // threads per workgroup of the vector kernels
+
+// ------------------------------------------------------------ prolongation
+// One thread per fine node (e, i): the physical position of node i of entity
+// e (the multilinear image of the Gauss-Lobatto reference node on level 0,
+// the node of the child's box above) and the coarse tensor basis of the
+// parent's box there; writes row i of P_e (B contiguous values).
+template <int D, int Q>
+__global__ __launch_bounds__(kSW) void k_prolong_blocks(int64_t n, int level0, const int64_t* __restrict__ cells,
+                                                      const double* __restrict__ xyz,
+                                                      const double* __restrict__ lo_l,
+                                                      const double* __restrict__ hi_l,
+                                                      const int64_t* __restrict__ parent,
+                                                      const double* __restrict__ lo_c,
+                                                      const double* __restrict__ hi_c,
+                                                      const double* __restrict__ nodes,
+                                                      double* __restrict__ P) {
+    constexpr int B = D == 2 ? Q * Q : Q * Q * Q;
+    constexpr int NC = 1 << D;
+    const int64_t r = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    if (r >= n * B) return;
+    const int64_t e = r / B;
+    const int i = (int)(r - e * B);
+    double xi[D], x[D];
+    {
+        int t = i;
+        for (int k = 0; k < D; ++k) {
+            xi[k] = nodes[t % Q];
+            t /= Q;
+        }
+    }
+    if (level0) {
+        for (int a = 0; a < D; ++a) x[a] = 0.0;
+        for (int c = 0; c < NC; ++c) {
+            double psi = 1.0;
+            for (int k = 0; k < D; ++k) psi *= ((c >> k) & 1) ? xi[k] : 1.0 - xi[k];
+            const int64_t v = cells[e * NC + c];
+            for (int a = 0; a < D; ++a) x[a] += xyz[v * D + a] * psi;
+        }
+    } else {
+        for (int k = 0; k < D; ++k) x[k] = lo_l[e * D + k] + xi[k] * (hi_l[e * D + k] - lo_l[e * D + k]);
+    }
+    const int64_t K = parent[e];
+    double l1[D][Q];
+    for (int k = 0; k < D; ++k) {
+        const double a = lo_c[K * D + k], w = hi_c[K * D + k] - a;
+        const double t = (x[k] - a) / w;
+        for (int j = 0; j < Q; ++j) {
+            double v = 1.0;
+            for (int m = 0; m < Q; ++m)
+                if (m != j) v *= (t - nodes[m]) / (nodes[j] - nodes[m]);
+            l1[k][j] = v;
+        }
+    }
+    double* out = P + r * B;
+    for (int j = 0; j < B; ++j) {
+        double v = 1.0;
+        int rj = j;
+        for (int k = 0; k < D; ++k) {
+            v *= l1[k][rj % Q];
+            rj /= Q;
+        }
+        out[j] = v;
+    }
+}
+
+// ---------------------------------------------------------------- Galerkin
+// One workgroup per coarse block (coarse cells first, then coarse faces).
+// For every contribution in list order: stage the fine block X and the two
+// prolongation blocks in LDS, Y = X P_c (held in registers, then written over
+// X), T = P_a^T Y, and accumulate T, T^T or T + T^T into the thread's entries
+// of the coarse block.  The order of every sum is fixed, so the result is
+// deterministic.
+template <int B, int NT>
+__global__ __launch_bounds__(NT) void k_galerkin(const double* __restrict__ Ad, const double* __restrict__ Af,
+                                                 const int64_t* __restrict__ fc,
+                                                 const double* __restrict__ P,
+                                                 const int64_t* __restrict__ ptr,
+                                                 const int64_t* __restrict__ item, int64_t nC,
+                                                 double* __restrict__ outd, double* __restrict__ outf) {
+    constexpr int BB = B * B, E = (BB + NT - 1) / NT;
+    __shared__ double sX[BB], sPa[BB], sPc[BB];
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    double acc[E];
+#pragma unroll
+    for (int u = 0; u < E; ++u) acc[u] = 0.0;
+    const int64_t i0 = ptr[t], i1 = ptr[t + 1];
+    for (int64_t it = i0; it < i1; ++it) {
+        const int64_t code = item[it];
+        const int mode = (int)(code & 3);
+        const int64_t src = code >> 2;
+        const double* X = (mode == 0 ? Ad : Af) + src * BB;
+        const int64_t ea = mode == 0 ? src : fc[2 * src];
+        const int64_t ec = mode == 0 ? src : fc[2 * src + 1];
+        for (int k = tid; k < BB; k += NT) {
+            sX[k] = X[k];
+            sPc[k] = P[ec * BB + k];
+            sPa[k] = P[ea * BB + k];
+        }
+        __syncthreads();
+        double y[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int k = tid + u * NT;
+            double s = 0.0;
+            if (k < BB) {
+                const int i = k / B, j = k - (k / B) * B;
+#pragma unroll 9
+                for (int m = 0; m < B; ++m) s += sX[i * B + m] * sPc[m * B + j];
+            }
+            y[u] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int k = tid + u * NT;
+            if (k < BB) sX[k] = y[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int k = tid + u * NT;
+            if (k < BB) {
+                const int i = k / B, j = k - (k / B) * B;
+                double tij = 0.0, tji = 0.0;
+                if (mode != 2) {
+#pragma unroll 9
+                    for (int m = 0; m < B; ++m) tij += sPa[m * B + i] * sX[m * B + j];
+                }
+                if (mode >= 2) {
+#pragma unroll 9
+                    for (int m = 0; m < B; ++m) tji += sPa[m * B + j] * sX[m * B + i];
+                }
+                acc[u] += mode == 3 ? tij + tji : (mode == 2 ? tji : tij);
+            }
+        }
+        __syncthreads();
+    }
+    double* out = t < nC ? outd + t * BB : outf + (t - nC) * BB;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        const int k = tid + u * NT;
+        if (k < BB) out[k] = acc[u];
+    }
+}
+
+// ----------------------------------------------------------------- Lanczos
+// Deterministic workgroup sum (wave shuffles, then the waves in order);
+// the result is valid in thread 0.
+__device__ double wg_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __shared__ double red[kSW / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kSW / 64; ++w) t += red[w];
+    return t;
+}
+
+// w = S A S v - beta vp (S = D^-1/2) with the raw blocks and per-cell face
+// lists; part[block] = partial (w, v).
+template <int B>
+__global__ __launch_bounds__(kSW) void k_lz_apply(int64_t n, const double* __restrict__ Ad,
+                                                const double* __restrict__ Af,
+                                                const int64_t* __restrict__ fc,
+                                                const int64_t* __restrict__ cptr,
+                                                const int64_t* __restrict__ code,
+                                                const double* __restrict__ s,
+                                                const double* __restrict__ v,
+                                                const double* __restrict__ vp, double beta,
+                                                double* __restrict__ w, double* __restrict__ part) {
+    constexpr int BB = B * B;
+    const int64_t r = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    double dv = 0.0;
+    if (r < n * B) {
+        const int64_t K = r / B;
+        const int i = (int)(r - K * B);
+        double y = 0.0;
+        const double* Dk = Ad + K * BB + i * B;
+        for (int j = 0; j < B; ++j) y += Dk[j] * (s[K * B + j] * v[K * B + j]);
+        for (int64_t e = cptr[K]; e < cptr[K + 1]; ++e) {
+            const int64_t f = code[e] >> 1;
+            const bool minus = (code[e] & 1) != 0;
+            const int64_t nb = minus ? fc[2 * f] : fc[2 * f + 1];
+            const double* F = Af + f * BB;
+            double fs = 0.0;
+            if (!minus)
+                for (int j = 0; j < B; ++j) fs += F[i * B + j] * (s[nb * B + j] * v[nb * B + j]);
+            else
+                for (int j = 0; j < B; ++j) fs += F[j * B + i] * (s[nb * B + j] * v[nb * B + j]);
+            y += fs;
+        }
+        const double wr = s[r] * y - beta * vp[r];
+        w[r] = wr;
+        dv = wr * v[r];
+    }
+    const double t = wg_sum(dv);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// w -= a v with a = sc[0]; part[block] = partial (w, w)
+__global__ __launch_bounds__(kSW) void k_lz_orth(int64_t m, const double* __restrict__ sc,
+                                               const double* __restrict__ v, double* __restrict__ w,
+                                               double* __restrict__ part) {
+    const int64_t r = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    double q = 0.0;
+    if (r < m) {
+        const double x = w[r] - sc[0] * v[r];
+        w[r] = x;
+        q = x * x;
+    }
+    const double t = wg_sum(q);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out[0] = sum of m partials (one workgroup, fixed order)
+__global__ __launch_bounds__(kSW) void k_lz_sum(int64_t m, const double* __restrict__ part,
+                                              double* __restrict__ out) {
+    double t = 0.0;
+    for (int64_t k = threadIdx.x; k < m; k += kSW) t += part[k];
+    t = wg_sum(t);
+    if (threadIdx.x == 0) out[0] = t;
+}
+
+// vp = v; v = w / beta
+__global__ __launch_bounds__(kSW) void k_lz_next(int64_t m, double beta, double* __restrict__ v,
+                                               double* __restrict__ vp, const double* __restrict__ w) {
+    const int64_t r = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    if (r < m) {
+        vp[r] = v[r];
+        v[r] = w[r] / beta;
+    }
+}
+
+template <typename T>
+T* dev_alloc(std::vector<void*>& owned, size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+        fail(DGMG_ENOMEM, "hipMalloc failed (device set-up)");
+    owned.push_back(p);
+    return (T*)p;
+}
+template <typename T>
+T* dev_upload(std::vector<void*>& owned, const std::vector<T>& h) {
+    T* d = dev_alloc<T>(owned, h.size());
+    if (!h.empty()) DSCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+template <typename T>
+void dev_download(std::vector<T>& h, const T* d, size_t count) {
+    h.resize(count);
+    if (count) DSCHK(hipMemcpy(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost));
+}
+
+unsigned grid_for(int64_t threads) { return (unsigned)((threads + kSW - 1) / kSW); }
+
+#define DS_DISPATCH_B(bval, ...)                                                       \
+    switch (bval) {                                                                    \
+        case 4: { constexpr int BV = 4; __VA_ARGS__; } break;                          \
+        case 8: { constexpr int BV = 8; __VA_ARGS__; } break;                          \
+        case 9: { constexpr int BV = 9; __VA_ARGS__; } break;                          \
+        case 16: { constexpr int BV = 16; __VA_ARGS__; } break;                        \
+        case 25: { constexpr int BV = 25; __VA_ARGS__; } break;                        \
+        case 27: { constexpr int BV = 27; __VA_ARGS__; } break;                        \
+        case 64: { constexpr int BV = 64; __VA_ARGS__; } break;                        \
+        default: fail(DGMG_EUNSUPPORTED, "unsupported block size");                    \
+    }
+
+}  // namespace
+
+struct DeviceSetup::Impl {
+    const Hierarchy& h;
+    int d = 0, q = 0, b = 0;
+    std::vector<void*> owned;
+    int64_t* cells = nullptr;
+    double *xyz = nullptr, *nodes = nullptr;
+    struct Op {
+        double *diag = nullptr, *fblk = nullptr;
+        int64_t* fc = nullptr;
+    };
+    std::vector<Op> ops;
+    std::vector<double*> P;
+    std::vector<int64_t*> parent;
+    Impl(const Hierarchy& hh) : h(hh) {}
+    ~Impl() {
+        for (void* p : owned) (void)hipFree(p);
+    }
+};
+
+DeviceSetup::DeviceSetup(const Hierarchy& h, const RefElement& re) : im(new Impl(h)) {
+    im->d = re.d;
+    im->q = re.q;
+    im->b = re.b;
+    im->ops.resize(h.n_levels);
+    im->P.assign(h.n_levels, nullptr);
+    im->parent.assign(h.n_levels, nullptr);
+    im->cells = dev_upload(im->owned, h.cells);
+    im->xyz = dev_upload(im->owned, h.xyz);
+    im->nodes = dev_upload(im->owned, re.nodes);
+}
+
+DeviceSetup::~DeviceSetup() { delete im; }
+
+void DeviceSetup::prolongation(int level, const std::vector<double>& lo_l, const std::vector<double>& hi_l,
+                               const std::vector<double>& lo_c, const std::vector<double>& hi_c,
+                               std::vector<double>& P) {
+    Impl& m = *im;
+    const int64_t n = m.h.n_ent[level];
+    const int b = m.b;
+    double* dlo_l = level ? dev_upload(m.owned, lo_l) : nullptr;
+    double* dhi_l = level ? dev_upload(m.owned, hi_l) : nullptr;
+    double* dlo_c = dev_upload(m.owned, lo_c);
+    double* dhi_c = dev_upload(m.owned, hi_c);
+    m.parent[level] = dev_upload(m.owned, m.h.parent[level]);
+    m.P[level] = dev_alloc<double>(m.owned, (size_t)n * b * b);
+    const unsigned g = grid_for(n * b);
+    const int l0 = level == 0 ? 1 : 0;
+#define DS_PROLONG(D_, Q_)                                                                              \
+    k_prolong_blocks<D_, Q_><<<g, kSW>>>(n, l0, m.cells, m.xyz, dlo_l, dhi_l, m.parent[level], dlo_c, \
+                                         dhi_c, m.nodes, m.P[level])
+    if (m.d == 2) {
+        switch (m.q) {
+            case 2: DS_PROLONG(2, 2); break;
+            case 3: DS_PROLONG(2, 3); break;
+            case 4: DS_PROLONG(2, 4); break;
+            case 5: DS_PROLONG(2, 5); break;
+            default: fail(DGMG_EUNSUPPORTED, "unsupported degree");
+        }
+    } else {
+        switch (m.q) {
+            case 2: DS_PROLONG(3, 2); break;
+            case 3: DS_PROLONG(3, 3); break;
+            case 4: DS_PROLONG(3, 4); break;
+            default: fail(DGMG_EUNSUPPORTED, "unsupported degree");
+        }
+    }
+#undef DS_PROLONG
+    DSCHK(hipGetLastError());
+    dev_download(P, m.P[level], (size_t)n * b * b);
+}
+
+void DeviceSetup::set_fine(const BlockOp& A0) {
+    Impl& m = *im;
+    m.ops[0].diag = dev_upload(m.owned, A0.diag);
+    m.ops[0].fblk = dev_upload(m.owned, A0.fblk);
+    m.ops[0].fc = dev_upload(m.owned, A0.fc);
+}
+
+void DeviceSetup::galerkin(int level, const BlockOp& A, BlockOp& Ac) {
+    Impl& m = *im;
+    if (!m.ops[level].diag || !m.P[level]) fail(DGMG_EINVAL, "device Galerkin product without A_l or P_l");
+    const int b = m.b, bb = b * b;
+    const int64_t nC = m.h.n_ent[level + 1];
+    GalerkinPlan plan;
+    galerkin_plan(A, m.h.parent[level], nC, Ac, plan);
+    int64_t* dptr = dev_upload(m.owned, plan.ptr);
+    int64_t* ditem = dev_upload(m.owned, plan.item);
+    Impl::Op& out = m.ops[level + 1];
+    out.diag = dev_alloc<double>(m.owned, (size_t)nC * bb);
+    out.fblk = dev_alloc<double>(m.owned, (size_t)Ac.nf * bb);
+    out.fc = dev_upload(m.owned, Ac.fc);
+    const int64_t nt = nC + Ac.nf;
+    const Impl::Op& in = m.ops[level];
+    if (nt > 0) {
+        DS_DISPATCH_B(b, {
+            constexpr int NT = BV * BV <= 64 ? 64 : (BV * BV <= 128 ? 128 : 256);
+            k_galerkin<BV, NT><<<(unsigned)nt, NT>>>(in.diag, in.fblk, in.fc, m.P[level], dptr, ditem, nC,
+                                                     out.diag, out.fblk);
+        });
+        DSCHK(hipGetLastError());
+    }
+    dev_download(Ac.diag, out.diag, (size_t)nC * bb);
+    dev_download(Ac.fblk, out.fblk, (size_t)Ac.nf * bb);
+}
+
+double DeviceSetup::lanczos_theta_max(int level, const BlockOp& A, int steps) {
+    Impl& m = *im;
+    const Impl::Op& op = m.ops[level];
+    if (!op.diag) fail(DGMG_EINVAL, "device Lanczos without A_l");
+    const int b = A.b;
+    const int64_t n = A.n * b;
+    std::vector<double> sh(n), v0;
+    for (int64_t K = 0; K < A.n; ++K)
+        for (int i = 0; i < b; ++i) sh[K * b + i] = 1.0 / std::sqrt(A.diag[((size_t)K * b + i) * b + i]);
+    lanczos_start(n, v0);
+    std::vector<int64_t> cptr, code;
+    cell_face_lists(A, cptr, code);
+    // work vectors are released with the set-up object; a level's vectors
+    // are small next to its blocks
+    double* s = dev_upload(m.owned, sh);
+    double* v = dev_upload(m.owned, v0);
+    double* vp = dev_alloc<double>(m.owned, n);
+    DSCHK(hipMemset(vp, 0, n * sizeof(double)));
+    double* w = dev_alloc<double>(m.owned, n);
+    const unsigned g = grid_for(n);
+    double* part = dev_alloc<double>(m.owned, g);
+    double* sc = dev_alloc<double>(m.owned, 2);
+    int64_t* dptr = dev_upload(m.owned, cptr);
+    int64_t* dcode = dev_upload(m.owned, code);
+    std::vector<double> al, be;
+    double beta = 0.0;
+    const int64_t mmax = std::min<int64_t>(steps, n);
+    for (int64_t j = 0; j < mmax; ++j) {
+        DS_DISPATCH_B(b, {
+            k_lz_apply<BV><<<g, kSW>>>(A.n, op.diag, op.fblk, op.fc, dptr, dcode, s, v, vp, beta, w, part);
+        });
+        k_lz_sum<<<1, kSW>>>(g, part, sc);
+        k_lz_orth<<<g, kSW>>>(n, sc, v, w, part);
+        k_lz_sum<<<1, kSW>>>(g, part, sc + 1);
+        DSCHK(hipGetLastError());
+        double hs[2];
+        DSCHK(hipMemcpy(hs, sc, sizeof(hs), hipMemcpyDeviceToHost));
+        al.push_back(hs[0]);
+        beta = std::sqrt(hs[1]);
+        if (beta < 1e-14 || j == mmax - 1) break;
+        be.push_back(beta);
+        k_lz_next<<<g, kSW>>>(n, beta, v, vp, w);
+    }
+    DSCHK(hipGetLastError());
+    be.resize(al.size() > 0 ? al.size() - 1 : 0);
+    if (al.size() == 1) return al[0];
+    return tridiag_max_eig(al, be);
+}
+
+}  // namespace dgmg

@@ -108,36 +108,15 @@ static void ab(int b, const double* A, const double* B, double* C) {
         }
 }
 
-// Blockwise A_{l+1} = P^T A_l P.  A cell block of the coarse operator sums
-// P_e^T A_ee P_e over its children and the face terms between two children;
-// a coarse face block sums P_{e+}^T A_f P_{e-} over fine faces joining two
-// different agglomerates (stored with plus = smaller coarse id).
-void galerkin(const BlockOp& A, const std::vector<double>& P, const std::vector<int64_t>& parent,
-              int64_t nC, BlockOp& Ac) {
-    const int b = A.b, bb = b * b;
+// Integer structure of the blockwise A_{l+1} = P^T A_l P.  A coarse cell
+// block sums P_e^T A_ee P_e over its children (ascending e), then the face
+// terms between two of its children (ascending f); a coarse face block sums
+// P_{e+}^T A_f P_{e-} over the fine faces joining two different agglomerates
+// (ascending f), stored with plus = smaller coarse id.
+void galerkin_plan(const BlockOp& A, const std::vector<int64_t>& parent, int64_t nC, BlockOp& Ac,
+                   GalerkinPlan& plan) {
     Ac.n = nC;
-    Ac.b = b;
-    Ac.diag.assign((size_t)nC * bb, 0.0);
-    // children lists
-    std::vector<int64_t> cptr(nC + 1, 0), clist(A.n);
-    for (int64_t e = 0; e < A.n; ++e) cptr[parent[e] + 1]++;
-    for (int64_t K = 0; K < nC; ++K) cptr[K + 1] += cptr[K];
-    {
-        std::vector<int64_t> pos(cptr.begin(), cptr.end() - 1);
-        for (int64_t e = 0; e < A.n; ++e) clist[pos[parent[e]]++] = e;
-    }
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t K = 0; K < nC; ++K) {
-        std::vector<double> t1(bb), t2(bb);
-        double* out = &Ac.diag[(size_t)K * bb];
-        for (int64_t c = cptr[K]; c < cptr[K + 1]; ++c) {
-            const int64_t e = clist[c];
-            ab(b, &A.diag[(size_t)e * bb], &P[(size_t)e * bb], t1.data());
-            atb(b, &P[(size_t)e * bb], t1.data(), t2.data());
-            for (int k = 0; k < bb; ++k) out[k] += t2[k];
-        }
-    }
-    // coarse face keys
+    Ac.b = A.b;
     std::vector<int64_t> key(A.nf);
     for (int64_t f = 0; f < A.nf; ++f) {
         int64_t Kp = parent[A.fc[2 * f]], Km = parent[A.fc[2 * f + 1]];
@@ -154,33 +133,57 @@ void galerkin(const BlockOp& A, const std::vector<double>& P, const std::vector<
         Ac.fc[2 * g] = ukeys[g] / nC;
         Ac.fc[2 * g + 1] = ukeys[g] % nC;
     }
-    Ac.fblk.assign((size_t)Ac.nf * bb, 0.0);
-    const int64_t chunk = 8192;
-    std::vector<double> T((size_t)chunk * bb);
-    for (int64_t f0 = 0; f0 < A.nf; f0 += chunk) {
-        const int64_t f1 = std::min(A.nf, f0 + chunk);
+    // target entity of every fine cell and face
+    std::vector<int64_t> tf(A.nf);
 #pragma omp parallel for schedule(static)
-        for (int64_t f = f0; f < f1; ++f) {
-            std::vector<double> t1(bb);
-            const int64_t ep = A.fc[2 * f], em = A.fc[2 * f + 1];
-            ab(b, &A.fblk[(size_t)f * bb], &P[(size_t)em * bb], t1.data());
-            atb(b, &P[(size_t)ep * bb], t1.data(), &T[(size_t)(f - f0) * bb]);
-        }
-        for (int64_t f = f0; f < f1; ++f) {
-            const double* t = &T[(size_t)(f - f0) * bb];
-            const int64_t Kp = parent[A.fc[2 * f]], Km = parent[A.fc[2 * f + 1]];
-            if (Kp == Km) {
-                double* out = &Ac.diag[(size_t)Kp * bb];
-                for (int i = 0; i < b; ++i)
-                    for (int j = 0; j < b; ++j) out[i * b + j] += t[i * b + j] + t[j * b + i];
-            } else {
-                int64_t g = std::lower_bound(ukeys.begin(), ukeys.end(), key[f]) - ukeys.begin();
-                double* out = &Ac.fblk[(size_t)g * bb];
-                if (Kp < Km)
+    for (int64_t f = 0; f < A.nf; ++f)
+        tf[f] = key[f] < 0 ? parent[A.fc[2 * f]]
+                           : nC + (std::lower_bound(ukeys.begin(), ukeys.end(), key[f]) - ukeys.begin());
+    const int64_t nt = nC + Ac.nf;
+    plan.ptr.assign(nt + 1, 0);
+    for (int64_t e = 0; e < A.n; ++e) plan.ptr[parent[e] + 1]++;
+    for (int64_t f = 0; f < A.nf; ++f) plan.ptr[tf[f] + 1]++;
+    for (int64_t t = 0; t < nt; ++t) plan.ptr[t + 1] += plan.ptr[t];
+    plan.item.resize(plan.ptr[nt]);
+    std::vector<int64_t> pos(plan.ptr.begin(), plan.ptr.end() - 1);
+    for (int64_t e = 0; e < A.n; ++e) plan.item[pos[parent[e]]++] = e << 2;
+    for (int64_t f = 0; f < A.nf; ++f) {
+        const int64_t Kp = parent[A.fc[2 * f]], Km = parent[A.fc[2 * f + 1]];
+        const int mode = Kp == Km ? 3 : (Kp < Km ? 1 : 2);
+        plan.item[pos[tf[f]]++] = (f << 2) | mode;
+    }
+}
+
+void galerkin(const BlockOp& A, const std::vector<double>& P, const std::vector<int64_t>& parent,
+              int64_t nC, BlockOp& Ac) {
+    GalerkinPlan plan;
+    galerkin_plan(A, parent, nC, Ac, plan);
+    const int b = A.b, bb = b * b;
+    Ac.diag.assign((size_t)nC * bb, 0.0);
+    Ac.fblk.assign((size_t)Ac.nf * bb, 0.0);
+    const int64_t nt = nC + Ac.nf;
+#pragma omp parallel
+    {
+        std::vector<double> t1(bb), t(bb);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t u = 0; u < nt; ++u) {
+            double* out = u < nC ? &Ac.diag[(size_t)u * bb] : &Ac.fblk[(size_t)(u - nC) * bb];
+            for (int64_t it = plan.ptr[u]; it < plan.ptr[u + 1]; ++it) {
+                const int64_t src = plan.item[it] >> 2;
+                const int mode = (int)(plan.item[it] & 3);
+                const double* X = mode == 0 ? &A.diag[(size_t)src * bb] : &A.fblk[(size_t)src * bb];
+                const int64_t ea = mode == 0 ? src : A.fc[2 * src];
+                const int64_t ec = mode == 0 ? src : A.fc[2 * src + 1];
+                ab(b, X, &P[(size_t)ec * bb], t1.data());
+                atb(b, &P[(size_t)ea * bb], t1.data(), t.data());
+                if (mode <= 1)
                     for (int k = 0; k < bb; ++k) out[k] += t[k];
-                else
+                else if (mode == 2)
                     for (int i = 0; i < b; ++i)
                         for (int j = 0; j < b; ++j) out[i * b + j] += t[j * b + i];
+                else
+                    for (int i = 0; i < b; ++i)
+                        for (int j = 0; j < b; ++j) out[i * b + j] += t[i * b + j] + t[j * b + i];
             }
         }
     }
@@ -192,19 +195,22 @@ struct CellFaces {
 };
 static CellFaces cell_faces(const BlockOp& A) {
     CellFaces C;
-    C.ptr.assign(A.n + 1, 0);
-    for (int64_t f = 0; f < A.nf; ++f) {
-        C.ptr[A.fc[2 * f] + 1]++;
-        C.ptr[A.fc[2 * f + 1] + 1]++;
-    }
-    for (int64_t K = 0; K < A.n; ++K) C.ptr[K + 1] += C.ptr[K];
-    C.code.resize(C.ptr[A.n]);
-    std::vector<int64_t> pos(C.ptr.begin(), C.ptr.end() - 1);
-    for (int64_t f = 0; f < A.nf; ++f) {
-        C.code[pos[A.fc[2 * f]]++] = f << 1;
-        C.code[pos[A.fc[2 * f + 1]]++] = (f << 1) | 1;
-    }
+    cell_face_lists(A, C.ptr, C.code);
     return C;
+}
+void cell_face_lists(const BlockOp& A, std::vector<int64_t>& ptr, std::vector<int64_t>& code) {
+    ptr.assign(A.n + 1, 0);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        ptr[A.fc[2 * f] + 1]++;
+        ptr[A.fc[2 * f + 1] + 1]++;
+    }
+    for (int64_t K = 0; K < A.n; ++K) ptr[K + 1] += ptr[K];
+    code.resize(ptr[A.n]);
+    std::vector<int64_t> pos(ptr.begin(), ptr.end() - 1);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        code[pos[A.fc[2 * f]]++] = f << 1;
+        code[pos[A.fc[2 * f + 1]]++] = (f << 1) | 1;
+    }
 }
 
 static void apply_with(const BlockOp& A, const CellFaces& C, const double* x, double* y) {
@@ -238,7 +244,7 @@ void host_apply(const BlockOp& A, const double* x, double* y) { apply_with(A, ce
 
 // Largest eigenvalue of a symmetric tridiagonal matrix by Sturm-sequence
 // bisection (count of eigenvalues below a shift).
-static double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& bt) {
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& bt) {
     const int m = (int)a.size();
     double lo = INFINITY, hi = -INFINITY;
     for (int i = 0; i < m; ++i) {
@@ -266,6 +272,18 @@ static double tridiag_max_eig(const std::vector<double>& a, const std::vector<do
     return 0.5 * (lo + hi);
 }
 
+void lanczos_start(int64_t n, std::vector<double>& v) {
+    v.resize(n);
+    double nrm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = ((double)i + 1.0) * 0.6180339887498949;
+        v[i] = t - std::floor(t) - 0.5;
+        nrm += v[i] * v[i];
+    }
+    nrm = std::sqrt(nrm);
+    for (auto& x : v) x /= nrm;
+}
+
 // m Lanczos steps on D^-1/2 A D^-1/2 without reorthogonalisation, start
 // vector frac((i+1) * golden ratio conjugate) - 1/2, early stop when the next
 // beta falls below 1e-14; returns the largest Ritz value.
@@ -275,14 +293,7 @@ double lanczos_theta_max(const BlockOp& A, int steps) {
     std::vector<double> s(n), v(n), vp(n, 0.0), w(n), tmp(n);
     for (int64_t K = 0; K < A.n; ++K)
         for (int i = 0; i < b; ++i) s[K * b + i] = 1.0 / std::sqrt(A.diag[((size_t)K * b + i) * b + i]);
-    double nrm = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        double t = ((double)i + 1.0) * 0.6180339887498949;
-        v[i] = t - std::floor(t) - 0.5;
-        nrm += v[i] * v[i];
-    }
-    nrm = std::sqrt(nrm);
-    for (auto& x : v) x /= nrm;
+    lanczos_start(n, v);
     std::vector<double> al, be;
     double beta = 0.0;
     const int64_t mmax = std::min<int64_t>(steps, n);

@@ -190,6 +190,7 @@ template <typename T>
 static std::vector<T> to_colmajor(const std::vector<double>& a, int b) {
     const size_t bb = (size_t)b * b, nblk = a.size() / bb, bs = block_stride<T>(b);
     std::vector<T> out(nblk * bs, (T)0);
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < nblk; ++k)
         for (int i = 0; i < b; ++i)
             for (int j = 0; j < b; ++j) out[k * bs + (size_t)j * b + i] = (T)a[k * bb + (size_t)i * b + j];
@@ -725,24 +726,16 @@ struct AxisEll {
     std::vector<int32_t> up, lo;
     std::vector<double> vals;
 };
-static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, int d) {
+static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, int d, bool with_vals) {
     const int b = A.b, TC = kWG / b, TR = TC * b, NS = 1 + d;
     const int64_t n = A.n, ntiles = (n + TC - 1) / TC;
     if ((int64_t)axis.size() != A.nf) fail(DGMG_EINVAL, "face axis list does not match the operator");
     AxisEll E;
-    E.vals.assign((size_t)ntiles * NS * b * TR, 0.0);
     E.up.resize((size_t)d * n);
     E.lo.assign((size_t)d * n, -1);
+    std::vector<int64_t> upface((size_t)d * n, -1);   // face on the upper a-side of each cell
     for (int a = 0; a < d; ++a)
         for (int64_t c = 0; c < n; ++c) E.up[(size_t)a * n + c] = (int32_t)c;
-    auto put = [&](int64_t c, int slot, const double* blk) {
-        const int64_t t = c / TC;
-        const int lc = (int)(c - t * TC);
-        for (int i = 0; i < b; ++i)
-            for (int j = 0; j < b; ++j)
-                E.vals[(((size_t)t * NS + slot) * b + j) * TR + (size_t)lc * b + i] = blk[(size_t)i * b + j];
-    };
-    for (int64_t c = 0; c < n; ++c) put(c, 0, &A.diag[(size_t)c * b * b]);
     for (int64_t f = 0; f < A.nf; ++f) {
         const int64_t p = A.fc[2 * f], m = A.fc[2 * f + 1];
         const int a = axis[f];
@@ -751,7 +744,24 @@ static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, in
             fail(DGMG_EUNSUPPORTED, "two faces on one side of a cell");
         E.up[(size_t)a * n + p] = (int32_t)m;
         E.lo[(size_t)a * n + m] = (int32_t)p;
-        put(p, 1 + a, &A.fblk[(size_t)f * b * b]);
+        upface[(size_t)a * n + p] = f;
+    }
+    if (!with_vals) return E;
+    E.vals.assign((size_t)ntiles * NS * b * TR, 0.0);
+    auto put = [&](int64_t c, int slot, const double* blk) {
+        const int64_t t = c / TC;
+        const int lc = (int)(c - t * TC);
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j)
+                E.vals[(((size_t)t * NS + slot) * b + j) * TR + (size_t)lc * b + i] = blk[(size_t)i * b + j];
+    };
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        put(c, 0, &A.diag[(size_t)c * b * b]);
+        for (int a = 0; a < d; ++a) {
+            const int64_t f = upface[(size_t)a * n + c];
+            if (f >= 0) put(c, 1 + a, &A.fblk[(size_t)f * b * b]);
+        }
     }
     return E;
 }
@@ -762,6 +772,7 @@ static std::vector<T> interleave_P(const std::vector<double>& P, int b, int64_t 
     const int TC = kWG / b, TR = TC * b;
     const int64_t ntiles = (n + TC - 1) / TC;
     std::vector<T> out((size_t)ntiles * b * TR, (T)0);
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < n; ++e) {
         const int64_t t = e / TC;
         const int lc = (int)(e - t * TC);
@@ -774,7 +785,10 @@ static std::vector<T> interleave_P(const std::vector<double>& P, int b, int64_t 
 
 template <typename T>
 static std::vector<T> convert(const std::vector<double>& a) {
-    return std::vector<T>(a.begin(), a.end());
+    std::vector<T> out(a.size());
+#pragma omp parallel for schedule(static)
+    for (size_t k = 0; k < a.size(); ++k) out[k] = (T)a[k];
+    return out;
 }
 
 // Fills the strict upper triangle (column-major view) of an n x n matrix
@@ -888,7 +902,7 @@ static void upload_level(dgmg_solver* s, int l) {
     const bool ax = l == 0 && !mf && s->fine_layout != DGMG_LAYOUT_TILE_ELL && !s->axis0.empty();
     if (mf) {
         // neighbours as in the axis-ELL layout; no operator values are stored
-        AxisEll E = build_axis_ell(A, s->axis0, s->dim);
+        AxisEll E = build_axis_ell(A, s->axis0, s->dim, false);
         L.mf = true;
         L.up = s->upload(E.up);
         L.lo = s->upload(E.lo);
@@ -901,7 +915,7 @@ static void upload_level(dgmg_solver* s, int l) {
             L.mf32 = mf_constants<float>(s, re, s->upload(convert<float>(s->mf_D)));
         }
     } else if (ax) {
-        AxisEll E = build_axis_ell(A, s->axis0, s->dim);
+        AxisEll E = build_axis_ell(A, s->axis0, s->dim, true);
         L.ax = true;
         L.up = s->upload(E.up);
         L.lo = s->upload(E.lo);
@@ -1233,6 +1247,12 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
             for (int64_t c = 0; c < h->n_cells; ++c)
                 for (int k = 0; k < np; ++k) s->mf_D[(size_t)c * np + k] *= ph->cell_scale[c];
     }
+    // prolongation blocks, Galerkin products and Lanczos estimates on the GPU
+    std::unique_ptr<DeviceSetup> ds;
+    if (mg->setup_on_device) {
+        if (!mg->device_setup) fail(DGMG_EINVAL, "setup_on_device needs device_setup");
+        ds.reset(new DeviceSetup(*h, re));
+    }
     double t1 = now_s();
     s->info.t_assembly = t1 - t0;
     // boxes and prolongations
@@ -1241,10 +1261,21 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     double t2 = now_s();
     s->info.t_hierarchy = t2 - t1;
     s->Ph.resize(s->L);
-    for (int l = 0; l + 1 < s->L; ++l) prolongation_blocks(*h, re, l, lo[l], hi[l], lo[l + 1], hi[l + 1], s->Ph[l]);
+    for (int l = 0; l + 1 < s->L; ++l) {
+        if (ds)
+            ds->prolongation(l, lo[l], hi[l], lo[l + 1], hi[l + 1], s->Ph[l]);
+        else
+            prolongation_blocks(*h, re, l, lo[l], hi[l], lo[l + 1], hi[l + 1], s->Ph[l]);
+    }
     double t3 = now_s();
     s->info.t_transfer = t3 - t2;
-    for (int l = 0; l + 1 < s->L; ++l) galerkin(s->ops[l], s->Ph[l], h->parent[l], h->n_ent[l + 1], s->ops[l + 1]);
+    if (ds && s->L > 1) ds->set_fine(s->ops[0]);
+    for (int l = 0; l + 1 < s->L; ++l) {
+        if (ds)
+            ds->galerkin(l, s->ops[l], s->ops[l + 1]);
+        else
+            galerkin(s->ops[l], s->Ph[l], h->parent[l], h->n_ent[l + 1], s->ops[l + 1]);
+    }
     double t4 = now_s();
     s->info.t_galerkin = t4 - t3;
     s->lv.resize(s->L);
@@ -1253,13 +1284,15 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
             s->lv[l].lam_lo = mg->lam_override[2 * l];
             s->lv[l].lam_hi = mg->lam_override[2 * l + 1];
         } else {
-            const double th = lanczos_theta_max(s->ops[l], mg->lanczos_steps);
+            const double th = ds ? ds->lanczos_theta_max(l, s->ops[l], mg->lanczos_steps)
+                                 : lanczos_theta_max(s->ops[l], mg->lanczos_steps);
             s->lv[l].lam_hi = mg->lam_safety * th;
             s->lv[l].lam_lo = s->lv[l].lam_hi / mg->smooth_range;
         }
         if (!(s->lv[l].lam_hi > s->lv[l].lam_lo) || !(s->lv[l].lam_lo > 0))
             fail(DGMG_EINVAL, "invalid Chebyshev interval");
     }
+    ds.reset();
     double t5 = now_s();
     s->info.t_smoother = t5 - t4;
     std::vector<double> Ac;

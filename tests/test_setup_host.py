@@ -110,3 +110,14 @@ def test_paper_2d_test_dof_counts():
         pr = make_problem("e1", p=p)
         h, s = problem.build(pr, device_setup=False)
         assert s.info()["n_dofs"] == table["dofs"][str(p)]
+
+
+def test_device_setup_option_needs_device_data():
+    """The GPU set-up of the hierarchy is rejected without device set-up, and
+    unknown set-up places are rejected by the binding."""
+    from paper_2602_16312_amd._ffi import DGMGError
+    pr = make_problem("c1", n=8)
+    with pytest.raises(DGMGError):
+        problem.build(pr, device_setup=False, setup="device")
+    with pytest.raises(ValueError):
+        problem.build(pr, device_setup=False, setup="gpu")
