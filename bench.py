@@ -88,7 +88,7 @@ def kernel_source_sha():
     the kernels they were taken on)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hpp", "kernels_multi.hpp"):
+    for name in ("kernels.hpp", "kernels_multi.hpp", "kernels_mf.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2602_16312_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
