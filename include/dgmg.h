@@ -149,11 +149,12 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * axis-aligned boxes only, single-column calls only; DGMG_EUNSUPPORTED
  * otherwise) stores no fine-level operator: the cell, face and mass terms
  * are evaluated by sum factorisation from the per-cell conductivity.
- * setup_on_device = 1 (needs device_setup = 1) computes the prolongation
- * blocks, the Galerkin products A_{l+1} = P^T A_l P and the Lanczos
- * estimates on the GPU (the host supplies their integer structure; the
- * coarse blocks are copied back for packing and inspection); 0 computes
- * them on the host.  Both sum in the same order per coarse block. */
+ * setup_on_device = 1 (needs device_setup = 1) computes the fine operator
+ * and mass blocks (except with adjoint = 1), the prolongation blocks, the
+ * Galerkin products A_{l+1} = P^T A_l P and the Lanczos estimates on the
+ * GPU (the host supplies their integer structure; the blocks are copied
+ * back for packing and inspection); 0 computes them on the host.  Both sum
+ * in the same order per block. */
 typedef struct {
     int32_t cheb_degree;
     int32_t cheb_sweeps;

@@ -30,6 +30,17 @@ struct RefElement {
     void init(int dim, int deg);
 };
 
+// Face rule of each axis on the reference cell: for axis a and face point
+// iq, the reference points on the upper (xi_a = 1, "plus" side of a face) and
+// lower (xi_a = 0, "minus" side) cell faces, the weight, and the basis values
+// and reference gradients there ([d][qf][...] arrays).
+struct FaceRef {
+    int qf = 0;                                   // (p+1)^(d-1) points per face
+    std::vector<double> xi_p, xi_m, w;            // [d][qf][d], [d][qf][d], [d][qf]
+    std::vector<double> phi_p, phi_m, g_p, g_m;   // [d][qf][b], [d][qf][b][d]
+    void init(const RefElement& re);
+};
+
 // 1D Lagrange values and derivatives on `nodes` at x.
 void lagrange1d(const std::vector<double>& nodes, double x, double* val, double* der);
 // tensor basis values (and gradients if grad != nullptr) at reference point xi
@@ -118,8 +129,12 @@ class DeviceSetup {
     void prolongation(int level, const std::vector<double>& lo_l, const std::vector<double>& hi_l,
                       const std::vector<double>& lo_c, const std::vector<double>& hi_c,
                       std::vector<double>& P);
-    // uploads the fine operator A_0
+    // uploads the fine operator A_0 (unless it was assembled on the device)
     void set_fine(const BlockOp& A0);
+    // A_0 = cM M + A and the mass blocks assembled on the device (the blocks
+    // stay there for the Galerkin products); host copies into A0 and mass.
+    void assemble_fine(const Faces& F, const RefElement& re, const dgmg_disc& disc,
+                       const dgmg_physics& ph, double cM, BlockOp& A0, std::vector<double>& mass);
     // A_{l+1} = P_l^T A_l P_l on the device (needs A_l and P_l there); host copy into Ac
     void galerkin(int level, const BlockOp& A, BlockOp& Ac);
     // largest Ritz value of `steps` Lanczos steps on D^-1/2 A_l D^-1/2 (device A_l)

@@ -460,8 +460,20 @@ __global__ __launch_bounds__(kWG) void k_dot(int64_t N, const double* __restrict
 __global__ __launch_bounds__(kWG) void k_finalize(int32_t np, const double* __restrict__ partial,
                                                   double* __restrict__ sc, int slot, int mode) {
     __shared__ double red[kWG];
+    // eight independent running sums keep eight loads in flight per thread
+    constexpr int U = 8;
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = 0.0;
+    int k = threadIdx.x;
+    for (; k + (U - 1) * kWG < np; k += U * kWG) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] += partial[k + u * kWG];
+    }
+    for (; k < np; k += kWG) a[0] += partial[k];
     double s = 0.0;
-    for (int k = threadIdx.x; k < np; k += kWG) s += partial[k];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += a[u];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kWG / 2; w > 0; w >>= 1) {

@@ -536,13 +536,27 @@ template <int R>
 __global__ __launch_bounds__(kWG) void k_finalize_m(int32_t np, const double* __restrict__ partial,
                                                     double* __restrict__ sc, int slot, int mode) {
     __shared__ double red[kWG][R + 1];
+    // four independent running sums per column keep 4 R loads in flight
+    constexpr int U = 4;
+    double a[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[u][q] = 0.0;
+    int k = threadIdx.x;
+    for (; k + (U - 1) * kWG < np; k += U * kWG) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < R; ++q) a[u][q] += partial[(size_t)(k + u * kWG) * R + q];
+    }
+    for (; k < np; k += kWG) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[0][q] += partial[(size_t)k * R + q];
+    }
     double s[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) s[q] = 0.0;
-    for (int k = threadIdx.x; k < np; k += kWG) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) s[q] += partial[(size_t)k * R + q];
-    }
+    for (int q = 0; q < R; ++q) s[q] = (a[0][q] + a[1][q]) + (a[2][q] + a[3][q]);
 #pragma unroll
     for (int q = 0; q < R; ++q) red[threadIdx.x][q] = s[q];
     __syncthreads();

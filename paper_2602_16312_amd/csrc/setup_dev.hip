@@ -1,15 +1,18 @@
-// Device part of the set-up: the prolongation blocks (section 5.1, tensor
-// Lagrange bases on the agglomerates' bounding boxes), the blockwise Galerkin
-// products A_{l+1} = P^T A_l P (section 5.1, eq. inherited_matrices) and the
-// Lanczos estimate of the largest eigenvalue of D^-1 A_l that sets the
-// Chebyshev interval (section 6).  The host supplies the integer structure
-// (coarse face lists and the ordered contribution lists of every coarse
-// block); every floating-point operation of these phases runs here.
+// Device part of the set-up: the fine SIPDG operator and mass blocks
+// (section 3 and eq. fully_discrete), the prolongation blocks (section 5.1,
+// tensor Lagrange bases on the agglomerates' bounding boxes), the blockwise
+// Galerkin products A_{l+1} = P^T A_l P (section 5.1, eq.
+// inherited_matrices) and the Lanczos estimate of the largest eigenvalue of
+// D^-1 A_l that sets the Chebyshev interval (section 6).  The host supplies
+// the integer structure (face lists, coarse face lists and the ordered
+// contribution lists of every coarse block) and the reference-element
+// tables; every floating-point operation of these phases runs here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -260,6 +263,280 @@ __global__ __launch_bounds__(kSW) void k_lz_next(int64_t m, double beta, double*
     }
 }
 
+// ------------------------------------------------------------ fine assembly
+// (section 3: the SIPDG form a_h with the Gauss-Legendre rules of each cell
+// and face, multilinear geometry, per-cell conductivities; the mass term of
+// eq. fully_discrete)
+
+// Jacobian J[a][k] = dx_a/dxi_k of the multilinear map at xi, its
+// determinant and the inverse transpose.
+template <int D>
+__device__ void dev_cell_map(const double* X, const double* xi, double* J, double* det, double* JinvT) {
+    constexpr int NC = 1 << D;
+    for (int a = 0; a < D * D; ++a) J[a] = 0.0;
+    for (int c = 0; c < NC; ++c) {
+        double f[D], df[D];
+        for (int k = 0; k < D; ++k) {
+            const int bit = (c >> k) & 1;
+            f[k] = bit ? xi[k] : 1.0 - xi[k];
+            df[k] = bit ? 1.0 : -1.0;
+        }
+        for (int k = 0; k < D; ++k) {
+            double g = df[k];
+            for (int m = 0; m < D; ++m)
+                if (m != k) g *= f[m];
+            for (int a = 0; a < D; ++a) J[a * D + k] += X[c * D + a] * g;
+        }
+    }
+    if constexpr (D == 2) {
+        const double dt = J[0] * J[3] - J[1] * J[2];
+        *det = dt;
+        JinvT[0] = J[3] / dt;
+        JinvT[1] = -J[2] / dt;
+        JinvT[2] = -J[1] / dt;
+        JinvT[3] = J[0] / dt;
+    } else {
+        const double *r0 = J, *r1 = J + 3, *r2 = J + 6;
+        const double c00 = r1[1] * r2[2] - r1[2] * r2[1];
+        const double c01 = r1[2] * r2[0] - r1[0] * r2[2];
+        const double c02 = r1[0] * r2[1] - r1[1] * r2[0];
+        const double c10 = r0[2] * r2[1] - r0[1] * r2[2];
+        const double c11 = r0[0] * r2[2] - r0[2] * r2[0];
+        const double c12 = r0[1] * r2[0] - r0[0] * r2[1];
+        const double c20 = r0[1] * r1[2] - r0[2] * r1[1];
+        const double c21 = r0[2] * r1[0] - r0[0] * r1[2];
+        const double c22 = r0[0] * r1[1] - r0[1] * r1[0];
+        const double dt = r0[0] * c00 + r0[1] * c01 + r0[2] * c02;
+        *det = dt;
+        JinvT[0] = c00 / dt; JinvT[1] = c01 / dt; JinvT[2] = c02 / dt;
+        JinvT[3] = c10 / dt; JinvT[4] = c11 / dt; JinvT[5] = c12 / dt;
+        JinvT[6] = c20 / dt; JinvT[7] = c21 / dt; JinvT[8] = c22 / dt;
+    }
+}
+
+template <int D>
+__device__ void dev_corners(const int64_t* cells, const double* xyz, int64_t c, double* X) {
+    constexpr int NC = 1 << D;
+    for (int k = 0; k < NC; ++k) {
+        const int64_t v = cells[c * NC + k];
+        for (int a = 0; a < D; ++a) X[k * D + a] = xyz[v * D + a];
+    }
+}
+
+// s * (packed symmetric D) -> full D x D
+template <int D>
+__device__ void dev_unpack_D(const double* Dp, double s, double* Dm) {
+    if constexpr (D == 2) {
+        Dm[0] = s * Dp[0]; Dm[1] = s * Dp[1];
+        Dm[2] = s * Dp[1]; Dm[3] = s * Dp[2];
+    } else {
+        Dm[0] = s * Dp[0]; Dm[1] = s * Dp[1]; Dm[2] = s * Dp[2];
+        Dm[3] = s * Dp[1]; Dm[4] = s * Dp[3]; Dm[5] = s * Dp[4];
+        Dm[6] = s * Dp[2]; Dm[7] = s * Dp[4]; Dm[8] = s * Dp[5];
+    }
+}
+
+// Per cell: w_q |det J| and J^-T at every cell quadrature point (cgeo, 1 + D^2
+// values per point), the cell volume and a flag for a non-positive Jacobian.
+template <int D>
+__global__ __launch_bounds__(kSW) void k_asm_cell_geo(int64_t n, int qc, const int64_t* __restrict__ cells,
+                                                    const double* __restrict__ xyz,
+                                                    const double* __restrict__ cq_xi,
+                                                    const double* __restrict__ cq_w,
+                                                    double* __restrict__ cgeo, double* __restrict__ vol,
+                                                    int32_t* __restrict__ bad) {
+    constexpr int G = 1 + D * D;
+    const int64_t c = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    if (c >= n) return;
+    double X[(1 << D) * D], J[D * D], JiT[D * D], det;
+    dev_corners<D>(cells, xyz, c, X);
+    double v = 0.0;
+    int nb = 0;
+    for (int q = 0; q < qc; ++q) {
+        dev_cell_map<D>(X, cq_xi + q * D, J, &det, JiT);
+        if (!(det > 0.0)) ++nb;
+        const double wd = cq_w[q] * fabs(det);
+        v += wd;
+        double* g = cgeo + (c * qc + q) * G;
+        g[0] = wd;
+        for (int k = 0; k < D * D; ++k) g[1 + k] = JiT[k];
+    }
+    vol[c] = v;
+    bad[c] = nb;
+}
+
+// Per face and face point: dS, sigma, D+ n, D- n, J+^-T, J-^-T (fgeo,
+// FG = 2 + 2D + 2D^2 values per point).  n is the unit normal out of the
+// plus cell from its geometry; sigma = eta_F mean(n.D+ n, n.D- n) with the
+// paper's eta_F = c p(p+1) mean(|F|/|K+|, |F|/|K-|) or a fixed eta.
+template <int D>
+__global__ __launch_bounds__(kSW) void k_asm_face_geo(
+    int64_t nf, int qf, const int64_t* __restrict__ plus, const int64_t* __restrict__ minus,
+    const int32_t* __restrict__ axis, const int64_t* __restrict__ cells, const double* __restrict__ xyz,
+    const double* __restrict__ Dcell, const double* __restrict__ scale, const double* __restrict__ vol,
+    const double* __restrict__ fxi_p, const double* __restrict__ fxi_m, const double* __restrict__ fw,
+    int pen_fixed, double eta_in, int p, double* __restrict__ fgeo) {
+    constexpr int NP = D * (D + 1) / 2, FG = 2 + 2 * D + 2 * D * D;
+    const int64_t f = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    if (f >= nf) return;
+    const int64_t cp = plus[f], cm = minus[f];
+    const int ax = axis[f];
+    double Xp[(1 << D) * D], Xm[(1 << D) * D], J[D * D], JiTp[D * D], JiTm[D * D], detp, detm;
+    dev_corners<D>(cells, xyz, cp, Xp);
+    dev_corners<D>(cells, xyz, cm, Xm);
+    double Dp[D * D], Dm[D * D];
+    dev_unpack_D<D>(Dcell + cp * NP, scale ? scale[cp] : 1.0, Dp);
+    dev_unpack_D<D>(Dcell + cm * NP, scale ? scale[cm] : 1.0, Dm);
+    double area = 0.0;
+    for (int q = 0; q < qf; ++q) {
+        const int o = ax * qf + q;
+        dev_cell_map<D>(Xp, fxi_p + o * D, J, &detp, JiTp);
+        double nn = 0.0;
+        for (int a = 0; a < D; ++a) nn += JiTp[a * D + ax] * JiTp[a * D + ax];
+        nn = sqrt(nn);
+        area += fw[o] * fabs(detp) * nn;
+    }
+    const double cpen = eta_in > 0.0 ? eta_in : 1.0;
+    const double eta = pen_fixed ? eta_in : cpen * p * (p + 1) * 0.5 * (area / vol[cp] + area / vol[cm]);
+    for (int q = 0; q < qf; ++q) {
+        const int o = ax * qf + q;
+        dev_cell_map<D>(Xp, fxi_p + o * D, J, &detp, JiTp);
+        dev_cell_map<D>(Xm, fxi_m + o * D, J, &detm, JiTm);
+        double nv[D], nn = 0.0;
+        for (int a = 0; a < D; ++a) {
+            nv[a] = JiTp[a * D + ax];
+            nn += nv[a] * nv[a];
+        }
+        nn = sqrt(nn);
+        for (int a = 0; a < D; ++a) nv[a] /= nn;
+        double* g = fgeo + (f * qf + q) * FG;
+        g[0] = fw[o] * fabs(detp) * nn;
+        double nDn = 0.0;
+        for (int a = 0; a < D; ++a) {
+            double sp = 0.0, sm = 0.0;
+            for (int k = 0; k < D; ++k) {
+                sp += Dp[a * D + k] * nv[k];
+                sm += Dm[a * D + k] * nv[k];
+            }
+            g[2 + a] = sp;
+            g[2 + D + a] = sm;
+        }
+        for (int a = 0; a < D; ++a) nDn += 0.5 * nv[a] * (g[2 + a] + g[2 + D + a]);
+        g[1] = eta * nDn;
+        for (int k = 0; k < D * D; ++k) {
+            g[2 + 2 * D + k] = JiTp[k];
+            g[2 + 2 * D + D * D + k] = JiTm[k];
+        }
+    }
+}
+
+// conormal flux of basis function i at a face point: (J^-T grad phi_i) . (D n)
+template <int D>
+__device__ __forceinline__ double face_flux(const double* JiT, const double* gref, const double* Dn) {
+    double fl = 0.0;
+    for (int a = 0; a < D; ++a) {
+        double G = 0.0;
+        for (int k = 0; k < D; ++k) G += JiT[a * D + k] * gref[k];
+        fl += G * Dn[a];
+    }
+    return fl;
+}
+
+// One thread per cell-block entry (c, i, j): the mass and stiffness
+// integrals over the cell, diag = s_K S + cM M, then the same-side face
+// terms of every face of the cell in ascending face order.
+template <int D, int B>
+__global__ __launch_bounds__(kSW) void k_asm_diag(
+    int64_t n, const double* __restrict__ cgeo, const double* __restrict__ cq_phi,
+    const double* __restrict__ cq_dphi, const double* __restrict__ Dcell, const double* __restrict__ scale,
+    double cM, const int64_t* __restrict__ cptr, const int64_t* __restrict__ code,
+    const int32_t* __restrict__ axis, int qf, const double* __restrict__ fgeo,
+    const double* __restrict__ fphi_p, const double* __restrict__ fphi_m, const double* __restrict__ fg_p,
+    const double* __restrict__ fg_m, double* __restrict__ diag, double* __restrict__ mass) {
+    constexpr int NP = D * (D + 1) / 2, G = 1 + D * D, FG = 2 + 2 * D + 2 * D * D, BB = B * B;
+    const int64_t r = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    if (r >= n * BB) return;
+    const int64_t c = r / BB;
+    const int ij = (int)(r - c * BB), i = ij / B, j = ij - (ij / B) * B;
+    double Dc[D * D];
+    dev_unpack_D<D>(Dcell + c * NP, 1.0, Dc);
+    double Md = 0.0, Sun = 0.0;
+    for (int q = 0; q < B; ++q) {   // B = number of cell quadrature points
+        const double* g = cgeo + (c * B + q) * G;
+        const double wd = g[0];
+        const double* JiT = g + 1;
+        double Gi[D], Gj[D], DGj[D];
+        for (int a = 0; a < D; ++a) {
+            double si = 0.0, sj = 0.0;
+            for (int k = 0; k < D; ++k) {
+                si += JiT[a * D + k] * cq_dphi[(q * B + i) * D + k];
+                sj += JiT[a * D + k] * cq_dphi[(q * B + j) * D + k];
+            }
+            Gi[a] = si;
+            Gj[a] = sj;
+        }
+        for (int a = 0; a < D; ++a) {
+            double s = 0.0;
+            for (int k = 0; k < D; ++k) s += Dc[a * D + k] * Gj[k];
+            DGj[a] = s;
+        }
+        double s = 0.0;
+        for (int a = 0; a < D; ++a) s += Gi[a] * DGj[a];
+        Md += wd * cq_phi[q * B + i] * cq_phi[q * B + j];
+        Sun += wd * s;
+    }
+    double v = (scale ? scale[c] : 1.0) * Sun + cM * Md;
+    mass[r] = Md;
+    for (int64_t e = cptr[c]; e < cptr[c + 1]; ++e) {
+        const int64_t f = code[e] >> 1;
+        const bool mi = (code[e] & 1) != 0;
+        const int ax = axis[f];
+        const double* phi = mi ? fphi_m : fphi_p;
+        const double* gr = mi ? fg_m : fg_p;
+        const double sgn = mi ? -1.0 : 1.0;
+        double L = 0.0;
+        for (int q = 0; q < qf; ++q) {
+            const int o = ax * qf + q;
+            const double* g = fgeo + (f * qf + q) * FG;
+            const double* Dn = g + 2 + (mi ? D : 0);
+            const double* JiT = g + 2 + 2 * D + (mi ? D * D : 0);
+            const double ji = sgn * phi[o * B + i], jj = sgn * phi[o * B + j];
+            const double fi = face_flux<D>(JiT, gr + (o * B + i) * D, Dn);
+            const double fj = face_flux<D>(JiT, gr + (o * B + j) * D, Dn);
+            L += g[0] * (-0.5 * ji * fj - 0.5 * fi * jj + g[1] * ji * jj);
+        }
+        v += L;
+    }
+    diag[r] = v;
+}
+
+// One thread per face-block entry (f, i, j): the coupling of plus-side row i
+// with minus-side column j.
+template <int D, int B>
+__global__ __launch_bounds__(kSW) void k_asm_faces(int64_t nf, const int32_t* __restrict__ axis, int qf,
+                                                 const double* __restrict__ fgeo,
+                                                 const double* __restrict__ fphi_p,
+                                                 const double* __restrict__ fphi_m,
+                                                 const double* __restrict__ fg_p,
+                                                 const double* __restrict__ fg_m, double* __restrict__ fblk) {
+    constexpr int FG = 2 + 2 * D + 2 * D * D, BB = B * B;
+    const int64_t r = (int64_t)blockIdx.x * kSW + threadIdx.x;
+    if (r >= nf * BB) return;
+    const int64_t f = r / BB;
+    const int ij = (int)(r - f * BB), i = ij / B, j = ij - (ij / B) * B;
+    const int ax = axis[f];
+    double L = 0.0;
+    for (int q = 0; q < qf; ++q) {
+        const int o = ax * qf + q;
+        const double* g = fgeo + (f * qf + q) * FG;
+        const double ji = fphi_p[o * B + i], jj = -fphi_m[o * B + j];
+        const double fi = face_flux<D>(g + 2 + 2 * D, fg_p + (o * B + i) * D, g + 2);
+        const double fj = face_flux<D>(g + 2 + 2 * D + D * D, fg_m + (o * B + j) * D, g + 2 + D);
+        L += g[0] * (-0.5 * ji * fj - 0.5 * fi * jj + g[1] * ji * jj);
+    }
+    fblk[r] = L;
+}
+
 template <typename T>
 T* dev_alloc(std::vector<void*>& owned, size_t count) {
     void* p = nullptr;
@@ -367,8 +644,100 @@ void DeviceSetup::prolongation(int level, const std::vector<double>& lo_l, const
     dev_download(P, m.P[level], (size_t)n * b * b);
 }
 
+void DeviceSetup::assemble_fine(const Faces& F, const RefElement& re, const dgmg_disc& disc,
+                                const dgmg_physics& ph, double cM, BlockOp& A0, std::vector<double>& mass) {
+    Impl& m = *im;
+    const int d = re.d, b = re.b, bb = b * b, np = d * (d + 1) / 2;
+    const int64_t n = m.h.n_cells, nf = (int64_t)F.plus.size();
+    FaceRef fr;
+    fr.init(re);
+    const int qf = fr.qf;
+    // inputs and reference tables
+    std::vector<double> Dh(ph.D_cell, ph.D_cell + (size_t)n * np);
+    double* Dcell = dev_upload(m.owned, Dh);
+    double* scale = nullptr;
+    if (ph.cell_scale) scale = dev_upload(m.owned, std::vector<double>(ph.cell_scale, ph.cell_scale + n));
+    double* cq_xi = dev_upload(m.owned, re.cq_xi);
+    double* cq_w = dev_upload(m.owned, re.cq_w);
+    double* cq_phi = dev_upload(m.owned, re.cq_phi);
+    double* cq_dphi = dev_upload(m.owned, re.cq_dphi);
+    double* fxi_p = dev_upload(m.owned, fr.xi_p);
+    double* fxi_m = dev_upload(m.owned, fr.xi_m);
+    double* fw = dev_upload(m.owned, fr.w);
+    double* fphi_p = dev_upload(m.owned, fr.phi_p);
+    double* fphi_m = dev_upload(m.owned, fr.phi_m);
+    double* fg_p = dev_upload(m.owned, fr.g_p);
+    double* fg_m = dev_upload(m.owned, fr.g_m);
+    int64_t* dplus = dev_upload(m.owned, F.plus);
+    int64_t* dminus = dev_upload(m.owned, F.minus);
+    std::vector<int32_t> ax32(F.axis.begin(), F.axis.end());
+    int32_t* daxis = dev_upload(m.owned, ax32);
+    // structure of the fine operator
+    A0.n = n;
+    A0.b = b;
+    A0.nf = nf;
+    A0.fc.resize((size_t)nf * 2);
+    for (int64_t f = 0; f < nf; ++f) {
+        A0.fc[2 * f] = F.plus[f];
+        A0.fc[2 * f + 1] = F.minus[f];
+    }
+    std::vector<int64_t> cptr, code;
+    cell_face_lists(A0, cptr, code);
+    int64_t* dcptr = dev_upload(m.owned, cptr);
+    int64_t* dcode = dev_upload(m.owned, code);
+    // geometry
+    const int G = 1 + d * d, FG = 2 + 2 * d + 2 * d * d;
+    double* cgeo = dev_alloc<double>(m.owned, (size_t)n * re.qc * G);
+    double* vol = dev_alloc<double>(m.owned, n);
+    int32_t* bad = dev_alloc<int32_t>(m.owned, n);
+    double* fgeo = dev_alloc<double>(m.owned, (size_t)nf * qf * FG);
+    Impl::Op& op = m.ops[0];
+    op.diag = dev_alloc<double>(m.owned, (size_t)n * bb);
+    op.fblk = dev_alloc<double>(m.owned, (size_t)nf * bb);
+    op.fc = dev_upload(m.owned, A0.fc);
+    double* dmass = dev_alloc<double>(m.owned, (size_t)n * bb);
+    const int pen_fixed = disc.penalty_mode == DGMG_PENALTY_FIXED ? 1 : 0;
+    auto run = [&](auto dtag) {
+        constexpr int D = decltype(dtag)::value;
+        if (n > 0)
+            k_asm_cell_geo<D><<<grid_for(n), kSW>>>(n, re.qc, m.cells, m.xyz, cq_xi, cq_w, cgeo, vol, bad);
+        DSCHK(hipGetLastError());
+        std::vector<int32_t> hb;
+        dev_download(hb, bad, (size_t)n);
+        for (int32_t v : hb)
+            if (v) fail(DGMG_EINVAL, "non-positive Jacobian determinant in the mesh");
+        if (nf > 0)
+            k_asm_face_geo<D><<<grid_for(nf), kSW>>>(nf, qf, dplus, dminus, daxis, m.cells, m.xyz, Dcell, scale,
+                                                     vol, fxi_p, fxi_m, fw, pen_fixed, disc.eta, re.p, fgeo);
+        DSCHK(hipGetLastError());
+        DS_DISPATCH_B(b, {
+            if constexpr ((D == 2 && (BV == 4 || BV == 9 || BV == 16 || BV == 25)) ||
+                          (D == 3 && (BV == 8 || BV == 27 || BV == 64))) {
+                if (n > 0)
+                    k_asm_diag<D, BV><<<grid_for(n * bb), kSW>>>(n, cgeo, cq_phi, cq_dphi, Dcell, scale, cM,
+                                                                  dcptr, dcode, daxis, qf, fgeo, fphi_p, fphi_m,
+                                                                  fg_p, fg_m, op.diag, dmass);
+                if (nf > 0)
+                    k_asm_faces<D, BV><<<grid_for(nf * bb), kSW>>>(nf, daxis, qf, fgeo, fphi_p, fphi_m, fg_p,
+                                                                   fg_m, op.fblk);
+            } else {
+                fail(DGMG_EUNSUPPORTED, "block size does not match the dimension");
+            }
+        });
+        DSCHK(hipGetLastError());
+    };
+    if (d == 2)
+        run(std::integral_constant<int, 2>{});
+    else
+        run(std::integral_constant<int, 3>{});
+    dev_download(A0.diag, op.diag, (size_t)n * bb);
+    dev_download(A0.fblk, op.fblk, (size_t)nf * bb);
+    dev_download(mass, dmass, (size_t)n * bb);
+}
+
 void DeviceSetup::set_fine(const BlockOp& A0) {
     Impl& m = *im;
+    if (m.ops[0].diag) return;   // assembled here
     m.ops[0].diag = dev_upload(m.owned, A0.diag);
     m.ops[0].fblk = dev_upload(m.owned, A0.fblk);
     m.ops[0].fc = dev_upload(m.owned, A0.fc);

@@ -273,6 +273,43 @@ Faces find_faces(const Hierarchy& h) {
 }
 
 // ------------------------------------------------------------- assembly
+void FaceRef::init(const RefElement& re) {
+    const int d = re.d, b = re.b;
+    qf = b / re.q;
+    xi_p.assign((size_t)d * qf * d, 0.0);
+    xi_m.assign((size_t)d * qf * d, 0.0);
+    w.assign((size_t)d * qf, 0.0);
+    phi_p.assign((size_t)d * qf * b, 0.0);
+    phi_m.assign((size_t)d * qf * b, 0.0);
+    g_p.assign((size_t)d * qf * b * d, 0.0);
+    g_m.assign((size_t)d * qf * b * d, 0.0);
+    for (int ax = 0; ax < d; ++ax) {
+        for (int iq = 0; iq < qf; ++iq) {
+            double xp[3], xm[3], wt = 1.0;
+            int r = iq;
+            for (int k = 0; k < d; ++k) {
+                if (k == ax) {
+                    xp[k] = 1.0;
+                    xm[k] = 0.0;
+                } else {
+                    int a = r % re.q;
+                    r /= re.q;
+                    xp[k] = xm[k] = re.gx[a];
+                    wt *= re.gw[a];
+                }
+            }
+            size_t o = (size_t)ax * qf + iq;
+            for (int k = 0; k < d; ++k) {
+                xi_p[o * d + k] = xp[k];
+                xi_m[o * d + k] = xm[k];
+            }
+            w[o] = wt;
+            tensor_eval(re, xp, &phi_p[o * b], &g_p[o * b * d]);
+            tensor_eval(re, xm, &phi_m[o * b], &g_m[o * b * d]);
+        }
+    }
+}
+
 static void unpack_D(int d, const double* Dp, double s, double* D) {
     if (d == 2) {
         D[0] = s * Dp[0]; D[1] = s * Dp[1];
@@ -352,39 +389,15 @@ void assemble_fine(const Hierarchy& h, const Faces& F, const RefElement& re,
     if (bad) fail(DGMG_EINVAL, "non-positive Jacobian determinant in the mesh");
 
     // reference data of the face rule for each axis
-    const int qf = b / re.q;  // (p+1)^(d-1)
+    FaceRef fr;
+    fr.init(re);
+    const int qf = fr.qf;
     const int64_t nf = (int64_t)F.plus.size();
     A0.nf = nf;
     A0.fc.resize((size_t)nf * 2);
     A0.fblk.assign((size_t)nf * bb, 0.0);
-    std::vector<double> fxi_p((size_t)d * qf * d), fxi_m((size_t)d * qf * d), fw((size_t)d * qf);
-    std::vector<double> fphi_p((size_t)d * qf * b), fphi_m((size_t)d * qf * b);
-    std::vector<double> fg_p((size_t)d * qf * b * d), fg_m((size_t)d * qf * b * d);
-    for (int ax = 0; ax < d; ++ax) {
-        for (int iq = 0; iq < qf; ++iq) {
-            double xp[3], xm[3], w = 1.0;
-            int r = iq;
-            for (int k = 0; k < d; ++k) {
-                if (k == ax) {
-                    xp[k] = 1.0;
-                    xm[k] = 0.0;
-                } else {
-                    int a = r % re.q;
-                    r /= re.q;
-                    xp[k] = xm[k] = re.gx[a];
-                    w *= re.gw[a];
-                }
-            }
-            size_t o = (size_t)ax * qf + iq;
-            for (int k = 0; k < d; ++k) {
-                fxi_p[o * d + k] = xp[k];
-                fxi_m[o * d + k] = xm[k];
-            }
-            fw[o] = w;
-            tensor_eval(re, xp, &fphi_p[o * b], &fg_p[o * b * d]);
-            tensor_eval(re, xm, &fphi_m[o * b], &fg_m[o * b * d]);
-        }
-    }
+    const std::vector<double>&fxi_p = fr.xi_p, &fxi_m = fr.xi_m, &fw = fr.w;
+    const std::vector<double>&fphi_p = fr.phi_p, &fphi_m = fr.phi_m, &fg_p = fr.g_p, &fg_m = fr.g_m;
     const int B2 = 2 * b;
     // local 2b x 2b matrix of the face terms of a_h over [K+ DoFs, K- DoFs]
     // for the given (already scaled) tensors of the two sides

@@ -1221,6 +1221,14 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     for (int k = 0; k < ph->n_params; ++k) s->ip.p[k] = ph->params[k];
 
     double t0 = now_s();
+    // assembly, prolongation blocks, Galerkin products and Lanczos estimates
+    // on the GPU (the adjoint's conductivity derivatives come from the host
+    // assembly)
+    std::unique_ptr<DeviceSetup> ds;
+    if (mg->setup_on_device) {
+        if (!mg->device_setup) fail(DGMG_EINVAL, "setup_on_device needs device_setup");
+        ds.reset(new DeviceSetup(*h, re));
+    }
     Faces F = find_faces(*h);
     s->axis0 = F.axis;
     s->ops.resize(s->L);
@@ -1228,7 +1236,10 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     const bool want_adj = mg->adjoint != 0;
     if (want_adj && ph->model == DGMG_MODEL_BO)
         fail(DGMG_EUNSUPPORTED, "the adjoint is implemented for the FHN and Aliev-Panfilov models");
-    assemble_fine(*h, F, re, *disc, *ph, cM, s->ops[0], s->mass_h, want_adj ? &adj : nullptr);
+    if (ds && !want_adj)
+        ds->assemble_fine(F, re, *disc, *ph, cM, s->ops[0], s->mass_h);
+    else
+        assemble_fine(*h, F, re, *disc, *ph, cM, s->ops[0], s->mass_h, want_adj ? &adj : nullptr);
     // AUTO: matrix-free on meshes of identical boxes for p >= 2 (single-column
     // solvers), the axis-ELL blocks otherwise
     if (s->fine_layout == DGMG_LAYOUT_AUTO && s->p >= 2 && s->max_rhs == 1 && uniform_boxes(*h, s->mf_h))
@@ -1246,12 +1257,6 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         if (ph->cell_scale)
             for (int64_t c = 0; c < h->n_cells; ++c)
                 for (int k = 0; k < np; ++k) s->mf_D[(size_t)c * np + k] *= ph->cell_scale[c];
-    }
-    // prolongation blocks, Galerkin products and Lanczos estimates on the GPU
-    std::unique_ptr<DeviceSetup> ds;
-    if (mg->setup_on_device) {
-        if (!mg->device_setup) fail(DGMG_EINVAL, "setup_on_device needs device_setup");
-        ds.reset(new DeviceSetup(*h, re));
     }
     double t1 = now_s();
     s->info.t_assembly = t1 - t0;

@@ -1,9 +1,10 @@
-"""Set-up on the GPU (prolongation blocks, Galerkin products P^T A P and the
-Lanczos estimates): every level's blocks, prolongations and Chebyshev
-interval against the host set-up and the oracle's sparse Galerkin products,
-for every supported block size and both agglomeration methods; solves with a
-device-built hierarchy against the oracle; the full-size shell and cube
-against the host set-up."""
+"""Set-up on the GPU (fine SIPDG and mass blocks, prolongation blocks,
+Galerkin products P^T A P and the Lanczos estimates): every level's blocks,
+prolongations and Chebyshev interval and the mass action against the host
+set-up and the oracle's assembly and sparse Galerkin products, for every
+supported block size, jittered and box meshes and both agglomeration methods;
+solves with a device-built hierarchy against the oracle; the full-size shell
+and cube against the host set-up."""
 import time
 
 import numpy as np
@@ -42,6 +43,14 @@ CASES = [("c1", lambda: make_problem("c1", n=16)),                       # 2D Q1
 
 def compare_levels(sh, sd, scale_tol=1e-13):
     ih, idv = sh.info(), sd.info()
+    # mass blocks (the load vector's operator)
+    N = ih["n_dofs"]
+    f = np.random.default_rng(8).standard_normal(N)
+    bh = torch.empty(N, dtype=torch.float64, device="cuda")
+    bd = torch.empty(N, dtype=torch.float64, device="cuda")
+    api.mass_apply(sh, dev(f), bh)
+    api.mass_apply(sd, dev(f), bd)
+    assert rel(host(bd), host(bh)) <= 1e-14
     assert ih["n_cells"] == idv["n_cells"] and ih["n_faces"] == idv["n_faces"]
     L = ih["n_levels"]
     for l in range(L):
@@ -74,6 +83,22 @@ def test_device_setup_matches_host_and_oracle(name, make):
         assert abs(Al - mg.A[l]).max() <= 1e-12 * abs(mg.A[l]).max(), l
     for l in range(idv["n_levels"] - 1):
         assert abs(idv["lam_hi"][l] - mg.lam[l][1]) <= 1e-10 * mg.lam[l][1], l
+
+
+def test_device_setup_cell_scaling_fixed_penalty_and_adjoint():
+    """Per-cell conductivity scalings and the fixed penalty on the device
+    assembly; with adjoint = 1 the fine blocks come from the host assembly
+    (which also forms the conductivity derivatives)."""
+    pr = make_problem("c1", n=16)
+    sc = np.random.default_rng(12).uniform(0.5, 2.0, pr["n_cells"])
+    for adjoint in (False, True):
+        say("device setup scaled", adjoint)
+        h1, sh = problem.build(pr, precision="fp64", cell_scale=sc, adjoint=adjoint, setup="host")
+        h2, sd = problem.build(pr, precision="fp64", cell_scale=sc, adjoint=adjoint, setup="device")
+        compare_levels(sh, sd)
+    A0 = system_matrix(pr, scale=sc)[0]
+    Al = dense_level(sd.export_level(0))
+    assert abs(Al - A0).max() <= 1e-12 * abs(A0).max()
 
 
 @pytest.mark.parametrize("name,make", [CASES[1], CASES[6]], ids=["c2", "shell"])
