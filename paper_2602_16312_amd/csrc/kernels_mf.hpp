@@ -7,19 +7,23 @@
 // integrates every cell and face term exactly, and the only per-cell data is
 // the (scaled) conductivity D_K.  One workgroup holds a tile of TC = 256/B
 // cells (thread = one DoF row, as in the block layouts) and proceeds in
-// phases separated by barriers:
+// phases separated by barriers, every cell sum factorised into 1D passes:
 //   0. stage the cell's values and its 2d face neighbours' values in LDS;
-//   1. thread g evaluates u and grad u at cell quadrature point g and stores
-//      cM w u and the weighted fluxes D grad u;
-//   2. threads evaluate, at the face quadrature points, the traces and
-//      conormal derivatives of both sides and store the face fluxes
+//   1. u and its reference gradient at the cell quadrature points by d
+//      passes of 1D contractions (x, y, z), then cM w u and the weighted
+//      fluxes D grad u per point;
+//   2a. per face node: the traces of both sides (the Lobatto end layers) and
+//      their normal derivatives;
+//   2. per face quadrature point, from the face-node data: values, conormal
+//      derivatives and the face fluxes
 //        f_val = (-s/2 (w_K + w_N) + sigma (u_K - u_N)) w,
 //        f_con = -s/2 (u_K - u_N) w   (tested against n.D_K grad v),
 //      with s = +1 when the neighbour is on the cell's upper side;
-//   2b. per face and tangential node pair, the face fluxes are integrated
+//   2b. per face and tangential node pair, the face fluxes integrated
 //      against the tangential factors of the test functions;
-//   3. thread I integrates the cell terms against its basis function and
-//      adds the face terms times its normal factor.
+//   3. the cell terms tested against every basis function by d passes of
+//      1D contractions (z, y, x), plus the face terms times each test
+//      function's normal factor.
 // Included by solver.hip after kernels.hpp.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -51,24 +55,61 @@ __device__ __forceinline__ int pk(int a, int b) {
 }
 
 // (A (va + vb)) at the thread's row; every thread of the workgroup must call
-// it (it synchronises), `active` marks threads that own a real row.
+// it (it synchronises), `active` marks threads that own a real row.  Every
+// pass below maps item i of a cell to thread i of that cell (B items).
 template <typename T, int B, bool VB>
 __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cell, bool active,
                                           const T* __restrict__ va, const T* __restrict__ vb) {
     const MfConst<T>& C = L.mf;
     constexpr int TC = Tile<T, B>::TC, D = dim_of<B>(), Q = mf_q<B>(), NF = 2 * D;
-    constexpr int QF = D == 3 ? Q * Q : Q;            // face quadrature points
+    constexpr int QN = D == 3 ? Q * Q : Q;            // face nodes = face quadrature points
     constexpr int NP = npack<D>();
+    // the 1D tables and per-axis constants, read with lane-dependent indices
+    constexpr int OI = 0, OD = Q * Q, OE = 2 * Q * Q, OW = OE + 2 * Q, OH = OW + Q, OA = OH + 3, OT = OA + 3;
+    __shared__ T tb[OT + 3];
     __shared__ T xs[TC][B];
-    __shared__ T xn[TC][NF][B];
     __shared__ T Dk[TC][NP];
     __shared__ T Dn[TC][NF][D];                       // row a of the neighbour's D
-    __shared__ T fq[TC][B][D + 1];
-    __shared__ T ff[TC][NF][QF][D + 1];
-    __shared__ T fT[TC][NF][QF][2];                   // face fluxes integrated tangentially
     __shared__ int hasn[TC][NF];                      // face has a neighbour
+    __shared__ T s1[TC][3][B];                        // 1D-pass partial sums
+    __shared__ T s2[TC][3][B];
+    __shared__ T fq[TC][B][D + 1];                    // cell terms at the cell points
+    // two regions, each shared by arrays whose lifetimes do not overlap:
+    //   rA: neighbour values xn (phases 0-2a), then face fluxes ff (2-2b)
+    //   rB: face-node data fn (2a-2), then tangential integrals fT (2b-3)
+    constexpr int SXN = TC * NF * B, SFF = TC * NF * QN * (D + 1);
+    constexpr int SFN = TC * NF * QN * 4, SFT = TC * NF * QN * 2;
+    __shared__ T rA[SXN > SFF ? SXN : SFF];
+    __shared__ T rB[SFN > SFT ? SFN : SFT];
+    T(*xn)[NF][B] = reinterpret_cast<T(*)[NF][B]>(rA);
+    T(*ff)[NF][QN][D + 1] = reinterpret_cast<T(*)[NF][QN][D + 1]>(rA);
+    T(*fn)[NF][QN][4] = reinterpret_cast<T(*)[NF][QN][4]>(rB);
+    T(*fT)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(rB);
+    const T* Ig = tb + OI;
+    const T* Dg = tb + OD;
+    const T* Ed = tb + OE;
+    const T* gw = tb + OW;
+    const T* hinv = tb + OH;
+    const T* area = tb + OA;
+    const T* etaa = tb + OT;
+    {
+        const int t = threadIdx.x;
+        if (t < Q * Q) {
+            tb[OI + t] = C.Ig[t];
+            tb[OD + t] = C.Dg[t];
+        }
+        if (t < 2 * Q) tb[OE + t] = C.Ed[t];
+        if (t < Q) tb[OW + t] = C.gw[t];
+        if (t < 3) {
+            tb[OH + t] = C.hinv[t];
+            tb[OA + t] = C.area[t];
+            tb[OT + t] = C.eta[t];
+        }
+    }
     const int i = threadIdx.x - lc * B;
     const bool slot = lc < TC;                        // thread maps to a (possibly padded) cell slot
+    // item coordinates of this thread (x fastest)
+    const int c0 = i % Q, c1 = (i / Q) % Q, c2 = D == 3 ? i / (Q * Q) : 0;
     // ---- phase 0: stage values
     if (slot) {
         T v = 0;
@@ -93,133 +134,168 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         if (i < NP) Dk[lc][i] = active ? C.D[(size_t)cell * NP + i] : T(0);
     }
     __syncthreads();
-    // ---- phase 1: cell quadrature point g = i
+    // ---- phase 1x: contract x: item (g0, j1, j2) -> sum_j0 l_j0(g0) x, l_j0'(g0) x
+    // ---- phase 2a: face node m of face f: traces of both sides (the Lobatto
+    //      end layers) and normal derivatives sum_ja l_ja'(e) x
     if (slot) {
-        int gk[3] = {i % Q, (i / Q) % Q, D == 3 ? i / (Q * Q) : 0};
-        T u = 0, gr[3] = {0, 0, 0};
-        if constexpr (D == 2) {
-            for (int j1 = 0; j1 < Q; ++j1) {
-                T sI = 0, sD = 0;
+        T a0 = 0, b0 = 0;
 #pragma unroll
-                for (int j0 = 0; j0 < Q; ++j0) {
-                    const T x = xs[lc][j0 + Q * j1];
-                    sI += C.Ig[gk[0] * Q + j0] * x;
-                    sD += C.Dg[gk[0] * Q + j0] * x;
-                }
-                const T a1 = C.Ig[gk[1] * Q + j1], d1 = C.Dg[gk[1] * Q + j1];
-                u += a1 * sI;
-                gr[0] += a1 * sD;
-                gr[1] += d1 * sI;
-            }
-        } else {
-            for (int j2 = 0; j2 < Q; ++j2) {
-                const T a2 = C.Ig[gk[2] * Q + j2], d2 = C.Dg[gk[2] * Q + j2];
-                for (int j1 = 0; j1 < Q; ++j1) {
-                    T sI = 0, sD = 0;
-#pragma unroll
-                    for (int j0 = 0; j0 < Q; ++j0) {
-                        const T x = xs[lc][j0 + Q * (j1 + Q * j2)];
-                        sI += C.Ig[gk[0] * Q + j0] * x;
-                        sD += C.Dg[gk[0] * Q + j0] * x;
-                    }
-                    const T a1 = C.Ig[gk[1] * Q + j1], d1 = C.Dg[gk[1] * Q + j1];
-                    u += a1 * a2 * sI;
-                    gr[0] += a1 * a2 * sD;
-                    gr[1] += d1 * a2 * sI;
-                    gr[2] += a1 * d2 * sI;
-                }
-            }
+        for (int j0 = 0; j0 < Q; ++j0) {
+            const T x = xs[lc][j0 + Q * (c1 + Q * c2)];
+            a0 += Ig[c0 * Q + j0] * x;
+            b0 += Dg[c0 * Q + j0] * x;
         }
-        T w = C.vol;
-#pragma unroll
-        for (int k = 0; k < D; ++k) w *= C.gw[gk[k]];
-        fq[lc][i][0] = C.cM * w * u;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            T s = 0;
-#pragma unroll
-            for (int b = 0; b < D; ++b) s += Dk[lc][pk<D>(a, b)] * C.hinv[b] * gr[b];
-            fq[lc][i][1 + a] = w * C.hinv[a] * s;
-        }
-    }
-    // ---- phase 2: face quadrature points (runtime face index: strides instead
-    // of indexed register arrays)
-    if (slot) {
-        for (int it = i; it < NF * QF; it += B) {
-            const int f = it / QF, qf = it - f * QF;
-            const int a = f >> 1;
-            const int side = f & 1;                  // 1: neighbour on the upper side
-            const T s = side ? T(1) : T(-1);
-            const int eK = side, eN = 1 - side;      // face at xi_a = eK of K, xi_a = eN of N
-            const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;   // tangential directions
+        s1[lc][0][i] = a0;
+        s1[lc][1][i] = b0;
+        for (int it = i; it < NF * QN; it += B) {
+            const int f = it / QN, m = it - f * QN;
+            const int a = f >> 1, eK = f & 1, eN = 1 - eK;
+            const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int sa = a == 0 ? 1 : (a == 1 ? Q : Q * Q);
-            const int s1 = t1 == 0 ? 1 : Q;
-            const int s2 = D == 3 ? (t2 == 1 ? Q : Q * Q) : 0;
-            const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
-            // Lobatto nodes contain both ends, so a trace is the face layer of
-            // nodes (layer 0 or Q-1); the normal derivative needs every layer
-            const int lK = eK * (Q - 1), lN = eN * (Q - 1);
-            T uK = 0, uN = 0, nK = 0, nN = 0, p1K = 0, p1N = 0, p2K = 0, p2N = 0;
-            for (int j2 = 0; j2 < (D == 3 ? Q : 1); ++j2) {
-                const T i2 = D == 3 ? C.Ig[g2 * Q + j2] : T(1);
-                const T e2 = D == 3 ? C.Dg[g2 * Q + j2] : T(0);
-                for (int j1 = 0; j1 < Q; ++j1) {
-                    const T tI = C.Ig[g1 * Q + j1] * i2;
-                    const T t1d = C.Dg[g1 * Q + j1] * i2;
-                    const T t2d = C.Ig[g1 * Q + j1] * e2;
-                    const int J0 = j1 * s1 + j2 * s2;
-                    T dnK = 0, dnN = 0;
+            const int st1 = t1 == 0 ? 1 : Q;
+            const int st2 = D == 3 ? (t2 == 1 ? Q : Q * Q) : 0;
+            const int J0 = (m % Q) * st1 + (D == 3 ? (m / Q) * st2 : 0);
+            T dK = 0, dN = 0;
 #pragma unroll
-                    for (int ja = 0; ja < Q; ++ja) {
-                        dnK += C.Ed[eK * Q + ja] * xs[lc][J0 + ja * sa];
-                        dnN += C.Ed[eN * Q + ja] * xn[lc][f][J0 + ja * sa];
-                    }
-                    const T vK = xs[lc][J0 + lK * sa], vN = xn[lc][f][J0 + lN * sa];
-                    uK += tI * vK;
-                    uN += tI * vN;
-                    nK += tI * dnK;
-                    nN += tI * dnN;
-                    p1K += t1d * vK;
-                    p1N += t1d * vN;
-                    p2K += t2d * vK;
-                    p2N += t2d * vN;
-                }
+            for (int ja = 0; ja < Q; ++ja) {
+                dK += Ed[eK * Q + ja] * xs[lc][J0 + ja * sa];
+                dN += Ed[eN * Q + ja] * xn[lc][f][J0 + ja * sa];
             }
-            T wK = Dk[lc][pk<D>(a, a)] * C.hinv[a] * nK + Dk[lc][pk<D>(a, t1)] * C.hinv[t1] * p1K;
-            T wN = Dn[lc][f][a] * C.hinv[a] * nN + Dn[lc][f][t1] * C.hinv[t1] * p1N;
-            if (D == 3) {
-                wK += Dk[lc][pk<D>(a, t2)] * C.hinv[t2] * p2K;
-                wN += Dn[lc][f][t2] * C.hinv[t2] * p2N;
-            }
-            T w = C.area[a] * C.gw[g1] * (D == 3 ? C.gw[g2] : T(1));
-            if (!hasn[lc][f]) w = 0;                  // boundary face: no terms
-            const T sig = C.eta[a] * T(0.5) * (Dk[lc][pk<D>(a, a)] + Dn[lc][f][a]);
-            const T jmp = uK - uN;
-            ff[lc][f][qf][0] = (T(-0.5) * s * (wK + wN) + sig * jmp) * w;
-            const T fc = T(-0.5) * s * jmp * w;
-            ff[lc][f][qf][1 + a] = fc * Dk[lc][pk<D>(a, a)] * C.hinv[a];
-            ff[lc][f][qf][1 + t1] = fc * Dk[lc][pk<D>(a, t1)] * C.hinv[t1];
-            if (D == 3) ff[lc][f][qf][1 + t2] = fc * Dk[lc][pk<D>(a, t2)] * C.hinv[t2];
+            fn[lc][f][m][0] = xs[lc][J0 + eK * (Q - 1) * sa];
+            fn[lc][f][m][1] = xn[lc][f][J0 + eN * (Q - 1) * sa];
+            fn[lc][f][m][2] = dK;
+            fn[lc][f][m][3] = dN;
         }
     }
     __syncthreads();
-    // ---- phase 2b: per face and tangential node pair m = (m1, m2), the face
-    // fluxes integrated against the tangential factors of the test functions:
-    // fT[.][0] = sum_q (f_val tI + f_con_t1 t1' + f_con_t2 t2'), fT[.][1] =
-    // sum_q f_con_a tI; a test function then needs only its normal factor
+    // cell terms at cell point (g0, g1, g2) from u and its reference gradient
+    auto cell_terms = [&](T u, const T* gr) {
+        T w = C.vol * gw[c0] * gw[c1];
+        if (D == 3) w *= gw[c2];
+        fq[lc][i][0] = C.cM * w * u;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T sd = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) sd += Dk[lc][pk<D>(a, b)] * hinv[b] * gr[b];
+            fq[lc][i][1 + a] = w * hinv[a] * sd;
+        }
+    };
+    // ---- phase 1y: contract y: item (g0, g1, j2)
+    // ---- phase 2: face points (g1, g2) of every face: values, conormal
+    //      derivatives and fluxes from the face-node data
     if (slot) {
-        for (int it = i; it < NF * QF; it += B) {
-            const int f = it / QF, m = it - f * QF;
+        T u0 = 0, uy = 0, ux = 0;
+#pragma unroll
+        for (int j1 = 0; j1 < Q; ++j1) {
+            const int src = c0 + Q * (j1 + Q * c2);
+            const T iy = Ig[c1 * Q + j1], dy = Dg[c1 * Q + j1];
+            u0 += iy * s1[lc][0][src];
+            uy += dy * s1[lc][0][src];
+            ux += iy * s1[lc][1][src];
+        }
+        if constexpr (D == 3) {
+            s2[lc][0][i] = u0;
+            s2[lc][1][i] = uy;
+            s2[lc][2][i] = ux;
+        } else {
+            const T gr[3] = {ux, uy, T(0)};
+            cell_terms(u0, gr);
+        }
+        for (int it = i; it < NF * QN; it += B) {
+            const int f = it / QN, qf = it - f * QN;
+            const int a = f >> 1;
+            const int side = f & 1;                  // 1: neighbour on the upper side
+            const T sgn = side ? T(1) : T(-1);
+            const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;   // tangential directions
+            const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
+            T uK = 0, uN = 0, nK = 0, nN = 0, p1K = 0, p1N = 0, p2K = 0, p2N = 0;
+#pragma unroll
+            for (int m2 = 0; m2 < (D == 3 ? Q : 1); ++m2) {
+                const T i2 = D == 3 ? Ig[g2 * Q + m2] : T(1);
+                const T e2 = D == 3 ? Dg[g2 * Q + m2] : T(0);
+#pragma unroll
+                for (int m1 = 0; m1 < Q; ++m1) {
+                    const T* nd = fn[lc][f][m1 + Q * m2];
+                    const T tI = Ig[g1 * Q + m1] * i2;
+                    const T t1d = Dg[g1 * Q + m1] * i2;
+                    const T vK = nd[0], vN = nd[1];
+                    uK += tI * vK;
+                    uN += tI * vN;
+                    nK += tI * nd[2];
+                    nN += tI * nd[3];
+                    p1K += t1d * vK;
+                    p1N += t1d * vN;
+                    if (D == 3) {
+                        const T t2d = Ig[g1 * Q + m1] * e2;
+                        p2K += t2d * vK;
+                        p2N += t2d * vN;
+                    }
+                }
+            }
+            T wK = Dk[lc][pk<D>(a, a)] * hinv[a] * nK + Dk[lc][pk<D>(a, t1)] * hinv[t1] * p1K;
+            T wN = Dn[lc][f][a] * hinv[a] * nN + Dn[lc][f][t1] * hinv[t1] * p1N;
+            if (D == 3) {
+                wK += Dk[lc][pk<D>(a, t2)] * hinv[t2] * p2K;
+                wN += Dn[lc][f][t2] * hinv[t2] * p2N;
+            }
+            T w = area[a] * gw[g1] * (D == 3 ? gw[g2] : T(1));
+            if (!hasn[lc][f]) w = 0;                  // boundary face: no terms
+            const T sig = etaa[a] * T(0.5) * (Dk[lc][pk<D>(a, a)] + Dn[lc][f][a]);
+            const T jmp = uK - uN;
+            ff[lc][f][qf][0] = (T(-0.5) * sgn * (wK + wN) + sig * jmp) * w;
+            const T fc = T(-0.5) * sgn * jmp * w;
+            ff[lc][f][qf][1 + a] = fc * Dk[lc][pk<D>(a, a)] * hinv[a];
+            ff[lc][f][qf][1 + t1] = fc * Dk[lc][pk<D>(a, t1)] * hinv[t1];
+            if (D == 3) ff[lc][f][qf][1 + t2] = fc * Dk[lc][pk<D>(a, t2)] * hinv[t2];
+        }
+    }
+    __syncthreads();
+    // ---- phase 1z (3D): contract z, cell terms at point (g0, g1, g2)
+    // ---- phase 2b: per face and tangential node pair m = (m1, m2), the face
+    //      fluxes integrated against the tangential factors of the test
+    //      functions: fT[.][0] = sum_q (f_val tI + f_con_t1 t1' + f_con_t2 t2'),
+    //      fT[.][1] = sum_q f_con_a tI; a test function then needs only its
+    //      normal factor
+    // ---- (2D) phase 3y: contract the cell terms over g1: items (g0, i1)
+    if (slot) {
+        if constexpr (D == 3) {
+            T u = 0, gr[3] = {0, 0, 0};
+#pragma unroll
+            for (int j2 = 0; j2 < Q; ++j2) {
+                const int src = c0 + Q * (c1 + Q * j2);
+                const T iz = Ig[c2 * Q + j2], dz = Dg[c2 * Q + j2];
+                u += iz * s2[lc][0][src];
+                gr[1] += iz * s2[lc][1][src];
+                gr[0] += iz * s2[lc][2][src];
+                gr[2] += dz * s2[lc][0][src];
+            }
+            cell_terms(u, gr);
+        } else {
+            T P = 0, X = 0;
+#pragma unroll
+            for (int g1 = 0; g1 < Q; ++g1) {
+                const T* F = fq[lc][c0 + Q * g1];
+                const T iy = Ig[g1 * Q + c1], dy = Dg[g1 * Q + c1];
+                P += iy * F[0] + dy * F[2];
+                X += iy * F[1];
+            }
+            s2[lc][0][i] = P;
+            s2[lc][1][i] = X;
+        }
+        for (int it = i; it < NF * QN; it += B) {
+            const int f = it / QN, m = it - f * QN;
             const int a = f >> 1;
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int m1 = m % Q, m2 = D == 3 ? m / Q : 0;
             T sv = 0, sn = 0;
-            for (int qf = 0; qf < QF; ++qf) {
+#pragma unroll
+            for (int qf = 0; qf < QN; ++qf) {
                 const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
-                const T i1 = C.Ig[g1 * Q + m1], i2 = D == 3 ? C.Ig[g2 * Q + m2] : T(1);
+                const T i1 = Ig[g1 * Q + m1], i2 = D == 3 ? Ig[g2 * Q + m2] : T(1);
                 const T* F = ff[lc][f][qf];
-                sv += F[0] * i1 * i2 + F[1 + t1] * C.Dg[g1 * Q + m1] * i2;
-                if (D == 3) sv += F[1 + t2] * i1 * C.Dg[g2 * Q + m2];
+                sv += F[0] * i1 * i2 + F[1 + t1] * Dg[g1 * Q + m1] * i2;
+                if (D == 3) sv += F[1 + t2] * i1 * Dg[g2 * Q + m2];
                 sn += F[1 + a] * i1 * i2;
             }
             fT[lc][f][m][0] = sv;
@@ -227,33 +303,50 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         }
     }
     __syncthreads();
-    // ---- phase 3: test against the thread's basis function I = i (direct
-    // sums; with the loops unrolled the compiler keeps the 1D table entries
-    // in registers, which measured faster than factorising the sums)
+    if constexpr (D == 3) {
+        // ---- phase 3z: items (g0, g1, i2): W = sum_g2 (l_i2(g2) c0 + l_i2'(g2) c3),
+        //      X = sum_g2 l_i2(g2) c1, Y = sum_g2 l_i2(g2) c2 of the cell terms c
+        if (slot) {
+            T W = 0, X = 0, Y = 0;
+#pragma unroll
+            for (int g2 = 0; g2 < Q; ++g2) {
+                const T* F = fq[lc][c0 + Q * (c1 + Q * g2)];
+                const T iz = Ig[g2 * Q + c2], dz = Dg[g2 * Q + c2];
+                W += iz * F[0] + dz * F[3];
+                X += iz * F[1];
+                Y += iz * F[2];
+            }
+            s1[lc][0][i] = W;
+            s1[lc][1][i] = X;
+            s1[lc][2][i] = Y;
+        }
+        __syncthreads();
+        // ---- phase 3y: items (g0, i1, i2): P = sum_g1 (l_i1(g1) W + l_i1'(g1) Y),
+        //      X' = sum_g1 l_i1(g1) X
+        if (slot) {
+            T P = 0, X = 0;
+#pragma unroll
+            for (int g1 = 0; g1 < Q; ++g1) {
+                const int src = c0 + Q * (g1 + Q * c2);
+                const T iy = Ig[g1 * Q + c1], dy = Dg[g1 * Q + c1];
+                P += iy * s1[lc][0][src] + dy * s1[lc][2][src];
+                X += iy * s1[lc][1][src];
+            }
+            s2[lc][0][i] = P;
+            s2[lc][1][i] = X;
+        }
+        __syncthreads();
+    }
+    // ---- phase 3x: test function I = (i0, i1, i2): sum_g0 (l_i0(g0) P + l_i0'(g0) X'),
+    //      plus the face terms times the test function's normal factor
     T y = 0;
     if (slot) {
-        const int ik[3] = {i % Q, (i / Q) % Q, D == 3 ? i / (Q * Q) : 0};
-        for (int g = 0; g < B; ++g) {
-            const int gk[3] = {g % Q, (g / Q) % Q, D == 3 ? g / (Q * Q) : 0};
-            T pI[3], pD[3];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                pI[k] = C.Ig[gk[k] * Q + ik[k]];
-                pD[k] = C.Dg[gk[k] * Q + ik[k]];
-            }
-            T val = pI[0];
-#pragma unroll
-            for (int k = 1; k < D; ++k) val *= pI[k];
-            y += fq[lc][g][0] * val;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                T dv = pD[a];
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-                    if (k != a) dv *= pI[k];
-                y += fq[lc][g][1 + a] * dv;
-            }
+        for (int g0 = 0; g0 < Q; ++g0) {
+            const int src = g0 + Q * (c1 + Q * c2);
+            y += Ig[g0 * Q + c0] * s2[lc][0][src] + Dg[g0 * Q + c0] * s2[lc][1][src];
         }
+        const int ik[3] = {c0, c1, c2};
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int a = f >> 1, eK = f & 1;
@@ -261,7 +354,7 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const int m = ik[t1] + (D == 3 ? Q * ik[t2] : 0);
             // normal factor: trace (0 or 1 at the Lobatto ends) and derivative
             if (ik[a] == eK * (Q - 1)) y += fT[lc][f][m][0];
-            y += C.Ed[eK * Q + ik[a]] * fT[lc][f][m][1];
+            y += Ed[eK * Q + ik[a]] * fT[lc][f][m][1];
         }
     }
     return y;
