@@ -199,6 +199,11 @@ typedef struct {
     double t_assembly, t_hierarchy, t_transfer, t_galerkin, t_smoother, t_coarse, t_upload;
     int64_t device_bytes;
     int32_t fine_layout;   /* DGMG_LAYOUT_TILE_ELL, _AXIS_ELL or _MATRIX_FREE as used */
+    /* storage of every level's operator as used (0 for the coarsest level,
+     * which is solved with its dense inverse); agglomerated levels whose
+     * agglomerates form a conforming grid of boxes use AXIS_ELL unless
+     * fine_layout = TILE_ELL was asked for */
+    int32_t level_layout[DGMG_MAX_LEVELS];
 } dgmg_solver_info;
 int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info);
 

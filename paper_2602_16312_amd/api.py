@@ -120,8 +120,8 @@ class Solver:
                                  smoother=i.t_smoother, coarse=i.t_coarse,
                                  upload=i.t_upload),
                     device_bytes=i.device_bytes,
-                    fine_layout={1: "tile_ell", 2: "axis_ell", 3: "matrix_free"}.get(i.fine_layout,
-                                                                                    "none"))
+                    fine_layout=_LAYOUT_NAMES.get(i.fine_layout, "none"),
+                    level_layout=[_LAYOUT_NAMES.get(v, "none") for v in i.level_layout[:L]])
 
     def export_level(self, level, blocks=True):
         """Host copies of a level's FP64 operator and transfer blocks
@@ -147,6 +147,9 @@ class Solver:
         if getattr(self, "_s", None):
             F.lib().dgmg_destroy_solver(self._s)
             self._s = None
+
+
+_LAYOUT_NAMES = {1: "tile_ell", 2: "axis_ell", 3: "matrix_free"}
 
 
 def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",),

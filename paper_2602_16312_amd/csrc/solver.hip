@@ -109,6 +109,10 @@ struct dgmg_solver {
     double mf_cM = 0.0, mf_eta[3] = {0, 0, 0};
     std::vector<double> mf_D;
     std::vector<int> axis0;           // axis of every fine face (face order of ops[0])
+    // levels >= 1 whose agglomerates form a conforming grid of boxes: axis of
+    // every face and whether its stored (plus, minus) order runs downwards
+    std::vector<std::vector<int>> axisl;
+    std::vector<std::vector<char>> flipl;
     int64_t N = 0;
     bool on_device = false;
     std::vector<DevLevel> lv;
@@ -766,6 +770,47 @@ static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, in
     return E;
 }
 
+// Faces of an agglomerated level whose boxes form a conforming grid: every
+// face separates its two boxes along one axis (centroid offset above half the
+// mean extent along it, below a quarter along the others).  Gives the axis
+// and whether the stored plus cell is the upper one; leaves `axis` empty when
+// some face does not qualify.
+static void coarse_face_axes(const BlockOp& A, const std::vector<double>& lo, const std::vector<double>& hi,
+                             int d, std::vector<int>& axis, std::vector<char>& flip) {
+    axis.assign(A.nf, -1);
+    flip.assign(A.nf, 0);
+    for (int64_t f = 0; f < A.nf; ++f) {
+        const int64_t p = A.fc[2 * f], m = A.fc[2 * f + 1];
+        int best = -1;
+        double rbest = 0.0;
+        bool aligned = true;
+        for (int a = 0; a < d; ++a) {
+            const double dc = 0.5 * (lo[m * d + a] + hi[m * d + a]) - 0.5 * (lo[p * d + a] + hi[p * d + a]);
+            const double ext = 0.5 * (hi[p * d + a] - lo[p * d + a] + hi[m * d + a] - lo[m * d + a]);
+            if (!(ext > 0)) {
+                aligned = false;
+                break;
+            }
+            const double r = std::fabs(dc) / ext;
+            if (r > rbest) {
+                if (best >= 0 && rbest >= 0.25) aligned = false;
+                rbest = r;
+                best = a;
+            } else if (r >= 0.25) {
+                aligned = false;
+            }
+        }
+        if (!aligned || best < 0 || rbest <= 0.5) {
+            axis.clear();
+            flip.clear();
+            return;
+        }
+        const double dcb = 0.5 * (lo[m * d + best] + hi[m * d + best]) - 0.5 * (lo[p * d + best] + hi[p * d + best]);
+        axis[f] = best;
+        flip[f] = dcb < 0 ? 1 : 0;
+    }
+}
+
 // prolongation blocks (row-major per fine entity) in tile-interleaved layout
 template <typename T>
 static std::vector<T> interleave_P(const std::vector<double>& P, int b, int64_t n) {
@@ -900,6 +945,34 @@ static void upload_level(dgmg_solver* s, int l) {
     // unless the caller asks for the tile-ELL layout everywhere
     const bool mf = l == 0 && s->fine_layout == DGMG_LAYOUT_MATRIX_FREE;
     const bool ax = l == 0 && !mf && s->fine_layout != DGMG_LAYOUT_TILE_ELL && !s->axis0.empty();
+    // agglomerated levels that form a conforming grid of boxes also store each
+    // face block once (faces reoriented from the lower to the upper box)
+    bool axc = false;
+    AxisEll Ec;
+    if (l > 0 && !last && s->fine_layout != DGMG_LAYOUT_TILE_ELL && (size_t)l < s->axisl.size() &&
+        !s->axisl[l].empty()) {
+        BlockOp Ao;
+        Ao.n = A.n;
+        Ao.b = A.b;
+        Ao.nf = A.nf;
+        Ao.diag = A.diag;
+        Ao.fc = A.fc;
+        Ao.fblk = A.fblk;
+        const std::vector<char>& fl = s->flipl[l];
+        for (int64_t f = 0; f < A.nf; ++f)
+            if (fl[f]) {
+                std::swap(Ao.fc[2 * f], Ao.fc[2 * f + 1]);
+                double* blk = &Ao.fblk[(size_t)f * b * b];
+                for (int i = 0; i < b; ++i)
+                    for (int j = i + 1; j < b; ++j) std::swap(blk[i * b + j], blk[j * b + i]);
+            }
+        try {
+            Ec = build_axis_ell(Ao, s->axisl[l], s->dim, true);
+            axc = true;
+        } catch (const Error& e) {
+            if (e.code != DGMG_EUNSUPPORTED) throw;   // two faces on one side: keep tile-ELL
+        }
+    }
     if (mf) {
         // neighbours as in the axis-ELL layout; no operator values are stored
         AxisEll E = build_axis_ell(A, s->axis0, s->dim, false);
@@ -914,8 +987,8 @@ static void upload_level(dgmg_solver* s, int l) {
             L.dinv32 = s->upload(convert<float>(dinv));
             L.mf32 = mf_constants<float>(s, re, s->upload(convert<float>(s->mf_D)));
         }
-    } else if (ax) {
-        AxisEll E = build_axis_ell(A, s->axis0, s->dim, true);
+    } else if (ax || axc) {
+        AxisEll E = axc ? std::move(Ec) : build_axis_ell(A, s->axis0, s->dim, true);
         L.ax = true;
         L.up = s->upload(E.up);
         L.lo = s->upload(E.lo);
@@ -1281,6 +1354,10 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         else
             galerkin(s->ops[l], s->Ph[l], h->parent[l], h->n_ent[l + 1], s->ops[l + 1]);
     }
+    // face axes of agglomerated levels that form a conforming grid of boxes
+    s->axisl.assign(s->L, {});
+    s->flipl.assign(s->L, {});
+    for (int l = 1; l + 1 < s->L; ++l) coarse_face_axes(s->ops[l], lo[l], hi[l], s->dim, s->axisl[l], s->flipl[l]);
     double t4 = now_s();
     s->info.t_galerkin = t4 - t3;
     s->lv.resize(s->L);
@@ -1382,9 +1459,13 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     }
     s->info.t_upload = now_s() - t6;
     s->info.device_bytes = s->dev_bytes;
-    s->info.fine_layout = !s->on_device ? 0
-                          : s->lv[0].mf ? DGMG_LAYOUT_MATRIX_FREE
-                          : s->lv[0].ax ? DGMG_LAYOUT_AXIS_ELL : DGMG_LAYOUT_TILE_ELL;
+    for (int l = 0; l < s->L; ++l) {
+        const DevLevel& Lv = s->lv[l];
+        s->info.level_layout[l] = !s->on_device || (l == s->L - 1 && s->L > 1) ? 0
+                                  : Lv.mf ? DGMG_LAYOUT_MATRIX_FREE
+                                  : Lv.ax ? DGMG_LAYOUT_AXIS_ELL : DGMG_LAYOUT_TILE_ELL;
+    }
+    s->info.fine_layout = s->info.level_layout[0];
     *out = guard.release();
     return DGMG_OK;
     API_END

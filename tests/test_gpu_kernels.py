@@ -39,6 +39,11 @@ def _gpu():
 def test_apply_all_levels(name, n, kw, layout):
     pr, mg, h, s = _setup(name, n, kw, precision="mixed", layout=layout)
     assert s.info()["fine_layout"] == layout
+    # agglomerated grid levels store each face block once too, unless the
+    # tile layout is asked for everywhere; the coarsest level has no layout
+    lay = s.info()["level_layout"]
+    L = len(lay)
+    assert lay[1:L - 1] == [layout] * (L - 2) and lay[L - 1] == "none"
     rng = np.random.default_rng(1)
     for l in range(len(mg.A) - 1):
         x = rng.standard_normal(mg.A[l].shape[0])
@@ -50,6 +55,23 @@ def test_apply_all_levels(name, n, kw, layout):
         say("apply", name, n, kw, layout, "level", l, "fp32")
         api.apply(s, l, dev(x), y, "mixed")
         assert rel(host(y), ref) <= 2e-6
+
+
+def test_irregular_agglomerates_keep_tile_layout():
+    """STR agglomerates of the shell do not form a grid: its coarse levels
+    keep the tile layout (faces stored for both cells), and their applies
+    match the oracle's Galerkin operators."""
+    pr = make_problem("c4", h=0.09)
+    A0, M, A, cM = system_matrix(pr)
+    mg = VCycle(A0, oracle_hierarchy(pr)["P"])
+    h, s = problem.build(pr, precision="mixed")
+    lay = s.info()["level_layout"]
+    assert lay[0] == "axis_ell" and all(v == "tile_ell" for v in lay[1:-1]) and lay[-1] == "none"
+    x = np.random.default_rng(6).standard_normal(mg.A[1].shape[0])
+    y = torch.empty(len(x), dtype=torch.float64, device="cuda")
+    say("apply shell level 1")
+    api.apply(s, 1, dev(x), y, "fp64")
+    assert rel(host(y), mg.A[1] @ x) <= 1e-13
 
 
 @pytest.mark.parametrize("layout", ["auto", "axis_ell", "tile_ell"])
