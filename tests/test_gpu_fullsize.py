@@ -1,6 +1,7 @@
 """Full-size 256x256 Q2 Aliev-Panfilov problem (589,824 DoFs) in the launch
-configuration the benchmark times: FP64 steps against the oracle, mixed
-precision against the FP64 oracle, sampled operator rows."""
+configuration the benchmark times (hierarchy built on the GPU): FP64 steps
+against the oracle, mixed precision against the FP64 oracle, sampled operator
+rows of the device-assembled operator."""
 import numpy as np
 import pytest
 
@@ -29,7 +30,7 @@ def _state(pr):
 
 def test_sampled_operator_rows(c2):
     pr, sim = c2
-    h, s = problem.build(pr, precision="mixed")
+    h, s = problem.build(pr, precision="mixed", setup="device")
     rng = np.random.default_rng(9)
     cells = rng.choice(pr["n_cells"], 64, replace=False)
     M, A = assemble(pr, row_cells=cells)
@@ -47,7 +48,7 @@ def test_two_steps_fp64_and_mixed(c2):
     pr, sim = c2
     _, ref, stats = sim.run(2, 1e-12)
     say("full c2 fp64 2 steps")
-    h, s = problem.build(pr, precision="fp64", lam_override=sim.mg.lam)
+    h, s = problem.build(pr, precision="fp64", lam_override=sim.mg.lam, setup="device")
     st = _state(pr)
     for k in range(2):
         r = api.time_step(s, st, (k + 1) * pr["dt"], tol=1e-12)
@@ -55,7 +56,7 @@ def test_two_steps_fp64_and_mixed(c2):
         assert rel(host(st.U), ref[k]) <= 1e-10
     del s, h
     say("full c2 mixed 2 steps")
-    h, s = problem.build(pr, precision="mixed")
+    h, s = problem.build(pr, precision="mixed", setup="device")
     st = _state(pr)
     for k in range(2):
         r = api.time_step(s, st, (k + 1) * pr["dt"], tol=1e-8)
