@@ -137,8 +137,9 @@ def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None, nrhs=1, mfma=F
     from paper_2602_16312_amd import api, problem
 
     t0 = time.perf_counter()
+    # the solver's device memory comes from torch's caching allocator
     h, s = problem.build(pr, precision=precision, max_rhs=nrhs, mfma=mfma,
-                         fine_layout=fine_layout, setup=setup)
+                         fine_layout=fine_layout, setup=setup, allocator="torch")
     setup_s = time.perf_counter() - t0
     log(f"{precision}: setup {setup_s:.1f} s")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")

@@ -32,6 +32,7 @@
 #ifndef DGMG_H
 #define DGMG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -125,6 +126,21 @@ typedef struct {
     const double* params;
 } dgmg_physics;
 
+/* Device memory provider for the solver's own buffers (operators, transfer
+ * blocks, work vectors and set-up temporaries; e.g. a framework's caching
+ * allocator).  alloc returns device memory of at least `bytes` bytes, 256-byte
+ * aligned, on the current device, or NULL on failure (the call then fails with
+ * DGMG_ENOMEM); free releases a pointer that alloc returned.  alloc is called
+ * only inside dgmg_setup_levels, free inside dgmg_setup_levels (set-up
+ * temporaries, or everything on an error) and dgmg_destroy_solver; never on
+ * the solve or time-stepping path.  ctx is passed through; the functions and
+ * ctx must stay valid until dgmg_destroy_solver has returned. */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes);
+    void (*free)(void* ctx, void* ptr);
+    void* ctx;
+} dgmg_allocator;
+
 enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
 /* Multigrid options (section 6): Chebyshev-Jacobi degree and number of
  * pre/post sweeps, Lanczos steps, lambda_hi = lam_safety * theta_max,
@@ -169,6 +185,7 @@ typedef struct {
     int32_t mfma;
     int32_t fine_layout;
     int32_t setup_on_device;
+    const dgmg_allocator* allocator;  /* NULL: hipMalloc / hipFree; copied at set-up */
 } dgmg_mg_opts;
 
 enum { DGMG_LAYOUT_AUTO = 0, DGMG_LAYOUT_TILE_ELL = 1, DGMG_LAYOUT_AXIS_ELL = 2,

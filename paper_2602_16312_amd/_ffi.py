@@ -48,6 +48,14 @@ class Physics(C.Structure):
                 ("model", C.c_int32), ("n_params", C.c_int32), ("params", dp)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class MGOpts(C.Structure):
     _fields_ = [("cheb_degree", C.c_int32), ("cheb_sweeps", C.c_int32),
                 ("lanczos_steps", C.c_int32), ("lam_safety", C.c_double),
@@ -55,7 +63,7 @@ class MGOpts(C.Structure):
                 ("precision", C.c_int32), ("device_setup", C.c_int32),
                 ("adjoint", C.c_int32), ("max_rhs", C.c_int32),
                 ("mfma", C.c_int32), ("fine_layout", C.c_int32),
-                ("setup_on_device", C.c_int32)]
+                ("setup_on_device", C.c_int32), ("allocator", C.POINTER(Allocator))]
 
 
 class SolverInfo(C.Structure):

@@ -98,9 +98,42 @@ def build_hierarchy(xyz, cell_vtx, n_levels, method="grid", grid_bins=None,
     return Hierarchy(h, keep=None)
 
 
+class TorchAllocator:
+    """dgmg_allocator backed by torch's caching allocator on the current
+    device: every block the library asks for is a uint8 tensor kept alive
+    until the library frees it.  Marshalling only; the memory is used by the
+    library's kernels."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.live = {}
+
+        def _alloc(ctx, nbytes):
+            try:
+                t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+            except RuntimeError:
+                return None
+            p = (t.data_ptr() + 255) // 256 * 256
+            self.live[p] = t
+            return p
+
+        def _free(ctx, ptr):
+            self.live.pop(ptr, None)
+
+        self._c_alloc = F.ALLOC_FN(_alloc)
+        self._c_free = F.FREE_FN(_free)
+        self.struct = F.Allocator(self._c_alloc, self._c_free, None)
+
+    @property
+    def live_bytes(self):
+        return sum(t.numel() for t in self.live.values())
+
+
 class Solver:
-    def __init__(self, handle):
+    def __init__(self, handle, keep=None):
         self._s = handle
+        self._keep = keep   # objects the library calls back into (allocator)
 
     @property
     def handle(self):
@@ -156,10 +189,12 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
                  bdf=2, cell_scale=None, precision="fp64", cheb_degree=3,
                  cheb_sweeps=3, lanczos_steps=20, lam_safety=1.2,
                  smooth_range=20.0, lam_override=None, device_setup=True, adjoint=False,
-                 max_rhs=1, mfma=False, fine_layout="auto", setup="host"):
+                 max_rhs=1, mfma=False, fine_layout="auto", setup="host", allocator=None):
     """dgmg_setup_levels: assembly, Galerkin hierarchy, smoother, coarse factor.
-    setup = "device" computes the prolongations, Galerkin products and Lanczos
-    estimates on the GPU, "host" on the CPU."""
+    setup = "device" computes the assembly, prolongations, Galerkin products and
+    Lanczos estimates on the GPU, "host" on the CPU.  allocator: None (the
+    library uses hipMalloc), "torch" or a TorchAllocator (device memory from
+    torch's caching allocator)."""
     if setup not in ("host", "device"):
         raise ValueError("setup must be 'host' or 'device'")
     d = F.Disc(p, 0 if penalty[0] == "paper" else 1,
@@ -176,14 +211,21 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
     if lam_override is not None:
         lam, lo = _dptr(np.asarray(lam_override, dtype=np.float64).ravel())
         keep.append(lam)
+    if allocator == "torch":
+        allocator = TorchAllocator()
+    ap = None
+    if allocator is not None:
+        if not isinstance(allocator, TorchAllocator):
+            raise ValueError("allocator must be None, 'torch' or a TorchAllocator")
+        ap = C.pointer(allocator.struct)
     mg = F.MGOpts(cheb_degree, cheb_sweeps, lanczos_steps, lam_safety, smooth_range,
                   lo, PRECISIONS[precision], 1 if device_setup else 0, 1 if adjoint else 0,
                   int(max_rhs), 1 if mfma else 0, LAYOUTS[fine_layout],
-                  1 if setup == "device" else 0)
+                  1 if setup == "device" else 0, ap)
     s = C.c_void_p()
     F.check(F.lib().dgmg_setup_levels(hier.handle, C.byref(d), C.byref(ph), C.byref(mg),
                                       C.byref(s)))
-    return Solver(s)
+    return Solver(s, keep=allocator)
 
 
 def _pcg_opts(tol, tol_mode, max_it, flexible):

@@ -117,11 +117,20 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
 // Lanczos start vector: v_i = frac((i+1) * golden ratio conjugate) - 1/2, normalised
 void lanczos_start(int64_t n, std::vector<double>& v);
 
+// Device memory of the library's own buffers: the caller's allocator when one
+// was given at set-up, hipMalloc / hipFree otherwise.
+struct DeviceMemory {
+    dgmg_allocator user{};
+    bool has_user = false;
+    void* alloc(size_t bytes) const;    // fails with DGMG_ENOMEM
+    void release(void* p) const noexcept;
+};
+
 // Device set-up (prolongation blocks, Galerkin products and Lanczos
 // estimates on the GPU); holds its device buffers until destroyed.
 class DeviceSetup {
   public:
-    DeviceSetup(const Hierarchy& h, const RefElement& re);
+    DeviceSetup(const Hierarchy& h, const RefElement& re, const DeviceMemory& mem);
     ~DeviceSetup();
     DeviceSetup(const DeviceSetup&) = delete;
     DeviceSetup& operator=(const DeviceSetup&) = delete;

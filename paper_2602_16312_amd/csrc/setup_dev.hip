@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -537,16 +538,24 @@ __global__ __launch_bounds__(kSW) void k_asm_faces(int64_t nf, const int32_t* __
     fblk[r] = L;
 }
 
+// set-up temporaries come from the solver's device memory provider and are
+// released with the set-up object
+struct Owned {
+    const DeviceMemory& mem;
+    std::vector<void*> ptrs;
+    explicit Owned(const DeviceMemory& m) : mem(m) {}
+    ~Owned() {
+        for (void* p : ptrs) mem.release(p);
+    }
+};
 template <typename T>
-T* dev_alloc(std::vector<void*>& owned, size_t count) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
-        fail(DGMG_ENOMEM, "hipMalloc failed (device set-up)");
-    owned.push_back(p);
+T* dev_alloc(Owned& owned, size_t count) {
+    void* p = owned.mem.alloc(std::max<size_t>(count, 1) * sizeof(T));
+    owned.ptrs.push_back(p);
     return (T*)p;
 }
 template <typename T>
-T* dev_upload(std::vector<void*>& owned, const std::vector<T>& h) {
+T* dev_upload(Owned& owned, const std::vector<T>& h) {
     T* d = dev_alloc<T>(owned, h.size());
     if (!h.empty()) DSCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
     return d;
@@ -576,7 +585,7 @@ unsigned grid_for(int64_t threads) { return (unsigned)((threads + kSW - 1) / kSW
 struct DeviceSetup::Impl {
     const Hierarchy& h;
     int d = 0, q = 0, b = 0;
-    std::vector<void*> owned;
+    Owned owned;
     int64_t* cells = nullptr;
     double *xyz = nullptr, *nodes = nullptr;
     struct Op {
@@ -586,22 +595,21 @@ struct DeviceSetup::Impl {
     std::vector<Op> ops;
     std::vector<double*> P;
     std::vector<int64_t*> parent;
-    Impl(const Hierarchy& hh) : h(hh) {}
-    ~Impl() {
-        for (void* p : owned) (void)hipFree(p);
-    }
+    Impl(const Hierarchy& hh, const DeviceMemory& mem) : h(hh), owned(mem) {}
 };
 
-DeviceSetup::DeviceSetup(const Hierarchy& h, const RefElement& re) : im(new Impl(h)) {
-    im->d = re.d;
-    im->q = re.q;
-    im->b = re.b;
-    im->ops.resize(h.n_levels);
-    im->P.assign(h.n_levels, nullptr);
-    im->parent.assign(h.n_levels, nullptr);
-    im->cells = dev_upload(im->owned, h.cells);
-    im->xyz = dev_upload(im->owned, h.xyz);
-    im->nodes = dev_upload(im->owned, re.nodes);
+DeviceSetup::DeviceSetup(const Hierarchy& h, const RefElement& re, const DeviceMemory& mem) : im(nullptr) {
+    std::unique_ptr<Impl> m(new Impl(h, mem));   // released (with its buffers) if an upload fails
+    m->d = re.d;
+    m->q = re.q;
+    m->b = re.b;
+    m->ops.resize(h.n_levels);
+    m->P.assign(h.n_levels, nullptr);
+    m->parent.assign(h.n_levels, nullptr);
+    m->cells = dev_upload(m->owned, h.cells);
+    m->xyz = dev_upload(m->owned, h.xyz);
+    m->nodes = dev_upload(m->owned, re.nodes);
+    im = m.release();
 }
 
 DeviceSetup::~DeviceSetup() { delete im; }

@@ -66,6 +66,29 @@ void set_last_error(const std::string& m) { g_last_error = m; }
         default: fail(DGMG_EUNSUPPORTED, "unsupported block size");                    \
     }
 
+void* DeviceMemory::alloc(size_t bytes) const {
+    void* p = nullptr;
+    if (has_user) {
+        p = user.alloc(user.ctx, bytes);
+        if (!p) fail(DGMG_ENOMEM, "the caller's allocator returned NULL");
+        if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+            user.free(user.ctx, p);
+            fail(DGMG_EINVAL, "the caller's allocator returned memory that is not 256-byte aligned");
+        }
+        return p;
+    }
+    if (hipMalloc(&p, bytes) != hipSuccess) fail(DGMG_ENOMEM, "hipMalloc failed");
+    return p;
+}
+
+void DeviceMemory::release(void* p) const noexcept {
+    if (!p) return;
+    if (has_user)
+        user.free(user.ctx, p);
+    else
+        (void)hipFree(p);
+}
+
 static double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -153,12 +176,11 @@ struct dgmg_solver {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     size_t prof_used = 0;
 
+    DeviceMemory mem;
     template <typename T>
     T* dalloc(size_t count) {
-        void* p = nullptr;
         if (count == 0) count = 1;
-        hipError_t e = hipMalloc(&p, count * sizeof(T));
-        if (e != hipSuccess) fail(DGMG_ENOMEM, "hipMalloc failed");
+        void* p = mem.alloc(count * sizeof(T));
         allocs.push_back(p);
         dev_bytes += (int64_t)(count * sizeof(T));
         return (T*)p;
@@ -174,7 +196,7 @@ struct dgmg_solver {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
-        for (void* p : allocs) (void)hipFree(p);
+        for (void* p : allocs) mem.release(p);
         if (sc_host) (void)hipHostFree(sc_host);
         if (act_host) (void)hipHostFree(act_host);
     }
@@ -1297,10 +1319,15 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     // assembly, prolongation blocks, Galerkin products and Lanczos estimates
     // on the GPU (the adjoint's conductivity derivatives come from the host
     // assembly)
+    if (mg->allocator) {
+        if (!mg->allocator->alloc || !mg->allocator->free) fail(DGMG_EINVAL, "allocator without alloc or free");
+        s->mem.user = *mg->allocator;
+        s->mem.has_user = true;
+    }
     std::unique_ptr<DeviceSetup> ds;
     if (mg->setup_on_device) {
         if (!mg->device_setup) fail(DGMG_EINVAL, "setup_on_device needs device_setup");
-        ds.reset(new DeviceSetup(*h, re));
+        ds.reset(new DeviceSetup(*h, re, s->mem));
     }
     Faces F = find_faces(*h);
     s->axis0 = F.axis;

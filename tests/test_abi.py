@@ -69,3 +69,37 @@ def test_indefinite_coarse_operator_is_reported():
         api.setup_levels(h, 1, pr["D_cell"] * 1e5, 1.0, 1.0, 1e3, "fhn", pr["params"],
                          penalty=("fixed", -50.0), device_setup=False)
     assert e.value.code == -2
+
+
+PAIRS = [("dgmg_mesh", "Mesh"), ("dgmg_agglo_opts", "AggloOpts"), ("dgmg_disc", "Disc"),
+         ("dgmg_physics", "Physics"), ("dgmg_allocator", "Allocator"), ("dgmg_mg_opts", "MGOpts"),
+         ("dgmg_solver_info", "SolverInfo"), ("dgmg_pcg_opts", "PCGOpts"),
+         ("dgmg_pcg_stats", "PCGStats"), ("dgmg_state", "State")]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Size and every field offset of the binding's structures against the C
+    compiler's layout of the header's structures."""
+    import subprocess
+    import ctypes as C
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dgmg.h"', "int main(void) {"]
+    for cname, pyname in PAIRS:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(F, pyname)._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            cname, key, val = ln.split()
+            got[(cname, key)] = int(val)
+    for cname, pyname in PAIRS:
+        cls = getattr(F, pyname)
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
