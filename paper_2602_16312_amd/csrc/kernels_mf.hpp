@@ -71,20 +71,29 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     __shared__ T Dk[TC][NP];
     __shared__ T Dn[TC][NF][D];                       // row a of the neighbour's D
     __shared__ int hasn[TC][NF];                      // face has a neighbour
-    __shared__ T s1[TC][3][B];                        // 1D-pass partial sums
-    __shared__ T s2[TC][3][B];
-    __shared__ T fq[TC][B][D + 1];                    // cell terms at the cell points
-    // two regions, each shared by arrays whose lifetimes do not overlap:
-    //   rA: neighbour values xn (phases 0-2a), then face fluxes ff (2-2b)
-    //   rB: face-node data fn (2a-2), then tangential integrals fT (2b-3)
+    // four regions, each shared by arrays whose lifetimes do not overlap
+    // (intervals between barriers: 0 stage, 1 = 1x/2a, 2 = 1y/2, 3 = 1z/2b
+    // (2D: 2b/3y), 4 = 3z, 5 = 3y, 6 = 3x):
+    //   rA: neighbour values xn (0-1), face fluxes ff (2-3), 3z sums A3 (4-5)
+    //   rB: face-node data fn (1-2), tangential integrals fT (3-end)
+    //   rC: 1x sums A1 (1-2), 3D cell terms fq (3-4), 3y sums A4 (5-6; 2D 3-4)
+    //   rD: 3D 1y sums A2 (2-3); 2D cell terms fq (2-3)
     constexpr int SXN = TC * NF * B, SFF = TC * NF * QN * (D + 1);
     constexpr int SFN = TC * NF * QN * 4, SFT = TC * NF * QN * 2;
+    constexpr int SC = TC * (D == 3 ? B * (D + 1) : 2 * B), SD = TC * (D == 3 ? 3 * B : B * (D + 1));
     __shared__ T rA[SXN > SFF ? SXN : SFF];
     __shared__ T rB[SFN > SFT ? SFN : SFT];
+    __shared__ T rC[SC];
+    __shared__ T rD[SD];
     T(*xn)[NF][B] = reinterpret_cast<T(*)[NF][B]>(rA);
     T(*ff)[NF][QN][D + 1] = reinterpret_cast<T(*)[NF][QN][D + 1]>(rA);
+    T(*A3)[3][B] = reinterpret_cast<T(*)[3][B]>(rA);
     T(*fn)[NF][QN][4] = reinterpret_cast<T(*)[NF][QN][4]>(rB);
     T(*fT)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(rB);
+    T(*A1)[2][B] = reinterpret_cast<T(*)[2][B]>(rC);
+    T(*A4)[2][B] = reinterpret_cast<T(*)[2][B]>(rC);
+    T(*A2)[3][B] = reinterpret_cast<T(*)[3][B]>(rD);
+    T(*fq)[B][D + 1] = reinterpret_cast<T(*)[B][D + 1]>(D == 3 ? rC : rD);
     const T* Ig = tb + OI;
     const T* Dg = tb + OD;
     const T* Ed = tb + OE;
@@ -145,8 +154,8 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             a0 += Ig[c0 * Q + j0] * x;
             b0 += Dg[c0 * Q + j0] * x;
         }
-        s1[lc][0][i] = a0;
-        s1[lc][1][i] = b0;
+        A1[lc][0][i] = a0;
+        A1[lc][1][i] = b0;
         for (int it = i; it < NF * QN; it += B) {
             const int f = it / QN, m = it - f * QN;
             const int a = f >> 1, eK = f & 1, eN = 1 - eK;
@@ -190,14 +199,14 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         for (int j1 = 0; j1 < Q; ++j1) {
             const int src = c0 + Q * (j1 + Q * c2);
             const T iy = Ig[c1 * Q + j1], dy = Dg[c1 * Q + j1];
-            u0 += iy * s1[lc][0][src];
-            uy += dy * s1[lc][0][src];
-            ux += iy * s1[lc][1][src];
+            u0 += iy * A1[lc][0][src];
+            uy += dy * A1[lc][0][src];
+            ux += iy * A1[lc][1][src];
         }
         if constexpr (D == 3) {
-            s2[lc][0][i] = u0;
-            s2[lc][1][i] = uy;
-            s2[lc][2][i] = ux;
+            A2[lc][0][i] = u0;
+            A2[lc][1][i] = uy;
+            A2[lc][2][i] = ux;
         } else {
             const T gr[3] = {ux, uy, T(0)};
             cell_terms(u0, gr);
@@ -210,7 +219,9 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;   // tangential directions
             const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
             T uK = 0, uN = 0, nK = 0, nN = 0, p1K = 0, p1N = 0, p2K = 0, p2N = 0;
-#pragma unroll
+            // FP64: partial unrolling keeps the register count, and with it
+            // the occupancy, in check
+#pragma unroll(sizeof(T) == 8 ? 1 : Q)
             for (int m2 = 0; m2 < (D == 3 ? Q : 1); ++m2) {
                 const T i2 = D == 3 ? Ig[g2 * Q + m2] : T(1);
                 const T e2 = D == 3 ? Dg[g2 * Q + m2] : T(0);
@@ -265,10 +276,10 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             for (int j2 = 0; j2 < Q; ++j2) {
                 const int src = c0 + Q * (c1 + Q * j2);
                 const T iz = Ig[c2 * Q + j2], dz = Dg[c2 * Q + j2];
-                u += iz * s2[lc][0][src];
-                gr[1] += iz * s2[lc][1][src];
-                gr[0] += iz * s2[lc][2][src];
-                gr[2] += dz * s2[lc][0][src];
+                u += iz * A2[lc][0][src];
+                gr[1] += iz * A2[lc][1][src];
+                gr[0] += iz * A2[lc][2][src];
+                gr[2] += dz * A2[lc][0][src];
             }
             cell_terms(u, gr);
         } else {
@@ -280,8 +291,8 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
                 P += iy * F[0] + dy * F[2];
                 X += iy * F[1];
             }
-            s2[lc][0][i] = P;
-            s2[lc][1][i] = X;
+            A4[lc][0][i] = P;
+            A4[lc][1][i] = X;
         }
         for (int it = i; it < NF * QN; it += B) {
             const int f = it / QN, m = it - f * QN;
@@ -289,7 +300,7 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int m1 = m % Q, m2 = D == 3 ? m / Q : 0;
             T sv = 0, sn = 0;
-#pragma unroll
+#pragma unroll(sizeof(T) == 8 ? Q : QN)
             for (int qf = 0; qf < QN; ++qf) {
                 const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
                 const T i1 = Ig[g1 * Q + m1], i2 = D == 3 ? Ig[g2 * Q + m2] : T(1);
@@ -316,9 +327,9 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
                 X += iz * F[1];
                 Y += iz * F[2];
             }
-            s1[lc][0][i] = W;
-            s1[lc][1][i] = X;
-            s1[lc][2][i] = Y;
+            A3[lc][0][i] = W;
+            A3[lc][1][i] = X;
+            A3[lc][2][i] = Y;
         }
         __syncthreads();
         // ---- phase 3y: items (g0, i1, i2): P = sum_g1 (l_i1(g1) W + l_i1'(g1) Y),
@@ -329,11 +340,11 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             for (int g1 = 0; g1 < Q; ++g1) {
                 const int src = c0 + Q * (g1 + Q * c2);
                 const T iy = Ig[g1 * Q + c1], dy = Dg[g1 * Q + c1];
-                P += iy * s1[lc][0][src] + dy * s1[lc][2][src];
-                X += iy * s1[lc][1][src];
+                P += iy * A3[lc][0][src] + dy * A3[lc][2][src];
+                X += iy * A3[lc][1][src];
             }
-            s2[lc][0][i] = P;
-            s2[lc][1][i] = X;
+            A4[lc][0][i] = P;
+            A4[lc][1][i] = X;
         }
         __syncthreads();
     }
@@ -344,7 +355,7 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
 #pragma unroll
         for (int g0 = 0; g0 < Q; ++g0) {
             const int src = g0 + Q * (c1 + Q * c2);
-            y += Ig[g0 * Q + c0] * s2[lc][0][src] + Dg[g0 * Q + c0] * s2[lc][1][src];
+            y += Ig[g0 * Q + c0] * A4[lc][0][src] + Dg[g0 * Q + c0] * A4[lc][1][src];
         }
         const int ik[3] = {c0, c1, c2};
 #pragma unroll
