@@ -207,6 +207,26 @@ def test_pcg_edge_cases():
     assert e.value.code == -3
 
 
+@pytest.mark.parametrize("n", [1, 3])
+def test_single_level_is_an_exact_solve(n):
+    """Degenerate hierarchies: one level (the V-cycle is the dense coarse
+    solve, so PCG needs one iteration), down to a mesh of one cell (no
+    faces, one ragged tile)."""
+    pr = make_problem("c1", n=n, group=[])
+    A0 = system_matrix(pr)[0].toarray()
+    for prec in ("fp64", "mixed"):
+        h, s = problem.build(pr, precision=prec)
+        assert s.info()["n_levels"] == 1
+        b = np.random.default_rng(10 + n).standard_normal(pr["N"])
+        x = torch.zeros(pr["N"], dtype=torch.float64, device="cuda")
+        say("single level", n, prec)
+        st = api.pcg_solve(s, dev(b), x, tol=1e-12)
+        # FP64: B = A^-1 exactly; mixed: A^-1 up to the FP32 rounding of r
+        # and z, so the outer PCG takes a second iteration to reach 1e-12
+        assert st["converged"] and st["its"] <= (1 if prec == "fp64" else 3), st
+        assert rel(host(x), np.linalg.solve(A0, b)) <= 1e-11
+
+
 def test_bitwise_repeatable():
     pr, mg, h, s = _setup("c2", 64, {}, precision="mixed")
     b = dev(np.random.default_rng(8).standard_normal(pr["N"]))
