@@ -308,13 +308,16 @@ def run_sweep(kind, precision, fine_layout="auto"):
 
 
 def cpu_baseline(pr, tol, nsteps):
+    """The oracle timed on the host cores over the first `nsteps` steps;
+    also returns its solution after those steps."""
     from oracle.stepper import Simulation
+    from workloads.configs import iapp_nodal
     log("cpu baseline: oracle setup")
     sim = Simulation(pr)
     log("cpu baseline: timing steps")
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
-    _, _, stats = sim.run(nsteps, tol, record=False)
+    state, _, stats = sim.run(nsteps, tol, iapp_fn=lambda t: iapp_nodal(pr, t), record=False)
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
@@ -322,7 +325,7 @@ def cpu_baseline(pr, tol, nsteps):
                 kind="oracle",
                 sample=f"first {nsteps} time steps of the same workload (scipy CSR PCG + "
                        f"V-cycle, FP64, tol {tol}); oracle setup excluded; "
-                       f"its={[s['its'] for s in stats]}")
+                       f"its={[s['its'] for s in stats]}"), state[0]
 
 
 def main():
@@ -442,7 +445,16 @@ def main():
         out["mixed_vs_fp64_rel_diff"] = float(np.abs(res["U"] - r64["U"]).max()
                                               / np.abs(r64["U"]).max())
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pr, args.tol, args.cpu_steps)
+        out["cpu_baseline"], U_oracle = cpu_baseline(pr, args.tol, args.cpu_steps)
+        if nrhs == 1:
+            # error of each GPU solver against the oracle over the same steps
+            # (all stopped at the same relative residual)
+            err = {"steps": args.cpu_steps, "tol": args.tol}
+            for prec in ("mixed",) + (() if args.no_fp64 else ("fp64",)):
+                rg = run_gpu(pr, prec, args.cpu_steps, 0, args.tol, fine_layout=args.fine_layout,
+                             setup=args.setup)
+                err[prec] = float(np.linalg.norm(rg["U"] - U_oracle) / np.linalg.norm(U_oracle))
+            out["rel_err_vs_oracle"] = err
     print(json.dumps(out))
 
 
