@@ -95,6 +95,12 @@ int dgmg_hierarchy_info(const dgmg_hierarchy* h, int32_t level, int32_t* n_level
                         int64_t* n_entities);
 /* host out: n_entities(level) parent ids on level+1. */
 int dgmg_hierarchy_parents(const dgmg_hierarchy* h, int32_t level, int64_t* out);
+/* Bounding boxes of the entities of `level` (level 0: the cells), the
+ * boxes that carry the coarse tensor bases (section 5.1): host lo, hi:
+ * n_entities(level) x dim, the smallest and largest vertex coordinates of the
+ * fine cells an entity contains.  Errors: DGMG_EINVAL (null, level out of
+ * range). */
+int dgmg_hierarchy_boxes(const dgmg_hierarchy* h, int32_t level, double* lo, double* hi);
 void dgmg_destroy_hierarchy(dgmg_hierarchy* h);
 
 enum { DGMG_PENALTY_PAPER = 0, DGMG_PENALTY_FIXED = 1 };

@@ -13,7 +13,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOTSPD", -3: "ENAN", -4: "EHIP", -5: "ENOMEM",
 
 # every symbol declared in include/dgmg.h
 EXPORTS = [
-    "dgmg_build_hierarchy", "dgmg_hierarchy_info", "dgmg_hierarchy_parents",
+    "dgmg_build_hierarchy", "dgmg_hierarchy_info", "dgmg_hierarchy_parents", "dgmg_hierarchy_boxes",
     "dgmg_destroy_hierarchy", "dgmg_setup_levels", "dgmg_destroy_solver",
     "dgmg_get_info", "dgmg_pcg_solve", "dgmg_ionic_step", "dgmg_time_step",
     "dgmg_pcg_solve_multi", "dgmg_time_step_multi", "dgmg_apply_multi", "dgmg_vcycle_multi",
@@ -114,6 +114,7 @@ def lib():
         L.dgmg_build_hierarchy.argtypes = [C.POINTER(Mesh), C.POINTER(AggloOpts), C.POINTER(vp)]
         L.dgmg_hierarchy_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), i64p]
         L.dgmg_hierarchy_parents.argtypes = [vp, C.c_int32, i64p]
+        L.dgmg_hierarchy_boxes.argtypes = [vp, C.c_int32, dp, dp]
         L.dgmg_destroy_hierarchy.argtypes = [vp]
         L.dgmg_destroy_hierarchy.restype = None
         L.dgmg_setup_levels.argtypes = [vp, C.POINTER(Disc), C.POINTER(Physics),

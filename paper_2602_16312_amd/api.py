@@ -67,6 +67,14 @@ class Hierarchy:
         F.check(F.lib().dgmg_hierarchy_parents(self._h, level, out.ctypes.data_as(F.i64p)))
         return out
 
+    def boxes(self, level, dim):
+        """dgmg_hierarchy_boxes: (lo, hi) of every entity of `level`."""
+        lo = np.empty((self.n_entities(level), dim))
+        hi = np.empty_like(lo)
+        F.check(F.lib().dgmg_hierarchy_boxes(self._h, level, lo.ctypes.data_as(F.dp),
+                                             hi.ctypes.data_as(F.dp)))
+        return lo, hi
+
     def __del__(self):
         if getattr(self, "_h", None):
             F.lib().dgmg_destroy_hierarchy(self._h)

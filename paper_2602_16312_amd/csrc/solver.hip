@@ -1268,6 +1268,18 @@ int dgmg_hierarchy_parents(const dgmg_hierarchy* h, int32_t level, int64_t* out)
     API_END
 }
 
+int dgmg_hierarchy_boxes(const dgmg_hierarchy* h, int32_t level, double* lo, double* hi) {
+    API_BEGIN
+    if (!h || !lo || !hi) fail(DGMG_EINVAL, "null argument");
+    if (level < 0 || level >= h->n_levels) fail(DGMG_EINVAL, "level out of range");
+    std::vector<double> l, u;
+    level_boxes(*h, level, l, u);
+    std::copy(l.begin(), l.end(), lo);
+    std::copy(u.begin(), u.end(), hi);
+    return DGMG_OK;
+    API_END
+}
+
 void dgmg_destroy_hierarchy(dgmg_hierarchy* h) { delete h; }
 
 int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg_physics* ph,

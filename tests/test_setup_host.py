@@ -5,6 +5,7 @@ import pytest
 import scipy.sparse as sp
 
 from paper_2602_16312_amd import problem
+from paper_2602_16312_amd import _ffi as F
 from workloads import make_problem
 from oracle.assemble import system_matrix
 from oracle.hierarchy import build_hierarchy as oracle_hierarchy
@@ -121,3 +122,22 @@ def test_device_setup_option_needs_device_data():
         problem.build(pr, device_setup=False, setup="device")
     with pytest.raises(ValueError):
         problem.build(pr, device_setup=False, setup="gpu")
+
+
+@pytest.mark.parametrize("name,kw", [("c2", dict(n=16)), ("c4", dict(h=0.09)), ("c3", dict(n=4))])
+def test_hierarchy_boxes_match_oracle(name, kw):
+    """The agglomerates' bounding boxes (the supports of the coarse bases) as
+    exported by the library equal the oracle's (min/max are exact), and the
+    level-0 boxes are the cells' own vertex ranges."""
+    pr = make_problem(name, **kw)
+    h, s = problem.build(pr, device_setup=False)
+    oh = oracle_hierarchy(pr)
+    d = pr["dim"]
+    lo0, hi0 = h.boxes(0, d)
+    X = pr["xyz"][pr["cell_vtx"]]
+    assert np.array_equal(lo0, X.min(axis=1)) and np.array_equal(hi0, X.max(axis=1))
+    for l in range(1, len(oh["n"])):
+        lo, hi = h.boxes(l, d)
+        assert np.array_equal(lo, oh["lo"][l]) and np.array_equal(hi, oh["hi"][l]), l
+    with pytest.raises(F.DGMGError):
+        h.boxes(len(oh["n"]), d)
