@@ -336,6 +336,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline", action="store_true",
+                    help="time the oracle on the 3D workloads too (its set-up alone takes minutes "
+                         "there; the default line, c2, always carries it)")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--workload", default="c2", choices=list(WORKLOADS),
                     help="c2: 256x256 Q2 (default bench line); c3: 64^3 Q2 cube; "
@@ -444,7 +447,10 @@ def main():
                        "iters": _stats(r64["its"])}
         out["mixed_vs_fp64_rel_diff"] = float(np.abs(res["U"] - r64["U"]).max()
                                               / np.abs(r64["U"]).max())
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "c2" and not args.cpu_baseline:
+        out["cpu_baseline"] = {"skipped": "the oracle's set-up on this 3D workload takes minutes; "
+                                          "pass --cpu-baseline to time it (the c2 line carries it)"}
+    elif not args.no_cpu_baseline:
         out["cpu_baseline"], U_oracle = cpu_baseline(pr, args.tol, args.cpu_steps)
         if nrhs == 1:
             # error of each GPU solver against the oracle over the same steps
