@@ -39,7 +39,10 @@ class SensorMisfit(torch.autograd.Function):
     @staticmethod
     def forward(ctx, s, prob, targets, steps, tol, checkpoint, precision):
         s_host = s.detach().double().cpu().numpy()
-        h, solver = problem.build(prob, precision=precision, cell_scale=s_host, adjoint=True)
+        # hierarchy on the GPU (the fine blocks and dA/ds_K come from the host
+        # assembly when the adjoint is requested), memory from torch
+        h, solver = problem.build(prob, precision=precision, cell_scale=s_host, adjoint=True,
+                                  setup="device", allocator="torch")
         api.set_sensors(solver, prob["sensor_cell"], prob["sensor_ref"])
         st = _fresh_state(prob)
         loss = _zeros(1)
