@@ -214,12 +214,12 @@ def test_single_level_is_an_exact_solve(n):
     faces, one ragged tile)."""
     pr = make_problem("c1", n=n, group=[])
     A0 = system_matrix(pr)[0].toarray()
-    for prec in ("fp64", "mixed"):
-        h, s = problem.build(pr, precision=prec)
+    for prec, where in (("fp64", "host"), ("mixed", "host"), ("fp64", "device")):
+        h, s = problem.build(pr, precision=prec, setup=where)
         assert s.info()["n_levels"] == 1
         b = np.random.default_rng(10 + n).standard_normal(pr["N"])
         x = torch.zeros(pr["N"], dtype=torch.float64, device="cuda")
-        say("single level", n, prec)
+        say("single level", n, prec, where)
         st = api.pcg_solve(s, dev(b), x, tol=1e-12)
         # FP64: B = A^-1 exactly; mixed: A^-1 up to the FP32 rounding of r
         # and z, so the outer PCG takes a second iteration to reach 1e-12
