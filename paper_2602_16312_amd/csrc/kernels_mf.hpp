@@ -219,29 +219,40 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;   // tangential directions
             const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
             T uK = 0, uN = 0, nK = 0, nN = 0, p1K = 0, p1N = 0, p2K = 0, p2N = 0;
-            // FP64: partial unrolling keeps the register count, and with it
-            // the occupancy, in check
-#pragma unroll(sizeof(T) == 8 ? 1 : Q)
+            // sums over m1 first, then weighted by the m2 factor (the
+            // tensor weights are never formed); FP64: partial unrolling keeps
+            // the register count, and with it the occupancy, in check
+#pragma unroll 1
             for (int m2 = 0; m2 < (D == 3 ? Q : 1); ++m2) {
-                const T i2 = D == 3 ? Ig[g2 * Q + m2] : T(1);
-                const T e2 = D == 3 ? Dg[g2 * Q + m2] : T(0);
+                T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
 #pragma unroll
                 for (int m1 = 0; m1 < Q; ++m1) {
                     const T* nd = fn[lc][f][m1 + Q * m2];
-                    const T tI = Ig[g1 * Q + m1] * i2;
-                    const T t1d = Dg[g1 * Q + m1] * i2;
-                    const T vK = nd[0], vN = nd[1];
-                    uK += tI * vK;
-                    uN += tI * vN;
-                    nK += tI * nd[2];
-                    nN += tI * nd[3];
-                    p1K += t1d * vK;
-                    p1N += t1d * vN;
-                    if (D == 3) {
-                        const T t2d = Ig[g1 * Q + m1] * e2;
-                        p2K += t2d * vK;
-                        p2N += t2d * vN;
-                    }
+                    const T iy = Ig[g1 * Q + m1], dy = Dg[g1 * Q + m1];
+                    a0 += iy * nd[0];
+                    a1 += iy * nd[1];
+                    a2 += iy * nd[2];
+                    a3 += iy * nd[3];
+                    a4 += dy * nd[0];
+                    a5 += dy * nd[1];
+                }
+                if (D == 3) {
+                    const T i2 = Ig[g2 * Q + m2], e2 = Dg[g2 * Q + m2];
+                    uK += i2 * a0;
+                    uN += i2 * a1;
+                    nK += i2 * a2;
+                    nN += i2 * a3;
+                    p1K += i2 * a4;
+                    p1N += i2 * a5;
+                    p2K += e2 * a0;
+                    p2N += e2 * a1;
+                } else {
+                    uK = a0;
+                    uN = a1;
+                    nK = a2;
+                    nN = a3;
+                    p1K = a4;
+                    p1N = a5;
                 }
             }
             T wK = Dk[lc][pk<D>(a, a)] * hinv[a] * nK + Dk[lc][pk<D>(a, t1)] * hinv[t1] * p1K;
@@ -300,14 +311,26 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int m1 = m % Q, m2 = D == 3 ? m / Q : 0;
             T sv = 0, sn = 0;
-#pragma unroll(sizeof(T) == 8 ? Q : QN)
-            for (int qf = 0; qf < QN; ++qf) {
-                const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
-                const T i1 = Ig[g1 * Q + m1], i2 = D == 3 ? Ig[g2 * Q + m2] : T(1);
-                const T* F = ff[lc][f][qf];
-                sv += F[0] * i1 * i2 + F[1 + t1] * Dg[g1 * Q + m1] * i2;
-                if (D == 3) sv += F[1 + t2] * i1 * Dg[g2 * Q + m2];
-                sn += F[1 + a] * i1 * i2;
+            // sums over g1 first, then weighted by the g2 factor
+#pragma unroll 1
+            for (int g2 = 0; g2 < (D == 3 ? Q : 1); ++g2) {
+                T e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+                for (int g1 = 0; g1 < Q; ++g1) {
+                    const T* F = ff[lc][f][g1 + Q * g2];
+                    const T i1 = Ig[g1 * Q + m1], d1 = Dg[g1 * Q + m1];
+                    e0 += F[0] * i1 + F[1 + t1] * d1;
+                    if (D == 3) e1 += F[1 + t2] * i1;
+                    e2 += F[1 + a] * i1;
+                }
+                if (D == 3) {
+                    const T i2 = Ig[g2 * Q + m2], d2 = Dg[g2 * Q + m2];
+                    sv += i2 * e0 + d2 * e1;
+                    sn += i2 * e2;
+                } else {
+                    sv = e0;
+                    sn = e2;
+                }
             }
             fT[lc][f][m][0] = sv;
             fT[lc][f][m][1] = sn;
