@@ -78,7 +78,7 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     //   rB: face-node data fn (1-2), tangential integrals fT (3-end)
     //   rC: 1x sums A1 (1-2), 3D cell terms fq (3-4), 3y sums A4 (5-6; 2D 3-4)
     //   rD: 3D 1y sums A2 (2-3); 2D cell terms fq (2-3)
-    constexpr int SXN = TC * NF * B, SFF = TC * NF * QN * (D + 1);
+    constexpr int SXN = TC * NF * B, SFF = TC * NF * QN * 2;
     constexpr int SFN = TC * NF * QN * 4, SFT = TC * NF * QN * 2;
     constexpr int SC = TC * (D == 3 ? B * (D + 1) : 2 * B), SD = TC * (D == 3 ? 3 * B : B * (D + 1));
     __shared__ T rA[SXN > SFF ? SXN : SFF];
@@ -86,7 +86,7 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     __shared__ T rC[SC];
     __shared__ T rD[SD];
     T(*xn)[NF][B] = reinterpret_cast<T(*)[NF][B]>(rA);
-    T(*ff)[NF][QN][D + 1] = reinterpret_cast<T(*)[NF][QN][D + 1]>(rA);
+    T(*ff)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(rA);
     T(*A3)[3][B] = reinterpret_cast<T(*)[3][B]>(rA);
     T(*fn)[NF][QN][4] = reinterpret_cast<T(*)[NF][QN][4]>(rB);
     T(*fT)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(rB);
@@ -265,11 +265,10 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             if (!hasn[lc][f]) w = 0;                  // boundary face: no terms
             const T sig = etaa[a] * T(0.5) * (Dk[lc][pk<D>(a, a)] + Dn[lc][f][a]);
             const T jmp = uK - uN;
+            // value flux, and the conormal flux factor: it is tested against
+            // n.D_K grad v, i.e. times D_K[a][k] / h_k for each direction k
             ff[lc][f][qf][0] = (T(-0.5) * sgn * (wK + wN) + sig * jmp) * w;
-            const T fc = T(-0.5) * sgn * jmp * w;
-            ff[lc][f][qf][1 + a] = fc * Dk[lc][pk<D>(a, a)] * hinv[a];
-            ff[lc][f][qf][1 + t1] = fc * Dk[lc][pk<D>(a, t1)] * hinv[t1];
-            if (D == 3) ff[lc][f][qf][1 + t2] = fc * Dk[lc][pk<D>(a, t2)] * hinv[t2];
+            ff[lc][f][qf][1] = T(-0.5) * sgn * jmp * w;
         }
     }
     __syncthreads();
@@ -310,30 +309,33 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const int a = f >> 1;
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int m1 = m % Q, m2 = D == 3 ? m / Q : 0;
-            T sv = 0, sn = 0;
+            // D_K[a][k] / h_k of the normal (ka) and tangential (k1, k2) directions
+            const T ka = Dk[lc][pk<D>(a, a)] * hinv[a];
+            const T k1 = Dk[lc][pk<D>(a, t1)] * hinv[t1];
+            const T k2 = D == 3 ? Dk[lc][pk<D>(a, t2)] * hinv[t2] : T(0);
+            T sv = 0, sc = 0;
             // sums over g1 first, then weighted by the g2 factor
 #pragma unroll 1
             for (int g2 = 0; g2 < (D == 3 ? Q : 1); ++g2) {
-                T e0 = 0, e1 = 0, e2 = 0;
+                T e0 = 0, e1 = 0;
 #pragma unroll
                 for (int g1 = 0; g1 < Q; ++g1) {
                     const T* F = ff[lc][f][g1 + Q * g2];
                     const T i1 = Ig[g1 * Q + m1], d1 = Dg[g1 * Q + m1];
-                    e0 += F[0] * i1 + F[1 + t1] * d1;
-                    if (D == 3) e1 += F[1 + t2] * i1;
-                    e2 += F[1 + a] * i1;
+                    e0 += F[0] * i1 + k1 * F[1] * d1;
+                    e1 += F[1] * i1;
                 }
                 if (D == 3) {
                     const T i2 = Ig[g2 * Q + m2], d2 = Dg[g2 * Q + m2];
-                    sv += i2 * e0 + d2 * e1;
-                    sn += i2 * e2;
+                    sv += i2 * e0 + k2 * e1 * d2;
+                    sc += i2 * e1;
                 } else {
                     sv = e0;
-                    sn = e2;
+                    sc = e1;
                 }
             }
             fT[lc][f][m][0] = sv;
-            fT[lc][f][m][1] = sn;
+            fT[lc][f][m][1] = ka * sc;
         }
     }
     __syncthreads();
