@@ -227,6 +227,10 @@ typedef struct {
      * agglomerates form a conforming grid of boxes use AXIS_ELL unless
      * fine_layout = TILE_ELL was asked for */
     int32_t level_layout[DGMG_MAX_LEVELS];
+    /* prolongation from level+1 to level: k > 0 when its blocks take only k
+     * distinct values (nested boxes) and are stored as a table of those with
+     * a type per entity; 0 when every entity's block is stored */
+    int32_t prolong_types[DGMG_MAX_LEVELS];
 } dgmg_solver_info;
 int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info);
 

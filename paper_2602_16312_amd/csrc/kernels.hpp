@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
                                                   const T* __restrict__ vb, const T* __restrict__ rhs,
                                                   T* __restrict__ r, T* __restrict__ d, T c1,
                                                   T* __restrict__ xout, double* __restrict__ partial,
-                                                  const T* __restrict__ P, T* __restrict__ rp) {
+                                                  const T* __restrict__ P, T* __restrict__ rp,
+                                                  const int32_t* __restrict__ ptype) {
     DGMG_TILE_THREAD(T, B)
     double contrib = 0.0;
     T rr = 0;
@@ -285,14 +286,16 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
         rs[threadIdx.x] = rr;
         __syncthreads();
         if (active) {
-            // thread (lc, j): column j of P_cell, contiguous in i
+            // thread (lc, j): column j of P_cell, contiguous in i (tile
+            // layout) or strided by B (row-major block of the cell's type)
             constexpr int TR = Tile<T, B>::TR;
             const int j = threadIdx.x - lc * B;
-            const T* Pc = P + ((size_t)tile * B + j) * TR + lc * B;
+            const T* Pc = ptype ? P + (size_t)ptype[cell] * B * B + j : P + ((size_t)tile * B + j) * TR + lc * B;
+            const int ks = ptype ? B : 1;
             const T* rc = rs + lc * B;
             T s = 0;
 #pragma unroll
-            for (int k = 0; k < B; ++k) s += Pc[k] * rc[k];
+            for (int k = 0; k < B; ++k) s += Pc[k * ks] * rc[k];
             rp[t] = s;
         }
     }
@@ -369,24 +372,28 @@ __global__ __launch_bounds__(kWG) void k_restrict_sum(int32_t nC, const int32_t*
 template <typename T, int B>
 __global__ __launch_bounds__(kWG) void k_prolong_add(int32_t n, const int32_t* __restrict__ parent,
                                                      const T* __restrict__ P, const T* __restrict__ xc,
-                                                     const T* __restrict__ dc, T* __restrict__ x) {
+                                                     const T* __restrict__ dc, T* __restrict__ x,
+                                                     const int32_t* __restrict__ ptype) {
     constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
     const int tile = blockIdx.x;
     const int lc = threadIdx.x / B;
     const int e = tile * TC + lc;
     if (lc >= TC || e >= n) return;
-    const int t = e * B + (threadIdx.x - lc * B);
+    const int i = threadIdx.x - lc * B;
+    const int t = e * B + i;
     const int K = parent[e];
-    const T* Pe = P + (size_t)tile * B * TR + threadIdx.x;
+    // row i of P_e: tile layout (stride TR) or the row-major block of e's type
+    const T* Pe = ptype ? P + (size_t)ptype[e] * B * B + (size_t)i * B : P + (size_t)tile * B * TR + threadIdx.x;
+    const size_t js = ptype ? 1 : TR;
     const T* v = xc + (size_t)K * B;
     T acc = 0;
     if (dc) {
         const T* w = dc + (size_t)K * B;
 #pragma unroll
-        for (int j = 0; j < B; ++j) acc += Pe[(size_t)j * TR] * (v[j] + w[j]);
+        for (int j = 0; j < B; ++j) acc += Pe[j * js] * (v[j] + w[j]);
     } else {
 #pragma unroll
-        for (int j = 0; j < B; ++j) acc += Pe[(size_t)j * TR] * v[j];
+        for (int j = 0; j < B; ++j) acc += Pe[j * js] * v[j];
     }
     x[t] += acc;
 }

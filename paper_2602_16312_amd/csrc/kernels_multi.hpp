@@ -152,7 +152,8 @@ __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __r
                                                     const T* __restrict__ vb, const T* __restrict__ rhs,
                                                     T* __restrict__ r, T* __restrict__ d, T c1,
                                                     T* __restrict__ xout, double* __restrict__ partial,
-                                                    const T* __restrict__ P, T* __restrict__ rp) {
+                                                    const T* __restrict__ P, T* __restrict__ rp,
+                                                    const int32_t* __restrict__ ptype) {
     DGMG_TILE_THREAD(T, B)
     double contrib[R];
     T rr[R];
@@ -203,13 +204,14 @@ __global__ __launch_bounds__(kWG) void k_residual_m(LevelArgs<T> L, const T* __r
         if (active) {
             constexpr int TR = Tile<T, B>::TR;
             const int j = threadIdx.x - lc * B;
-            const T* Pc = P + ((size_t)tile * B + j) * TR + lc * B;
+            const T* Pc = ptype ? P + (size_t)ptype[cell] * B * B + j : P + ((size_t)tile * B + j) * TR + lc * B;
+            const int ks = ptype ? B : 1;
             T s[R];
 #pragma unroll
             for (int q = 0; q < R; ++q) s[q] = 0;
 #pragma unroll
             for (int k = 0; k < B; ++k) {
-                const T pk = Pc[k];
+                const T pk = Pc[k * ks];
 #pragma unroll
                 for (int q = 0; q < R; ++q) s[q] += pk * rs[(lc * B + k) * R + q];
             }
@@ -411,15 +413,18 @@ __global__ __launch_bounds__(kWG) void k_restrict_sum_m(int32_t nC, const int32_
 template <typename T, int B, int R>
 __global__ __launch_bounds__(kWG) void k_prolong_add_m(int32_t n, const int32_t* __restrict__ parent,
                                                        const T* __restrict__ P, const T* __restrict__ xc,
-                                                       const T* __restrict__ dc, T* __restrict__ x) {
+                                                       const T* __restrict__ dc, T* __restrict__ x,
+                                                       const int32_t* __restrict__ ptype) {
     constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
     const int tile = blockIdx.x;
     const int lc = threadIdx.x / B;
     const int e = tile * TC + lc;
     if (lc >= TC || e >= n) return;
-    const int t = e * B + (threadIdx.x - lc * B);
+    const int i = threadIdx.x - lc * B;
+    const int t = e * B + i;
     const int K = parent[e];
-    const T* Pe = P + (size_t)tile * B * TR + threadIdx.x;
+    const T* Pe = ptype ? P + (size_t)ptype[e] * B * B + (size_t)i * B : P + (size_t)tile * B * TR + threadIdx.x;
+    const size_t js = ptype ? 1 : TR;
     const T* v = xc + (size_t)K * B * R;
     const T* w = dc ? dc + (size_t)K * B * R : nullptr;
     T acc[R];
@@ -427,7 +432,7 @@ __global__ __launch_bounds__(kWG) void k_prolong_add_m(int32_t n, const int32_t*
     for (int q = 0; q < R; ++q) acc[q] = 0;
 #pragma unroll 8
     for (int j = 0; j < B; ++j) {
-        const T p = Pe[(size_t)j * TR];
+        const T p = Pe[j * js];
 #pragma unroll
         for (int q = 0; q < R; ++q) acc[q] += p * (w ? v[j * R + q] + w[j * R + q] : v[j * R + q]);
     }

@@ -109,6 +109,8 @@ struct DevLevel {
     int32_t *up = nullptr, *lo = nullptr;                  // axis-ELL neighbours
     int32_t *child_ptr = nullptr, *child_list = nullptr;  // children on level l-1
     int32_t* parent = nullptr;                             // parent on level l+1
+    int32_t* ptype = nullptr;                              // P_e = table[ptype[e]] when set
+    int32_t ntypes = 0;                                    // distinct blocks in that table
     double *vals64 = nullptr, *dinv64 = nullptr, *P64 = nullptr;
     float *vals32 = nullptr, *dinv32 = nullptr, *P32 = nullptr;
     void *vb = nullptr, *vx = nullptr, *vx2 = nullptr, *vr = nullptr, *vd = nullptr, *vd2 = nullptr;
@@ -301,16 +303,16 @@ static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, c
 template <typename T, int R = 1>
 static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, const T* rhs,
                             T* r, T* d, T c1, T* xout, double* partial, hipStream_t st,
-                            const T* P = nullptr, T* rp = nullptr) {
+                            const T* P = nullptr, T* rp = nullptr, const int32_t* ptype = nullptr) {
     ProfScope ps(s, PK_RESIDUAL, level_index(s, L), st);
     DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
             if (vb) {
                 DISPATCH_B(s->b, k_residual<T, BV, true, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
             } else {
                 DISPATCH_B(s->b, k_residual<T, BV, false, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
             }
         } else if constexpr (LYV == LY_MF) {
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
@@ -320,20 +322,20 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
                 if (s->mfma && s->b == 8) {
                     if (vb)
                         k_residual_m<float, 8, 8, true, AXV, true><<<tiles_for<float, 8>(L), kWG, 0, st>>>(
-                            largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp);
+                            largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype);
                     else
                         k_residual_m<float, 8, 8, false, AXV, true><<<tiles_for<float, 8>(L), kWG, 0, st>>>(
-                            largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp);
+                            largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype);
                     done = true;
                 }
             }
             if (!done) {
                 if (vb) {
                     DISPATCH_B(s->b, k_residual_m<T, BV, R, true, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                         largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+                                         largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
                 } else {
                     DISPATCH_B(s->b, k_residual_m<T, BV, R, false, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
-                                         largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp));
+                                         largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
                 }
             }
         }
@@ -434,7 +436,7 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     T* rp = d2;   // free: no step result or pending correction lives there
     if (pending) {
         launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, (T*)nullptr, (T*)nullptr, c1, x2,
-                              nullptr, st, Pof<T>(L), rp);
+                              nullptr, st, Pof<T>(L), rp, L.ptype);
         std::swap(x, x2);
         xzero = false;
         pending = false;
@@ -445,7 +447,7 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
             xzero = false;
         }
         launch_residual<T, R>(s, L, x, (const T*)nullptr, b, (T*)nullptr, (T*)nullptr, c1, (T*)nullptr,
-                              nullptr, st, Pof<T>(L), rp);
+                              nullptr, st, Pof<T>(L), rp, L.ptype);
     }
     {
     ProfScope ps(s, PK_RESTRICT, l, st);
@@ -463,10 +465,10 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     ProfScope ps(s, PK_PROLONG, l, st);
     if constexpr (R == 1) {
         DISPATCH_B(s->b, k_prolong_add<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent, Pof<T>(L), xc,
-                                                                                     dc, x));
+                                                                                     dc, x, L.ptype));
     } else {
         DISPATCH_B(s->b, k_prolong_add_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent,
-                                                                                         Pof<T>(L), xc, dc, x));
+                                                                                         Pof<T>(L), xc, dc, x, L.ptype));
     }
     }
     for (int k = 0; k < s->cheb_s; ++k) sweep();
@@ -850,6 +852,45 @@ static std::vector<T> interleave_P(const std::vector<double>& P, int b, int64_t 
     return out;
 }
 
+// Distinct b x b blocks of P (bitwise equal): true, with a type per entity and
+// the row-major table of distinct blocks, when there are at most `maxt`.
+constexpr int kMaxPTypes = 64;
+static bool distinct_blocks(const std::vector<double>& P, int b, int64_t n, int maxt, std::vector<int32_t>& type,
+                            std::vector<double>& table) {
+    const size_t bb = (size_t)b * b;
+    std::vector<uint64_t> h(n);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < n; ++e) {
+        uint64_t x = 1469598103934665603ull;   // FNV-1a over the block's bytes
+        const unsigned char* c = reinterpret_cast<const unsigned char*>(&P[(size_t)e * bb]);
+        for (size_t k = 0; k < bb * sizeof(double); ++k) x = (x ^ c[k]) * 1099511628211ull;
+        h[e] = x;
+    }
+    std::vector<uint64_t> th;
+    std::vector<int64_t> rep;
+    type.assign(n, -1);
+    for (int64_t e = 0; e < n; ++e) {
+        int t = -1;
+        for (size_t k = 0; k < th.size(); ++k)
+            if (th[k] == h[e] &&
+                std::memcmp(&P[(size_t)e * bb], &P[(size_t)rep[k] * bb], bb * sizeof(double)) == 0) {
+                t = (int)k;
+                break;
+            }
+        if (t < 0) {
+            if ((int)th.size() == maxt) return false;
+            t = (int)th.size();
+            th.push_back(h[e]);
+            rep.push_back(e);
+        }
+        type[e] = t;
+    }
+    table.resize(rep.size() * bb);
+    for (size_t k = 0; k < rep.size(); ++k)
+        std::copy(&P[(size_t)rep[k] * bb], &P[(size_t)rep[k] * bb] + bb, &table[k * bb]);
+    return true;
+}
+
 template <typename T>
 static std::vector<T> convert(const std::vector<double>& a) {
     std::vector<T> out(a.size());
@@ -1034,8 +1075,19 @@ static void upload_level(dgmg_solver* s, int l) {
     if (!last) {
         std::vector<int32_t> par(s->parents[l].begin(), s->parents[l].end());
         L.parent = s->upload(par);
-        L.P64 = s->upload(interleave_P<double>(s->Ph[l], b, A.n));
-        if (s->prec == DGMG_PREC_MIXED) L.P32 = s->upload(interleave_P<float>(s->Ph[l], b, A.n));
+        std::vector<int32_t> ptype;
+        std::vector<double> ptab;
+        if (distinct_blocks(s->Ph[l], b, A.n, kMaxPTypes, ptype, ptab)) {
+            // few distinct prolongation blocks (boxes nested in boxes): a
+            // table of them and a type per entity instead of one block each
+            L.ptype = s->upload(ptype);
+            L.ntypes = (int32_t)(ptab.size() / ((size_t)b * b));
+            L.P64 = s->upload(ptab);
+            if (s->prec == DGMG_PREC_MIXED) L.P32 = s->upload(convert<float>(ptab));
+        } else {
+            L.P64 = s->upload(interleave_P<double>(s->Ph[l], b, A.n));
+            if (s->prec == DGMG_PREC_MIXED) L.P32 = s->upload(interleave_P<float>(s->Ph[l], b, A.n));
+        }
     }
     if (l > 0) {
         const auto& par = s->parents[l - 1];
@@ -1505,6 +1557,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
                                   : Lv.ax ? DGMG_LAYOUT_AXIS_ELL : DGMG_LAYOUT_TILE_ELL;
     }
     s->info.fine_layout = s->info.level_layout[0];
+    for (int l = 0; l < s->L; ++l) s->info.prolong_types[l] = s->on_device ? s->lv[l].ntypes : 0;
     *out = guard.release();
     return DGMG_OK;
     API_END

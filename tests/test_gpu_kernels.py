@@ -57,6 +57,22 @@ def test_apply_all_levels(name, n, kw, layout):
         assert rel(host(y), ref) <= 2e-6
 
 
+def test_prolongation_tables_on_box_hierarchies():
+    """Nested boxes: every level's prolongation blocks take 2^d distinct
+    values (child positions) and are stored as a table; the V-cycle with
+    them matches the oracle's.  Jittered fine cells keep one block each."""
+    pr, mg, h, s = _setup("c3", 8, {}, precision="fp64")
+    pt = s.info()["prolong_types"]
+    assert pt[:-1] == [8] * (len(pt) - 1), pt
+    r = np.random.default_rng(12).standard_normal(pr["N"])
+    z = torch.empty(pr["N"], dtype=torch.float64, device="cuda")
+    say("vcycle with prolongation tables")
+    api.vcycle(s, dev(r), z)
+    assert rel(host(z), mg(r)) <= 1e-11
+    pr2, mg2, h2, s2 = _setup("c2", 64, {}, precision="mixed")
+    assert s2.info()["prolong_types"][0] == 0
+
+
 def test_irregular_agglomerates_keep_tile_layout():
     """STR agglomerates of the shell do not form a grid: its coarse levels
     keep the tile layout (faces stored for both cells), and their applies
