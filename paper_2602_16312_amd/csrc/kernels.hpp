@@ -199,19 +199,23 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int l
 
 template <typename T, int B, bool VB>
 __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cell, bool active,
-                                          const T* __restrict__ va, const T* __restrict__ vb);
+                                          const T* __restrict__ va, const T* __restrict__ vb,
+                                          T** lds_free);
 
 // Operator layouts of a level: tile-ELL, axis-ELL, matrix-free boxes.
 enum { LY_TILE = 0, LY_AXIS = 1, LY_MF = 2 };
 
 // (A (va + vb)) at the thread's row for layout LY.  The matrix-free product
 // synchronises the workgroup, so every thread calls this; rows of inactive
-// threads are not used.
+// threads are not used.  When lds_free is given, the matrix-free product
+// stores there an LDS region of at least kWG values that no thread reads
+// any more (usable by the caller's epilogue without a further barrier).
 template <typename T, int B, bool VB, int LY>
 __device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int tile, int lc, int cell, bool active,
-                                       const T* __restrict__ va, const T* __restrict__ vb) {
+                                       const T* __restrict__ va, const T* __restrict__ vb,
+                                       T** lds_free = nullptr) {
     if constexpr (LY == LY_MF) {
-        return mf_row_apply<T, B, VB>(L, lc, cell, active, va, vb);
+        return mf_row_apply<T, B, VB>(L, lc, cell, active, va, vb, lds_free);
     } else {
         if (!active) return T(0);
         if constexpr (LY == LY_AXIS)
@@ -273,7 +277,8 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
     DGMG_TILE_THREAD(T, B)
     double contrib = 0.0;
     T rr = 0;
-    const T a = row_apply<T, B, VB, LY>(L, tile, lc, cell, active, va, vb);
+    T* lds_free = nullptr;
+    const T a = row_apply<T, B, VB, LY>(L, tile, lc, cell, active, va, vb, &lds_free);
     if (active) {
         rr = rhs[t] - a;
         if (r) r[t] = rr;
@@ -282,7 +287,10 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
         contrib = (double)rr * (double)rr;
     }
     if (P) {
-        __shared__ T rs[kWG];
+        // the matrix-free product hands back a free LDS region (its own
+        // occupancy is LDS-bound); the block layouts use their own
+        __shared__ T rs_own[LY == LY_MF ? 1 : kWG];
+        T* rs = LY == LY_MF ? lds_free : rs_own;
         rs[threadIdx.x] = rr;
         __syncthreads();
         if (active) {

@@ -59,7 +59,8 @@ __device__ __forceinline__ int pk(int a, int b) {
 // pass below maps item i of a cell to thread i of that cell (B items).
 template <typename T, int B, bool VB>
 __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cell, bool active,
-                                          const T* __restrict__ va, const T* __restrict__ vb) {
+                                          const T* __restrict__ va, const T* __restrict__ vb,
+                                          T** lds_free) {
     const MfConst<T>& C = L.mf;
     constexpr int TC = Tile<T, B>::TC, D = dim_of<B>(), Q = mf_q<B>(), NF = 2 * D;
     constexpr int QN = D == 3 ? Q * Q : Q;            // face nodes = face quadrature points
@@ -374,7 +375,10 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         __syncthreads();
     }
     // ---- phase 3x: test function I = (i0, i1, i2): sum_g0 (l_i0(g0) P + l_i0'(g0) X'),
-    //      plus the face terms times the test function's normal factor
+    //      plus the face terms times the test function's normal factor.
+    // rA (last read before the previous barrier) is free from here on.
+    static_assert((SXN > SFF ? SXN : SFF) >= kWG, "free region smaller than a workgroup");
+    if (lds_free) *lds_free = rA;
     T y = 0;
     if (slot) {
 #pragma unroll
