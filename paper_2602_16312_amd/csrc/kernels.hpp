@@ -390,9 +390,10 @@ __global__ __launch_bounds__(kWG) void k_prolong_add(int32_t n, const int32_t* _
     const int i = threadIdx.x - lc * B;
     const int t = e * B + i;
     const int K = parent[e];
-    // row i of P_e: tile layout (stride TR) or the row-major block of e's type
-    const T* Pe = ptype ? P + (size_t)ptype[e] * B * B + (size_t)i * B : P + (size_t)tile * B * TR + threadIdx.x;
-    const size_t js = ptype ? 1 : TR;
+    // row i of P_e: tile layout (stride TR) or the transposed block of e's
+    // type (stride B); either way the lanes of a row read consecutive words
+    const T* Pe = ptype ? P + (size_t)ptype[e] * B * B + i : P + (size_t)tile * B * TR + threadIdx.x;
+    const size_t js = ptype ? B : TR;
     const T* v = xc + (size_t)K * B;
     T acc = 0;
     if (dc) {

@@ -423,8 +423,8 @@ __global__ __launch_bounds__(kWG) void k_prolong_add_m(int32_t n, const int32_t*
     const int i = threadIdx.x - lc * B;
     const int t = e * B + i;
     const int K = parent[e];
-    const T* Pe = ptype ? P + (size_t)ptype[e] * B * B + (size_t)i * B : P + (size_t)tile * B * TR + threadIdx.x;
-    const size_t js = ptype ? 1 : TR;
+    const T* Pe = ptype ? P + (size_t)ptype[e] * B * B + i : P + (size_t)tile * B * TR + threadIdx.x;
+    const size_t js = ptype ? B : TR;
     const T* v = xc + (size_t)K * B * R;
     const T* w = dc ? dc + (size_t)K * B * R : nullptr;
     T acc[R];

@@ -242,6 +242,11 @@ template <>
 const double* Pof<double>(const DevLevel& L) { return L.P64; }
 template <>
 const float* Pof<float>(const DevLevel& L) { return L.P32; }
+// the prolongation's blocks: with a type table, its transposed half
+template <typename T>
+static const T* PofT(const DevLevel& L, int b) {
+    return Pof<T>(L) + (L.ptype ? (size_t)L.ntypes * b * b : 0);
+}
 
 // Brackets one launch with a pair of events when that kernel kind/level is
 // being timed (see dgmg_profile_begin).
@@ -464,11 +469,11 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     {
     ProfScope ps(s, PK_PROLONG, l, st);
     if constexpr (R == 1) {
-        DISPATCH_B(s->b, k_prolong_add<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent, Pof<T>(L), xc,
+        DISPATCH_B(s->b, k_prolong_add<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent, PofT<T>(L, s->b), xc,
                                                                                      dc, x, L.ptype));
     } else {
         DISPATCH_B(s->b, k_prolong_add_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent,
-                                                                                         Pof<T>(L), xc, dc, x, L.ptype));
+                                                                                         PofT<T>(L, s->b), xc, dc, x, L.ptype));
     }
     }
     for (int k = 0; k < s->cheb_s; ++k) sweep();
@@ -1078,10 +1083,18 @@ static void upload_level(dgmg_solver* s, int l) {
         std::vector<int32_t> ptype;
         std::vector<double> ptab;
         if (distinct_blocks(s->Ph[l], b, A.n, kMaxPTypes, ptype, ptab)) {
-            // few distinct prolongation blocks (boxes nested in boxes): a
-            // table of them and a type per entity instead of one block each
+            // few distinct prolongation blocks (boxes nested in boxes): a table
+            // of them and a type per entity instead of one block each.  The
+            // table holds every block row-major (read by the restriction,
+            // lanes along a column), then every block transposed (read by
+            // the prolongation, lanes along a row).
             L.ptype = s->upload(ptype);
-            L.ntypes = (int32_t)(ptab.size() / ((size_t)b * b));
+            const size_t bb = (size_t)b * b;
+            L.ntypes = (int32_t)(ptab.size() / bb);
+            ptab.resize(2 * L.ntypes * bb);
+            for (int32_t q = 0; q < L.ntypes; ++q)
+                for (int i = 0; i < b; ++i)
+                    for (int j = 0; j < b; ++j) ptab[(L.ntypes + q) * bb + (size_t)j * b + i] = ptab[q * bb + (size_t)i * b + j];
             L.P64 = s->upload(ptab);
             if (s->prec == DGMG_PREC_MIXED) L.P32 = s->upload(convert<float>(ptab));
         } else {
