@@ -54,6 +54,62 @@ __device__ __forceinline__ int pk(int a, int b) {
     else return a == 0 ? b : (a == 1 ? 2 + b : 5);
 }
 
+// LDS arena of the matrix-free product.  Barriers split the product into
+// intervals (3D: 0 stage, 1 = 1x/2a, 2 = 1y/2, 3 = 1z/2b, 4 = 3z, 5 = 3y,
+// 6 = 3x; 2D: 0 stage, 1 = 1x/2a, 2 = 1y/2, 3 = 2b/3y, 4 = 3x).  An array
+// lives from the interval that writes it to the last that reads it, and
+// arrays whose lives meet must not overlap; otherwise they share words, so
+// the arena is as large as the largest live set (intervals 1-2):
+//   xs  cell values            xn  neighbour values    (stage - 1x/2a)
+//   A1  1x sums                fn  face-node data      (1x/2a - 1y/2)
+//   A2  3D 1y sums             ff  face fluxes         (1y/2 - 1z/2b)
+//   fq  cell terms                                     (3D 1z - 3z; 2D 1y - 3y)
+//   fT  tangential integrals                           (2b - 3x)
+//   A3  3D 3z sums             A4  3y sums             (3z - 3y; 3y - 3x)
+//   fr  a region the caller may use once the product returns (3x on)
+template <int B>
+struct MfLayout {
+    static constexpr int TC = kWG / B, D = dim_of<B>(), Q = mf_q<B>(), NF = 2 * D;
+    static constexpr int QN = D == 3 ? Q * Q : Q;
+    static constexpr int S_xs = TC * B, S_xn = TC * NF * B, S_A1 = TC * 2 * B;
+    static constexpr int S_fn = TC * NF * QN * 4, S_ff = TC * NF * QN * 2, S_fT = S_ff;
+    static constexpr int S_A2 = D == 3 ? TC * 3 * B : 0, S_A3 = S_A2, S_fq = TC * B * (D + 1);
+    static constexpr int S_A4 = TC * 2 * B, S_fr = kWG;
+    static constexpr int O_fn = 0, O_A1 = S_fn, O_xs = O_A1 + S_A1, O_xn = O_xs + S_xs;
+    static constexpr int O_ff = O_xs, O_A2 = O_ff + S_ff;
+    static constexpr int O_fT = 0, O_fq = D == 3 ? S_fT : O_ff + S_ff;
+    static constexpr int O_A3 = O_xs, O_A4 = S_fT, O_fr = O_xs;
+    static constexpr int E = D == 3 ? 6 : 4;          // the 3x interval
+    struct Slot {
+        int off, size, first, last;
+    };
+    static constexpr int NS = 11;
+    static constexpr Slot slot(int k) {
+        const Slot s[NS] = {{O_xs, S_xs, 0, 1},     {O_xn, S_xn, 0, 1},     {O_A1, S_A1, 1, 2},
+                            {O_fn, S_fn, 1, 2},     {O_A2, S_A2, 2, 3},     {O_ff, S_ff, 2, 3},
+                            {O_fq, S_fq, D == 3 ? 3 : 2, D == 3 ? 4 : 3},   {O_fT, S_fT, 3, E},
+                            {O_A3, S_A3, 4, 5},     {O_A4, S_A4, D == 3 ? 5 : 3, E},
+                            {O_fr, S_fr, E, E + 1}};
+        return s[k];
+    }
+    static constexpr int size() {
+        int n = 0;
+        for (int k = 0; k < NS; ++k) n = slot(k).off + slot(k).size > n ? slot(k).off + slot(k).size : n;
+        return n;
+    }
+    static constexpr bool disjoint() {
+        for (int a = 0; a < NS; ++a)
+            for (int b = a + 1; b < NS; ++b) {
+                const Slot x = slot(a), y = slot(b);
+                if (x.size == 0 || y.size == 0) continue;
+                const bool live = x.first <= y.last && y.first <= x.last;
+                const bool mem = x.off < y.off + y.size && y.off < x.off + x.size;
+                if (live && mem) return false;
+            }
+        return true;
+    }
+};
+
 // (A (va + vb)) at the thread's row; every thread of the workgroup must call
 // it (it synchronises), `active` marks threads that own a real row.  Every
 // pass below maps item i of a cell to thread i of that cell (B items).
@@ -68,33 +124,22 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     // the 1D tables and per-axis constants, read with lane-dependent indices
     constexpr int OI = 0, OD = Q * Q, OE = 2 * Q * Q, OW = OE + 2 * Q, OH = OW + Q, OA = OH + 3, OT = OA + 3;
     __shared__ T tb[OT + 3];
-    __shared__ T xs[TC][B];
     __shared__ T Dk[TC][NP];
     __shared__ T Dn[TC][NF][D];                       // row a of the neighbour's D
     __shared__ int hasn[TC][NF];                      // face has a neighbour
-    // four regions, each shared by arrays whose lifetimes do not overlap
-    // (intervals between barriers: 0 stage, 1 = 1x/2a, 2 = 1y/2, 3 = 1z/2b
-    // (2D: 2b/3y), 4 = 3z, 5 = 3y, 6 = 3x):
-    //   rA: neighbour values xn (0-1), face fluxes ff (2-3), 3z sums A3 (4-5)
-    //   rB: face-node data fn (1-2), tangential integrals fT (3-end)
-    //   rC: 1x sums A1 (1-2), 3D cell terms fq (3-4), 3y sums A4 (5-6; 2D 3-4)
-    //   rD: 3D 1y sums A2 (2-3); 2D cell terms fq (2-3)
-    constexpr int SXN = TC * NF * B, SFF = TC * NF * QN * 2;
-    constexpr int SFN = TC * NF * QN * 4, SFT = TC * NF * QN * 2;
-    constexpr int SC = TC * (D == 3 ? B * (D + 1) : 2 * B), SD = TC * (D == 3 ? 3 * B : B * (D + 1));
-    __shared__ T rA[SXN > SFF ? SXN : SFF];
-    __shared__ T rB[SFN > SFT ? SFN : SFT];
-    __shared__ T rC[SC];
-    __shared__ T rD[SD];
-    T(*xn)[NF][B] = reinterpret_cast<T(*)[NF][B]>(rA);
-    T(*ff)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(rA);
-    T(*A3)[3][B] = reinterpret_cast<T(*)[3][B]>(rA);
-    T(*fn)[NF][QN][4] = reinterpret_cast<T(*)[NF][QN][4]>(rB);
-    T(*fT)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(rB);
-    T(*A1)[2][B] = reinterpret_cast<T(*)[2][B]>(rC);
-    T(*A4)[2][B] = reinterpret_cast<T(*)[2][B]>(rC);
-    T(*A2)[3][B] = reinterpret_cast<T(*)[3][B]>(rD);
-    T(*fq)[B][D + 1] = reinterpret_cast<T(*)[B][D + 1]>(D == 3 ? rC : rD);
+    using Ly = MfLayout<B>;
+    static_assert(Ly::disjoint(), "arrays live in one interval overlap in the LDS arena");
+    __shared__ T ar[Ly::size()];
+    T(*xs)[B] = reinterpret_cast<T(*)[B]>(ar + Ly::O_xs);
+    T(*xn)[NF][B] = reinterpret_cast<T(*)[NF][B]>(ar + Ly::O_xn);
+    T(*ff)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(ar + Ly::O_ff);
+    T(*A3)[3][B] = reinterpret_cast<T(*)[3][B]>(ar + Ly::O_A3);
+    T(*fn)[NF][QN][4] = reinterpret_cast<T(*)[NF][QN][4]>(ar + Ly::O_fn);
+    T(*fT)[NF][QN][2] = reinterpret_cast<T(*)[NF][QN][2]>(ar + Ly::O_fT);
+    T(*A1)[2][B] = reinterpret_cast<T(*)[2][B]>(ar + Ly::O_A1);
+    T(*A4)[2][B] = reinterpret_cast<T(*)[2][B]>(ar + Ly::O_A4);
+    T(*A2)[3][B] = reinterpret_cast<T(*)[3][B]>(ar + Ly::O_A2);
+    T(*fq)[B][D + 1] = reinterpret_cast<T(*)[B][D + 1]>(ar + Ly::O_fq);
     const T* Ig = tb + OI;
     const T* Dg = tb + OD;
     const T* Ed = tb + OE;
@@ -376,9 +421,7 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     }
     // ---- phase 3x: test function I = (i0, i1, i2): sum_g0 (l_i0(g0) P + l_i0'(g0) X'),
     //      plus the face terms times the test function's normal factor.
-    // rA (last read before the previous barrier) is free from here on.
-    static_assert((SXN > SFF ? SXN : SFF) >= kWG, "free region smaller than a workgroup");
-    if (lds_free) *lds_free = rA;
+    if (lds_free) *lds_free = ar + Ly::O_fr;
     T y = 0;
     if (slot) {
 #pragma unroll
