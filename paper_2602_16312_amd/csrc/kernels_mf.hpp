@@ -165,28 +165,40 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     const bool slot = lc < TC;                        // thread maps to a (possibly padded) cell slot
     // item coordinates of this thread (x fastest)
     const int c0 = i % Q, c1 = (i / Q) % Q, c2 = D == 3 ? i / (Q * Q) : 0;
-    // ---- phase 0: stage values
+    // ---- phase 0: stage values.  Branch-free, so that all loads of a round
+    //      are in flight together: the neighbour indices, then every value
+    //      and conductivity (padded slots and missing neighbours read the
+    //      tile's first cell or their own, and the value is discarded).
     if (slot) {
-        T v = 0;
-        if (active) v = VB ? va[(size_t)cell * B + i] + vb[(size_t)cell * B + i] : va[(size_t)cell * B + i];
-        xs[lc][i] = v;
+        const int cs = active ? cell : 0;
+        int nb[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int a = f >> 1;
-            int nb = -1;
-            if (active) {
-                nb = (f & 1) ? L.up[(size_t)a * L.n + cell] : L.lo[(size_t)a * L.n + cell];
-                if ((f & 1) && nb == cell) nb = -1;
-            }
-            T w = 0;
-            if (nb >= 0) w = VB ? va[(size_t)nb * B + i] + vb[(size_t)nb * B + i] : va[(size_t)nb * B + i];
-            xn[lc][f][i] = w;
-            if (i == 0) hasn[lc][f] = nb >= 0;
-            if (i < D) {
-                Dn[lc][f][i] = nb >= 0 ? C.D[(size_t)nb * NP + pk<D>(a, i)] : T(0);
-            }
+            const int v = (f & 1) ? L.up[(size_t)a * L.n + cs] : L.lo[(size_t)a * L.n + cs];
+            nb[f] = (!active || ((f & 1) && v == cs)) ? -1 : v;
         }
-        if (i < NP) Dk[lc][i] = active ? C.D[(size_t)cell * NP + i] : T(0);
+        auto val = [&](int c) -> T {
+            return VB ? va[(size_t)c * B + i] + vb[(size_t)c * B + i] : va[(size_t)c * B + i];
+        };
+        const T xv = val(cs);
+        const T dk = C.D[(size_t)cs * NP + (i < NP ? i : 0)];
+        T wv[NF], dv[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const int src = nb[f] >= 0 ? nb[f] : cs;
+            wv[f] = val(src);
+            dv[f] = C.D[(size_t)src * NP + pk<D>(f >> 1, i < D ? i : 0)];
+        }
+        xs[lc][i] = active ? xv : T(0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const bool h = nb[f] >= 0;
+            xn[lc][f][i] = h ? wv[f] : T(0);
+            if (i == 0) hasn[lc][f] = h;
+            if (i < D) Dn[lc][f][i] = h ? dv[f] : T(0);
+        }
+        if (i < NP) Dk[lc][i] = active ? dk : T(0);
     }
     __syncthreads();
     // ---- phase 1x: contract x: item (g0, j1, j2) -> sum_j0 l_j0(g0) x, l_j0'(g0) x
