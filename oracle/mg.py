@@ -13,13 +13,18 @@ Readings (listed in the design notes):
   Chebyshev acceleration algorithm preconditioned by D^-1; "degree 3 with 3
   smoothing steps" = the degree-3 recurrence restarted 3 times, each restart
   from the true residual b - A x;
+* Jacobi matrix D: the diagonal of A_l (section 6, the paper's choice) or,
+  as an option, the cells' b x b diagonal blocks ("point-block" Jacobi);
+  the block variant's Lanczos runs on L^-1 A L^-T with D_K = L_K L_K^T per
+  cell, which is similar to D^-1 A and also has a unit diagonal;
 * coarsest level: exact dense Cholesky solve;
 * PCG stops when ||r_k||_2 <= tol * ||r_0||_2 with r_0 from the warm start;
   the iteration count is the number of A applies inside the loop.
 
 Pins (tests/test_oracle_mg.py): Galerkin symmetry and kernel, Lanczos bound
-and accuracy against dense eigenvalues, Chebyshev error propagator equals
-the closed-form Chebyshev polynomial, V-cycle symmetry and positivity,
+and accuracy against dense eigenvalues (generalised eigenvalues of (A, D)
+for the block variant), Chebyshev error propagator equals the closed-form
+Chebyshev polynomial (both Jacobi variants), V-cycle symmetry and positivity,
 special cases (no smoothing -> P A_c^-1 P^T; one level -> exact inverse), PCG
 against dense solves.
 """
@@ -63,16 +68,67 @@ def lanczos_theta_max(A, diag, m=20):
     return float(np.linalg.eigvalsh(T).max())
 
 
+def diagonal_blocks(A, b):
+    """The cells' b x b diagonal blocks of A (n_cells x b x b)."""
+    C = A.tocoo()
+    keep = (C.row // b) == (C.col // b)
+    r, c = C.row[keep], C.col[keep]
+    Dk = np.zeros((A.shape[0] // b, b, b))
+    np.add.at(Dk, (r // b, r % b, c % b), C.data[keep])
+    return Dk
+
+
+def cell_block_inverse(A, b):
+    """D^-1 for the cell-block Jacobi variant: the inverse of every diagonal
+    block, as a block-diagonal sparse matrix."""
+    return sp.block_diag(list(np.linalg.inv(diagonal_blocks(A, b))), format="csr")
+
+
+def lanczos_theta_max_block(A, b, m=20):
+    """Largest Ritz value of m Lanczos steps on L^-1 A L^-T, where
+    D_K = L_K L_K^T are the Cholesky factors of the cells' diagonal blocks;
+    the same start vector and stopping rule as the point variant."""
+    n = A.shape[0]
+    Linv = np.linalg.inv(np.linalg.cholesky(diagonal_blocks(A, b)))
+    nb = n // b
+
+    def op(v):
+        y = np.einsum("kji,kj->ki", Linv, v.reshape(nb, b)).ravel()       # L^-T v
+        return np.einsum("kij,kj->ki", Linv, (A @ y).reshape(nb, b)).ravel()  # L^-1 (A y)
+
+    v = lanczos_start(n)
+    v /= np.linalg.norm(v)
+    v_prev = np.zeros(n)
+    alphas, betas = [], []
+    beta = 0.0
+    for j in range(min(m, n)):
+        w = op(v) - beta * v_prev
+        a = w @ v
+        w = w - a * v
+        alphas.append(a)
+        beta = np.linalg.norm(w)
+        if beta < 1e-14 or j == min(m, n) - 1:
+            break
+        betas.append(beta)
+        v_prev, v = v, w / beta
+    T = np.diag(alphas) + np.diag(betas[:len(alphas) - 1], 1) \
+        + np.diag(betas[:len(alphas) - 1], -1)
+    return float(np.linalg.eigvalsh(T).max())
+
+
 def chebyshev(A, dinv, b, x, lam_lo, lam_hi, degree=3, sweeps=3):
     """Chebyshev-accelerated Jacobi: ``sweeps`` restarts of the degree-k
-    recurrence on the interval [lam_lo, lam_hi] of D^-1 A."""
+    recurrence on the interval [lam_lo, lam_hi] of D^-1 A.  ``dinv`` is the
+    inverse diagonal (a vector) or the block-diagonal D^-1 (a sparse
+    matrix)."""
+    jac = (lambda r: dinv @ r) if sp.issparse(dinv) else (lambda r: dinv * r)
     theta = 0.5 * (lam_hi + lam_lo)
     delta = 0.5 * (lam_hi - lam_lo)
     sigma1 = theta / delta
     x = x.copy()
     for _ in range(sweeps):
         r = b - A @ x
-        d = dinv * r / theta
+        d = jac(r) / theta
         rho = 1.0 / sigma1
         for i in range(degree):
             x = x + d
@@ -80,7 +136,7 @@ def chebyshev(A, dinv, b, x, lam_lo, lam_hi, degree=3, sweeps=3):
                 break
             r = r - A @ d
             rho_new = 1.0 / (2.0 * sigma1 - rho)
-            d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * r)
+            d = rho_new * rho * d + (2.0 * rho_new / delta) * jac(r)
             rho = rho_new
     return x
 
@@ -89,19 +145,28 @@ class VCycle:
     """One V-cycle of agglomerated multigrid as a linear operator."""
 
     def __init__(self, A0, P, degree=3, sweeps=3, lanczos_m=20,
-                 lam_override=None, safety=1.2, smooth_range=20.0):
+                 lam_override=None, safety=1.2, smooth_range=20.0,
+                 jacobi="point", b=None):
+        """jacobi: "point" (inverse diagonal) or "cell_block" (inverse b x b
+        diagonal blocks; b is the block size of every level)."""
+        if jacobi not in ("point", "cell_block"):
+            raise ValueError(jacobi)
         self.A = [A0.tocsr()]
         self.P = P
         for Pl in P:
             self.A.append(galerkin(self.A[-1], Pl))
         self.L = len(self.A)
-        self.dinv = [1.0 / Al.diagonal() for Al in self.A]
+        if jacobi == "point":
+            self.dinv = [1.0 / Al.diagonal() for Al in self.A]
+        else:
+            self.dinv = [cell_block_inverse(Al, b) for Al in self.A[:-1]] + [None]
         self.lam = []
         for l in range(self.L - 1):
             if lam_override is not None:
                 lo, hi = lam_override[l]
             else:
-                th = lanczos_theta_max(self.A[l], self.A[l].diagonal(), lanczos_m)
+                th = (lanczos_theta_max(self.A[l], self.A[l].diagonal(), lanczos_m) if jacobi == "point"
+                      else lanczos_theta_max_block(self.A[l], b, lanczos_m))
                 hi = safety * th
                 lo = hi / smooth_range
             self.lam.append((lo, hi))

@@ -9,7 +9,8 @@ from workloads import make_problem
 from oracle.assemble import system_matrix
 from oracle.basis import gl_nodes, multi_index
 from oracle.hierarchy import build_hierarchy, fine_nodes_level0, box_nodes
-from oracle.mg import (VCycle, chebyshev, galerkin, lanczos_theta_max, pcg)
+from oracle.mg import (VCycle, cell_block_inverse, chebyshev, diagonal_blocks, galerkin,
+                       lanczos_theta_max, lanczos_theta_max_block, pcg)
 
 
 @pytest.mark.parametrize("name,n,expect", [("c1", 32, [1024, 64]),
@@ -105,6 +106,74 @@ def test_chebyshev_error_propagator_is_chebyshev_polynomial():
         x0 = np.random.default_rng(k).standard_normal(A.shape[0])
         x = chebyshev(A0, 1.0 / d, np.zeros_like(x0), x0, lo, hi, k, s)
         assert np.allclose(x, E @ x0, atol=1e-12 * np.abs(x0).max())
+
+
+def _block_diag_dense(A, b):
+    """The cells' diagonal blocks of A by dense slicing (independent of the
+    oracle's sparse extraction)."""
+    M = A.toarray()
+    D = np.zeros_like(M)
+    for K in range(M.shape[0] // b):
+        s = slice(K * b, (K + 1) * b)
+        D[s, s] = M[s, s]
+    return D
+
+
+def test_cell_block_inverse_and_lanczos_against_generalised_eigenvalues():
+    """Cell-block Jacobi: D^-1 D = I per cell; the block Lanczos estimate
+    bounds the largest generalised eigenvalue of (A, D) (scipy's symmetric
+    generalised eigensolver) from below and recovers it with full Lanczos."""
+    pr, A0 = _small_A0("c1", 8)
+    b = 4
+    D = _block_diag_dense(A0, b)
+    Dk = diagonal_blocks(A0, b)
+    for K in range(Dk.shape[0]):
+        assert np.array_equal(Dk[K], D[K * b:(K + 1) * b, K * b:(K + 1) * b])
+    Dinv = cell_block_inverse(A0, b).toarray()
+    assert np.allclose(Dinv @ D, np.eye(D.shape[0]), atol=1e-12)
+    assert np.abs(Dinv - Dinv.T).max() <= 1e-12 * np.abs(Dinv).max()
+    lam = sla.eigh(A0.toarray(), D, eigvals_only=True)[-1]
+    th = lanczos_theta_max_block(A0, b, 20)
+    assert th <= lam * (1 + 1e-12) and th >= 0.99 * lam
+    pr2, A2 = _small_A0("c1", 2)
+    lam2 = sla.eigh(A2.toarray(), _block_diag_dense(A2, b), eigvals_only=True)[-1]
+    assert abs(lanczos_theta_max_block(A2, b, 50) - lam2) < 1e-10
+    # a block-diagonal operator is its own block Jacobi matrix: theta = 1
+    from scipy.sparse import csr_matrix
+    assert abs(lanczos_theta_max_block(csr_matrix(D), b, 20) - 1.0) < 1e-13
+
+
+def test_chebyshev_cell_block_error_propagator():
+    """With D the cells' diagonal blocks the smoother's error propagator is
+    p(D^-1 A)^s, from the generalised eigenvectors A Q = D Q diag(lam),
+    Q^T D Q = I, so that D^-1 A = Q diag(lam) Q^T D."""
+    pr, A0 = _small_A0("c1", 4)
+    b = 4
+    A = A0.toarray()
+    D = _block_diag_dense(A0, b)
+    lam, Q = sla.eigh(A, D)
+    lo, hi = 0.3 * lam[-1], 1.1 * lam[-1]
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    Dinv = cell_block_inverse(A0, b)
+    for k, s in ((3, 1), (3, 3), (2, 2), (1, 1)):
+        T = np.polynomial.chebyshev.Chebyshev.basis(k)
+        pk = T((theta - lam) / delta) / T(theta / delta)
+        E = (Q * (pk ** s)[None, :]) @ Q.T @ D
+        x0 = np.random.default_rng(k).standard_normal(A.shape[0])
+        x = chebyshev(A0, Dinv, np.zeros_like(x0), x0, lo, hi, k, s)
+        assert np.allclose(x, E @ x0, atol=1e-12 * np.abs(x0).max())
+
+
+def test_vcycle_cell_block_symmetric_positive():
+    pr = make_problem("c2", n=8)
+    h = build_hierarchy(pr)
+    A0, M, A, cM = system_matrix(pr)
+    mg = VCycle(A0, h["P"], jacobi="cell_block", b=9)
+    B = _dense_op(mg, A0.shape[0])
+    assert np.abs(B - B.T).max() <= 1e-13 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
+    with pytest.raises(ValueError):
+        VCycle(A0, h["P"], jacobi="block")
 
 
 def _dense_op(op, n):
