@@ -131,7 +131,7 @@ def _iapp(pr, t, nrhs):
 
 
 def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None, nrhs=1, mfma=False,
-            fine_layout="auto", setup="device"):
+            fine_layout="auto", setup="device", jacobi="point"):
     import numpy as np
     import torch
     from paper_2602_16312_amd import api, problem
@@ -139,7 +139,7 @@ def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None, nrhs=1, mfma=F
     t0 = time.perf_counter()
     # the solver's device memory comes from torch's caching allocator
     h, s = problem.build(pr, precision=precision, max_rhs=nrhs, mfma=mfma,
-                         fine_layout=fine_layout, setup=setup, allocator="torch")
+                         fine_layout=fine_layout, setup=setup, allocator="torch", jacobi=jacobi)
     setup_s = time.perf_counter() - t0
     log(f"{precision}: setup {setup_s:.1f} s")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
@@ -347,6 +347,9 @@ def main():
                     choices=["auto", "tile_ell", "axis_ell", "matrix_free"],
                     help="device storage of the fine operator (auto: each face block once; "
                          "matrix_free: sum factorisation, meshes of identical boxes only)")
+    ap.add_argument("--jacobi", default="point", choices=["point", "cell_block"],
+                    help="Jacobi matrix of the Chebyshev smoother: the diagonal (the paper's) or "
+                         "the cells' inverted diagonal blocks")
     ap.add_argument("--setup", default="device", choices=["host", "device"],
                     help="where the prolongations, Galerkin products and Lanczos estimates "
                          "are computed (outside the timed region either way)")
@@ -385,7 +388,8 @@ def main():
     mfma = nrhs > 1 and not args.no_mfma
     pr = make_problem("c4" if args.workload == "c4x8" else args.workload)
     res = run_gpu(pr, "mixed", args.steps, args.warmup, args.tol, profile_kind="cheb_step",
-                  nrhs=nrhs, mfma=mfma, fine_layout=args.fine_layout, setup=args.setup)
+                  nrhs=nrhs, mfma=mfma, fine_layout=args.fine_layout, setup=args.setup,
+                  jacobi=args.jacobi)
     ms = res["wall"] / args.steps * 1e3
     value = pr["N"] * nrhs / (res["wall"] / args.steps)
     info = res["info"]
@@ -408,6 +412,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "n_dofs": int(pr["N"]), "rhs": nrhs, "cells_per_level": info["n_cells"],
                    "precision": "mixed: FP32 V-cycle, FP64 PCG and coarse solve",
+                   "smoother": f"Chebyshev degree 3, 3 sweeps, {args.jacobi.replace('_', '-')} Jacobi",
                    "dt": pr["dt"], "tol": args.tol},
         "iters": _stats(res["its"]),
         "setup_s": res["setup_s"],
@@ -441,7 +446,7 @@ def main():
             "utilisation": fl / MFMA_F32_PEAK_TFLOPS}
     if not args.no_fp64:
         r64 = run_gpu(pr, "fp64", args.steps, args.warmup, args.tol, nrhs=nrhs,
-                      fine_layout=args.fine_layout, setup=args.setup)
+                      fine_layout=args.fine_layout, setup=args.setup, jacobi=args.jacobi)
         out["fp64"] = {"value": pr["N"] * nrhs / (r64["wall"] / args.steps),
                        "ms_per_step": r64["wall"] / args.steps * 1e3,
                        "iters": _stats(r64["its"])}
@@ -458,7 +463,7 @@ def main():
             err = {"steps": args.cpu_steps, "tol": args.tol}
             for prec in ("mixed",) + (() if args.no_fp64 else ("fp64",)):
                 rg = run_gpu(pr, prec, args.cpu_steps, 0, args.tol, fine_layout=args.fine_layout,
-                             setup=args.setup)
+                             setup=args.setup, jacobi=args.jacobi)
                 err[prec] = float(np.linalg.norm(rg["U"] - U_oracle) / np.linalg.norm(U_oracle))
             out["rel_err_vs_oracle"] = err
     print(json.dumps(out))

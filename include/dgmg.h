@@ -176,7 +176,12 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * Galerkin products A_{l+1} = P^T A_l P and the Lanczos estimates on the
  * GPU (the host supplies their integer structure; the blocks are copied
  * back for packing and inspection); 0 computes them on the host.  Both sum
- * in the same order per block. */
+ * in the same order per block.  jacobi selects the Jacobi matrix D of the
+ * Chebyshev smoother: POINT the diagonal of A_l (section 6); CELL_BLOCK the
+ * cells' b x b diagonal blocks, each inverted once at set-up (host Cholesky;
+ * DGMG_ENOTSPD if a block is not positive definite), with the Lanczos
+ * estimate taken on L^-1 A_l L^-T, D_K = L_K L_K^T (single-column solvers
+ * only: DGMG_EUNSUPPORTED with max_rhs > 1). */
 typedef struct {
     int32_t cheb_degree;
     int32_t cheb_sweeps;
@@ -192,7 +197,10 @@ typedef struct {
     int32_t fine_layout;
     int32_t setup_on_device;
     const dgmg_allocator* allocator;  /* NULL: hipMalloc / hipFree; copied at set-up */
+    int32_t jacobi;                   /* DGMG_JACOBI_* */
 } dgmg_mg_opts;
+
+enum { DGMG_JACOBI_POINT = 0, DGMG_JACOBI_CELL_BLOCK = 1 };
 
 enum { DGMG_LAYOUT_AUTO = 0, DGMG_LAYOUT_TILE_ELL = 1, DGMG_LAYOUT_AXIS_ELL = 2,
        DGMG_LAYOUT_MATRIX_FREE = 3 };

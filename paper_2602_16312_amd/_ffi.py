@@ -63,7 +63,8 @@ class MGOpts(C.Structure):
                 ("precision", C.c_int32), ("device_setup", C.c_int32),
                 ("adjoint", C.c_int32), ("max_rhs", C.c_int32),
                 ("mfma", C.c_int32), ("fine_layout", C.c_int32),
-                ("setup_on_device", C.c_int32), ("allocator", C.POINTER(Allocator))]
+                ("setup_on_device", C.c_int32), ("allocator", C.POINTER(Allocator)),
+                ("jacobi", C.c_int32)]
 
 
 class SolverInfo(C.Structure):

@@ -14,6 +14,7 @@ MODELS = {"fhn": 0, "ap": 1, "bo": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 TOL_MODES = {"rel_r0": 0, "rel_b": 1, "abs": 2}
 LAYOUTS = {"auto": 0, "tile_ell": 1, "axis_ell": 2, "matrix_free": 3}
+JACOBI = {"point": 0, "cell_block": 1}
 
 
 def _dptr(a):
@@ -198,14 +199,18 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
                  bdf=2, cell_scale=None, precision="fp64", cheb_degree=3,
                  cheb_sweeps=3, lanczos_steps=20, lam_safety=1.2,
                  smooth_range=20.0, lam_override=None, device_setup=True, adjoint=False,
-                 max_rhs=1, mfma=False, fine_layout="auto", setup="host", allocator=None):
+                 max_rhs=1, mfma=False, fine_layout="auto", setup="host", allocator=None,
+                 jacobi="point"):
     """dgmg_setup_levels: assembly, Galerkin hierarchy, smoother, coarse factor.
     setup = "device" computes the assembly, prolongations, Galerkin products and
     Lanczos estimates on the GPU, "host" on the CPU.  allocator: None (the
     library uses hipMalloc), "torch" or a TorchAllocator (device memory from
-    torch's caching allocator)."""
+    torch's caching allocator).  jacobi: "point" (the diagonal) or
+    "cell_block" (the cells' inverted diagonal blocks) in the smoother."""
     if setup not in ("host", "device"):
         raise ValueError("setup must be 'host' or 'device'")
+    if jacobi not in JACOBI:
+        raise ValueError("jacobi must be 'point' or 'cell_block'")
     d = F.Disc(p, 0 if penalty[0] == "paper" else 1,
                float(penalty[1]) if len(penalty) > 1 else 0.0)
     D_cell, Dp = _dptr(D_cell)
@@ -230,7 +235,7 @@ def setup_levels(hier, p, D_cell, chi, Cm, dt, model, params, penalty=("paper",)
     mg = F.MGOpts(cheb_degree, cheb_sweeps, lanczos_steps, lam_safety, smooth_range,
                   lo, PRECISIONS[precision], 1 if device_setup else 0, 1 if adjoint else 0,
                   int(max_rhs), 1 if mfma else 0, LAYOUTS[fine_layout],
-                  1 if setup == "device" else 0, ap)
+                  1 if setup == "device" else 0, ap, JACOBI[jacobi])
     s = C.c_void_p()
     F.check(F.lib().dgmg_setup_levels(hier.handle, C.byref(d), C.byref(ph), C.byref(mg),
                                       C.byref(s)))

@@ -111,7 +111,8 @@ void host_apply(const BlockOp& A, const double* x, double* y);
 // per-cell face lists: faces of cell K are code[ptr[K]..ptr[K+1]),
 // code = face << 1 | (K is the minus side)
 void cell_face_lists(const BlockOp& A, std::vector<int64_t>& ptr, std::vector<int64_t>& code);
-double lanczos_theta_max(const BlockOp& A, int steps);
+double lanczos_theta_max(const BlockOp& A, int steps, const std::vector<double>* chol = nullptr);
+void cell_block_factors(const BlockOp& A, std::vector<double>& Lc, std::vector<double>& Dinv);
 // Largest eigenvalue of the symmetric tridiagonal matrix (a, off-diagonal bt).
 double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& bt);
 // Lanczos start vector: v_i = frac((i+1) * golden ratio conjugate) - 1/2, normalised

@@ -336,6 +336,31 @@ __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __re
     }
 }
 
+// Cell-block Jacobi (section 6 smoother with the cells' diagonal blocks as
+// D): y = alpha y + beta D_K^-1 v_K at row (K, i), D_K^-1 symmetric and
+// row-major per cell, so the lanes of a cell read consecutive words of
+// column j; alpha = 0 does not read y.  With x given also x += y (the last
+// Chebyshev step of a sweep).
+template <typename T, int B>
+__global__ __launch_bounds__(kWG) void k_block_jacobi(int32_t n, const T* __restrict__ Dinv,
+                                                      const T* __restrict__ v, T* __restrict__ y, T alpha,
+                                                      T beta, T* __restrict__ x) {
+    constexpr int TC = Tile<T, B>::TC;
+    const int lc = threadIdx.x / B;
+    const int cell = blockIdx.x * TC + lc;
+    if (lc >= TC || cell >= n) return;
+    const int i = threadIdx.x - lc * B;
+    const size_t t = (size_t)cell * B + i;
+    const T* Dc = Dinv + (size_t)cell * B * B + i;
+    const T* vc = v + (size_t)cell * B;
+    T z = 0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) z += Dc[(size_t)j * B] * vc[j];
+    const T yn = alpha == T(0) ? beta * z : alpha * y[t] + beta * z;
+    y[t] = yn;
+    if (x) x[t] += yn;
+}
+
 // First sweep from x = 0: r = b, d = dinv * b * c1.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cheb_init0(int64_t N, const T* __restrict__ b,

@@ -284,26 +284,109 @@ void lanczos_start(int64_t n, std::vector<double>& v) {
     for (auto& x : v) x /= nrm;
 }
 
-// m Lanczos steps on D^-1/2 A D^-1/2 without reorthogonalisation, start
-// vector frac((i+1) * golden ratio conjugate) - 1/2, early stop when the next
-// beta falls below 1e-14; returns the largest Ritz value.
-double lanczos_theta_max(const BlockOp& A, int steps) {
+// Cell-block Jacobi: the Cholesky factor L_K (lower, row-major) of every
+// diagonal block D_K and the inverse D_K^-1 = L_K^-T L_K^-1 (computed in its
+// lower triangle and mirrored, so exactly symmetric).  A pivot <= 0 fails
+// with DGMG_ENOTSPD.
+void cell_block_factors(const BlockOp& A, std::vector<double>& Lc, std::vector<double>& Dinv) {
     const int b = A.b;
+    const size_t bb = (size_t)b * b;
+    Lc.assign(A.n * bb, 0.0);
+    Dinv.assign(A.n * bb, 0.0);
+    bool bad = false;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t K = 0; K < A.n; ++K) {
+        const double* D = &A.diag[K * bb];
+        double* L = &Lc[K * bb];
+        for (int j = 0; j < b && !bad; ++j) {
+            double d = D[j * b + j];
+            for (int k = 0; k < j; ++k) d -= L[j * b + k] * L[j * b + k];
+            if (!(d > 0.0)) {
+                bad = true;
+                break;
+            }
+            L[j * b + j] = std::sqrt(d);
+            for (int i = j + 1; i < b; ++i) {
+                double v = D[i * b + j];
+                for (int k = 0; k < j; ++k) v -= L[i * b + k] * L[j * b + k];
+                L[i * b + j] = v / L[j * b + j];
+            }
+        }
+        if (bad) continue;
+        // columns of L^-1 by forward substitution, then D^-1 = L^-T L^-1
+        std::vector<double> Li(bb, 0.0);
+        for (int c = 0; c < b; ++c)
+            for (int i = c; i < b; ++i) {
+                double v = i == c ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) v -= L[i * b + k] * Li[k * b + c];
+                Li[i * b + c] = v / L[i * b + i];
+            }
+        double* Z = &Dinv[K * bb];
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double v = 0.0;
+                for (int k = i; k < b; ++k) v += Li[k * b + i] * Li[k * b + j];
+                Z[i * b + j] = v;
+                Z[j * b + i] = v;
+            }
+    }
+    if (bad) fail(DGMG_ENOTSPD, "a diagonal cell block is not positive definite");
+}
+
+// m Lanczos steps on S A S^T without reorthogonalisation, S = D^-1/2 (point
+// Jacobi) or S = L^-1 with D_K = L_K L_K^T per cell (cell-block Jacobi, chol
+// given); start vector frac((i+1) * golden ratio conjugate) - 1/2, early stop
+// when the next beta falls below 1e-14; returns the largest Ritz value.
+double lanczos_theta_max(const BlockOp& A, int steps, const std::vector<double>* chol) {
+    const int b = A.b;
+    const size_t bb = (size_t)b * b;
     const int64_t n = A.n * b;
     std::vector<double> s(n), v(n), vp(n, 0.0), w(n), tmp(n);
     for (int64_t K = 0; K < A.n; ++K)
         for (int i = 0; i < b; ++i) s[K * b + i] = 1.0 / std::sqrt(A.diag[((size_t)K * b + i) * b + i]);
+    // y = S^T x and y = S x (in place), per cell
+    auto scale_t = [&](const double* x, double* y) {
+        if (!chol) {
+            for (int64_t i = 0; i < n; ++i) y[i] = s[i] * x[i];
+            return;
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t K = 0; K < A.n; ++K) {     // back substitution with L_K^T
+            const double* L = &(*chol)[K * bb];
+            for (int i = b - 1; i >= 0; --i) {
+                double t = x[K * b + i];
+                for (int k = i + 1; k < b; ++k) t -= L[k * b + i] * y[K * b + k];
+                y[K * b + i] = t / L[i * b + i];
+            }
+        }
+    };
+    auto scale = [&](double* x) {
+        if (!chol) {
+            for (int64_t i = 0; i < n; ++i) x[i] *= s[i];
+            return;
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t K = 0; K < A.n; ++K) {     // forward substitution with L_K
+            const double* L = &(*chol)[K * bb];
+            for (int i = 0; i < b; ++i) {
+                double t = x[K * b + i];
+                for (int k = 0; k < i; ++k) t -= L[i * b + k] * x[K * b + k];
+                x[K * b + i] = t / L[i * b + i];
+            }
+        }
+    };
     lanczos_start(n, v);
     std::vector<double> al, be;
     double beta = 0.0;
     const int64_t mmax = std::min<int64_t>(steps, n);
     const CellFaces C = cell_faces(A);
     for (int64_t j = 0; j < mmax; ++j) {
-        for (int64_t i = 0; i < n; ++i) tmp[i] = s[i] * v[i];
+        scale_t(v.data(), tmp.data());
         apply_with(A, C, tmp.data(), w.data());
+        scale(w.data());
         double a = 0.0;
         for (int64_t i = 0; i < n; ++i) {
-            w[i] = s[i] * w[i] - beta * vp[i];
+            w[i] = w[i] - beta * vp[i];
             a += w[i] * v[i];
         }
         double bn = 0.0;

@@ -113,6 +113,8 @@ struct DevLevel {
     int32_t ntypes = 0;                                    // distinct blocks in that table
     double *vals64 = nullptr, *dinv64 = nullptr, *P64 = nullptr;
     float *vals32 = nullptr, *dinv32 = nullptr, *P32 = nullptr;
+    double* bj64 = nullptr;                                // cell-block Jacobi: D_K^-1 (symmetric)
+    float* bj32 = nullptr;
     void *vb = nullptr, *vx = nullptr, *vx2 = nullptr, *vr = nullptr, *vd = nullptr, *vd2 = nullptr;
     double lam_lo = 0, lam_hi = 0;
 };
@@ -128,6 +130,8 @@ struct dgmg_solver {
     int cheb_k = 3, cheb_s = 3;
     int max_rhs = 1, mfma = 0;
     int fine_layout = 0;              // DGMG_LAYOUT_*
+    int jacobi = 0;                   // DGMG_JACOBI_*
+    std::vector<std::vector<double>> bjinv;   // cell-block Jacobi: D_K^-1 per smoothed level
     // matrix-free fine level on identical boxes: extents, packed scaled D,
     // mass coefficient and penalty factors per axis
     double mf_h[3] = {0, 0, 0};
@@ -242,6 +246,12 @@ template <>
 const double* Pof<double>(const DevLevel& L) { return L.P64; }
 template <>
 const float* Pof<float>(const DevLevel& L) { return L.P32; }
+template <typename T>
+static const T* BJof(const DevLevel& L);
+template <>
+const double* BJof<double>(const DevLevel& L) { return L.bj64; }
+template <>
+const float* BJof<float>(const DevLevel& L) { return L.bj32; }
 // the prolongation's blocks: with a type table, its transposed half
 template <typename T>
 static const T* PofT(const DevLevel& L, int b) {
@@ -403,20 +413,34 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     T *x = (T*)L.vx, *x2 = (T*)L.vx2, *r = (T*)L.vr, *d = (T*)L.vd, *d2 = (T*)L.vd2;
     bool xzero = true, pending = false;
     const T* dinv = largs<T>(L).dinv;
+    // cell-block Jacobi (single column): the fused kernels run with their
+    // Jacobi term off (zero coefficient, no final correction) and
+    // k_block_jacobi then adds beta D^-1 v per cell (and x += d on a sweep's
+    // last step)
+    const bool bj = R == 1 && s->jacobi == DGMG_JACOBI_CELL_BLOCK;
+    auto bjac = [&](const T* v, T* y, T alpha, T beta, T* xo) {
+        if constexpr (R == 1)
+            DISPATCH_B(s->b, k_block_jacobi<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, BJof<T>(L), v, y,
+                                                                                          alpha, beta, xo));
+    };
+    const T cj = bj ? T(0) : c1;
     auto sweep = [&]() {
         if (xzero && !pending) {
             if constexpr (R == 1)
-                k_cheb_init0<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, b, dinv, r, d, c1);
+                k_cheb_init0<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, b, dinv, r, d, cj);
             else
                 k_cheb_init0_m<T, R><<<blocks_for(NR), kWG, 0, st>>>(NR, b, dinv, r, d, c1);
+            if (bj) bjac(r, d, T(0), c1, nullptr);
         } else if (pending) {
             // r = b - A(x + d), materialise x + d into x2
-            launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, d2, c1, x2, nullptr, st);
+            launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, d2, cj, x2, nullptr, st);
+            if (bj) bjac(r, d2, T(0), c1, nullptr);
             std::swap(x, x2);
             std::swap(d, d2);
             xzero = false;
         } else {
-            launch_residual<T, R>(s, L, x, (const T*)nullptr, b, r, d, c1, (T*)nullptr, nullptr, st);
+            launch_residual<T, R>(s, L, x, (const T*)nullptr, b, r, d, cj, (T*)nullptr, nullptr, st);
+            if (bj) bjac(r, d, T(0), c1, nullptr);
         }
         double rho = 1.0 / sigma1;
         for (int i = 1; i < s->cheb_k; ++i) {
@@ -424,8 +448,10 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
             // the last step of the sweep also applies the sweep's final
             // correction x += d (it needs only the row's own new d)
             const int last = i == s->cheb_k - 1;
-            launch_step<T, R>(s, L, d, x, r, d2, (T)(rn * rho), (T)(2.0 * rn / delta), xzero ? 1 : 0, last,
+            const T cr = (T)(2.0 * rn / delta);
+            launch_step<T, R>(s, L, d, x, r, d2, (T)(rn * rho), bj ? T(0) : cr, xzero ? 1 : 0, bj ? 0 : last,
                               st);
+            if (bj) bjac(r, d2, T(1), cr, last ? x : nullptr);
             xzero = false;
             if (!last) std::swap(d, d2);
             rho = rn;
@@ -1077,6 +1103,11 @@ static void upload_level(dgmg_solver* s, int l) {
             L.dinv32 = s->upload(convert<float>(dinv));
         }
     }
+    if (!last && s->jacobi == DGMG_JACOBI_CELL_BLOCK) {
+        L.bj64 = s->upload(s->bjinv[l]);
+        if (s->prec == DGMG_PREC_MIXED) L.bj32 = s->upload(convert<float>(s->bjinv[l]));
+        std::vector<double>().swap(s->bjinv[l]);
+    }
     if (!last) {
         std::vector<int32_t> par(s->parents[l].begin(), s->parents[l].end());
         L.parent = s->upload(par);
@@ -1379,6 +1410,10 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     if (mg->fine_layout == DGMG_LAYOUT_MATRIX_FREE && mg->max_rhs > 1)
         fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
     s->fine_layout = mg->fine_layout;
+    if (mg->jacobi != DGMG_JACOBI_POINT && mg->jacobi != DGMG_JACOBI_CELL_BLOCK) fail(DGMG_EINVAL, "unknown jacobi");
+    if (mg->jacobi == DGMG_JACOBI_CELL_BLOCK && s->max_rhs > 1)
+        fail(DGMG_EUNSUPPORTED, "cell-block Jacobi is implemented for single-column solvers");
+    s->jacobi = mg->jacobi;
     s->N = h->n_cells * re.b;
     s->S = ph->model == DGMG_MODEL_BO ? 3 : 1;
     s->parents = h->parent;
@@ -1465,13 +1500,20 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     double t4 = now_s();
     s->info.t_galerkin = t4 - t3;
     s->lv.resize(s->L);
+    if (s->jacobi == DGMG_JACOBI_CELL_BLOCK) s->bjinv.assign(s->L, {});
     for (int l = 0; l + 1 < s->L; ++l) {
+        std::vector<double> chol;
+        if (s->jacobi == DGMG_JACOBI_CELL_BLOCK) cell_block_factors(s->ops[l], chol, s->bjinv[l]);
         if (mg->lam_override) {
             s->lv[l].lam_lo = mg->lam_override[2 * l];
             s->lv[l].lam_hi = mg->lam_override[2 * l + 1];
         } else {
-            const double th = ds ? ds->lanczos_theta_max(l, s->ops[l], mg->lanczos_steps)
-                                 : lanczos_theta_max(s->ops[l], mg->lanczos_steps);
+            // the block variant's estimate runs on the host (its scaling is a
+            // per-cell triangular solve)
+            const double th = s->jacobi == DGMG_JACOBI_CELL_BLOCK
+                                  ? lanczos_theta_max(s->ops[l], mg->lanczos_steps, &chol)
+                                  : ds ? ds->lanczos_theta_max(l, s->ops[l], mg->lanczos_steps)
+                                       : lanczos_theta_max(s->ops[l], mg->lanczos_steps);
             s->lv[l].lam_hi = mg->lam_safety * th;
             s->lv[l].lam_lo = s->lv[l].lam_hi / mg->smooth_range;
         }
