@@ -74,6 +74,7 @@ struct LevelArgs {
     const int32_t* __restrict__ up;        // axis-ELL: [d][n] upper neighbour (itself if none)
     const int32_t* __restrict__ lo;        // axis-ELL: [d][n] lower neighbour (-1 if none)
     MfConst<T> mf;                         // matrix-free fine level (layout 2)
+    const int32_t* __restrict__ cmap;      // tile-ELL: tile position -> cell (null: identity)
 };
 
 // spatial dimension of a block size (Q1..Q3 in 2D: 4, 9, 16; in 3D: 8, 27, 64)
@@ -241,19 +242,24 @@ __device__ __forceinline__ void wg_sum_store(double v, double* partial) {
 }
 
 // ---------------------------------------------------------------- apply
-#define DGMG_TILE_THREAD(T, B)                                   \
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);            \
-    const int lc = threadIdx.x / B;                              \
-    const int cell = tile * Tile<T, B>::TC + lc;                 \
-    const bool active = lc < Tile<T, B>::TC && cell < L.n;       \
+// Thread (tile, lc, i) owns row i of cell tile * TC + lc, or, when MAPPED
+// (a tile-ELL level whose tiles group cells of similar neighbour count), of
+// cell cmap[tile * TC + lc]; vectors stay in cell order either way.
+#define DGMG_TILE_THREAD_M(T, B, MAPPED)                                          \
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);                           \
+    const int lc = threadIdx.x / B;                                             \
+    const int pos = tile * Tile<T, B>::TC + lc;                                 \
+    const bool active = lc < Tile<T, B>::TC && pos < L.n;                       \
+    const int cell = ((MAPPED) && L.cmap && active) ? L.cmap[pos] : pos;        \
     const int t = cell * B + (threadIdx.x - lc * B);
+#define DGMG_TILE_THREAD(T, B) DGMG_TILE_THREAD_M(T, B, false)
 
 // y = A va; optional partial of dot(w, y).
 template <typename T, int B, int LY>
 __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restrict__ va,
                                                T* __restrict__ y,
                                                const T* __restrict__ w, double* __restrict__ partial) {
-    DGMG_TILE_THREAD(T, B)
+    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
     double contrib = 0.0;
     const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, va, nullptr);
     if (active) {
@@ -274,7 +280,7 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
                                                   T* __restrict__ xout, double* __restrict__ partial,
                                                   const T* __restrict__ P, T* __restrict__ rp,
                                                   const int32_t* __restrict__ ptype) {
-    DGMG_TILE_THREAD(T, B)
+    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
     double contrib = 0.0;
     T rr = 0;
     T* lds_free = nullptr;
@@ -295,10 +301,12 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
         __syncthreads();
         if (active) {
             // thread (lc, j): column j of P_cell, contiguous in i (tile
-            // layout) or strided by B (row-major block of the cell's type)
-            constexpr int TR = Tile<T, B>::TR;
+            // layout, at the cell's own tile position) or strided by B
+            // (row-major block of the cell's type)
+            constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
             const int j = threadIdx.x - lc * B;
-            const T* Pc = ptype ? P + (size_t)ptype[cell] * B * B + j : P + ((size_t)tile * B + j) * TR + lc * B;
+            const int ht = cell / TC, hl = cell - ht * TC;
+            const T* Pc = ptype ? P + (size_t)ptype[cell] * B * B + j : P + ((size_t)ht * B + j) * TR + hl * B;
             const int ks = ptype ? B : 1;
             const T* rc = rs + lc * B;
             T s = 0;
@@ -320,7 +328,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __re
                                                    T* __restrict__ x, T* __restrict__ r,
                                                    T* __restrict__ dn, T cd, T cr, int assign,
                                                    int last) {
-    DGMG_TILE_THREAD(T, B)
+    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
     const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, d, nullptr);
     if (!active) return;
     const T dt = d[t];

@@ -110,6 +110,7 @@ struct DevLevel {
     int32_t *child_ptr = nullptr, *child_list = nullptr;  // children on level l-1
     int32_t* parent = nullptr;                             // parent on level l+1
     int32_t* ptype = nullptr;                              // P_e = table[ptype[e]] when set
+    int32_t* cmap = nullptr;                               // tile-ELL: tile position -> cell
     int32_t ntypes = 0;                                    // distinct blocks in that table
     double *vals64 = nullptr, *dinv64 = nullptr, *P64 = nullptr;
     float *vals32 = nullptr, *dinv32 = nullptr, *P32 = nullptr;
@@ -233,11 +234,11 @@ template <typename T>
 static LevelArgs<T> largs(const DevLevel& L);
 template <>
 LevelArgs<double> largs<double>(const DevLevel& L) {
-    return {L.vals64, L.slot_ptr, L.snb, L.dinv64, L.n, L.up, L.lo, L.mf64};
+    return {L.vals64, L.slot_ptr, L.snb, L.dinv64, L.n, L.up, L.lo, L.mf64, L.cmap};
 }
 template <>
 LevelArgs<float> largs<float>(const DevLevel& L) {
-    return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n, L.up, L.lo, L.mf32};
+    return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n, L.up, L.lo, L.mf32, L.cmap};
 }
 static int level_ly(const DevLevel& L) { return L.mf ? LY_MF : (L.ax ? LY_AXIS : LY_TILE); }
 template <typename T>
@@ -733,19 +734,48 @@ static void build_nbr(const BlockOp& A, std::vector<int32_t>& ptr, std::vector<i
 struct TileEll {
     std::vector<int32_t> slot_ptr, snb;
     std::vector<double> vals;
+    std::vector<int32_t> cmap;   // tile position -> cell; empty: identity
 };
-static TileEll build_tile_ell(const BlockOp& A) {
+// Tile-ELL: each tile is padded to its largest neighbour count.  With
+// window > 0 the cells of every run of `window` tiles are assigned to tile
+// positions by descending neighbour count (stable), so that a tile holds
+// cells of similar count while staying among nearby cells; kept only when
+// it saves at least 3% of the slots.
+static TileEll build_tile_ell(const BlockOp& A, int window = 0) {
     const int b = A.b, TC = kWG / b, TR = TC * b;
     const int64_t n = A.n, ntiles = (n + TC - 1) / TC;
     std::vector<int32_t> ptr, cell, code;
     build_nbr(A, ptr, cell, code);
+    auto deg = [&](int64_t c) { return ptr[c + 1] - ptr[c]; };
+    std::vector<int32_t> order(n);
+    for (int64_t c = 0; c < n; ++c) order[c] = (int32_t)c;
+    auto count_slots = [&]() {
+        int64_t tot = 0;
+        for (int64_t t = 0; t < ntiles; ++t) {
+            int mx = 0;
+            for (int lc = 0; lc < TC && t * TC + lc < n; ++lc) mx = std::max(mx, deg(order[t * TC + lc]));
+            tot += 1 + mx;
+        }
+        return tot;
+    };
     TileEll E;
+    if (window > 0) {
+        const int64_t plain = count_slots();
+        const int64_t w = (int64_t)window * TC;
+        for (int64_t w0 = 0; w0 < n; w0 += w)
+            std::stable_sort(order.begin() + w0, order.begin() + std::min(n, w0 + w),
+                             [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
+        if (count_slots() * 100 <= plain * 97)
+            E.cmap = order;
+        else
+            for (int64_t c = 0; c < n; ++c) order[c] = (int32_t)c;
+    }
     E.slot_ptr.assign(ntiles + 1, 0);
     for (int64_t t = 0; t < ntiles; ++t) {
         int mx = 0;
         for (int lc = 0; lc < TC; ++lc) {
-            const int64_t c = t * TC + lc;
-            if (c < n) mx = std::max(mx, ptr[c + 1] - ptr[c]);
+            const int64_t pos = t * TC + lc;
+            if (pos < n) mx = std::max(mx, deg(order[pos]));
         }
         E.slot_ptr[t + 1] = E.slot_ptr[t] + 1 + mx;
     }
@@ -756,8 +786,8 @@ static TileEll build_tile_ell(const BlockOp& A) {
     for (int64_t t = 0; t < ntiles; ++t) {
         const int64_t s0 = E.slot_ptr[t], ns = E.slot_ptr[t + 1] - s0;
         for (int lc = 0; lc < TC; ++lc) {
-            const int64_t c = t * TC + lc;
-            if (c >= n) continue;
+            if (t * TC + lc >= n) continue;
+            const int64_t c = order[t * TC + lc];
             for (int64_t sl = 0; sl < ns; ++sl) E.snb[(size_t)(s0 + sl) * TC + lc] = (int32_t)c;
             auto put = [&](int64_t gs, const double* blk, bool transpose) {
                 for (int i = 0; i < b; ++i)
@@ -1093,7 +1123,10 @@ static void upload_level(dgmg_solver* s, int l) {
             L.dinv32 = s->upload(convert<float>(dinv));
         }
     } else if (!last || s->L == 1) {
-        TileEll E = build_tile_ell(A);
+        // single-column solvers group cells of similar neighbour count
+        // into tiles (the multi-column kernels keep the identity mapping)
+        TileEll E = build_tile_ell(A, s->max_rhs == 1 ? 16 : 0);
+        if (!E.cmap.empty()) L.cmap = s->upload(E.cmap);
         L.slot_ptr = s->upload(E.slot_ptr);
         L.snb = s->upload(E.snb);
         L.vals64 = s->upload(E.vals);
