@@ -67,6 +67,52 @@ def cheb_step_bytes(info, prec_bytes, nrhs=1):
     return blocks + adjacency + vectors
 
 
+def level0_working_set(info, prec_bytes, nrhs=1):
+    """Bytes of the level-0 data the V-cycle's smoother touches: the stored
+    operator (or the matrix-free coefficients) and adjacency, the inverse
+    diagonal and the level's six work vectors (right-hand side, two x, r,
+    two d).  The same count as one step's algorithmic bytes, whose seven
+    vector streams are these seven vectors."""
+    b = info["b"]
+    n, nf = info["n_cells"][0], info["n_faces"][0]
+    N = n * b
+    if info.get("fine_layout") == "matrix_free":
+        d = info["dim"]
+        ops = n * (d * (d + 1) // 2) * prec_bytes + 2 * d * 4 * n
+    else:
+        ops = (n + nf) * b * b * prec_bytes + 4 * (n + 1) + 2 * 2 * 4 * nf
+    return ops + (6 * nrhs + 1) * prec_bytes * N
+
+
+INFINITY_CACHE_BYTES = 256 * 1024 * 1024
+
+
+def host_description():
+    """Logical CPUs available to this process, physical cores and model name
+    of the host (from the scheduler affinity and /proc/cpuinfo)."""
+    desc = {"nproc": len(os.sched_getaffinity(0))}
+    try:
+        txt = open("/proc/cpuinfo").read()
+    except OSError:
+        return desc
+    cores, model = set(), None
+    phys = core = None
+    for line in txt.splitlines():
+        if ":" not in line:
+            continue
+        k, v = [x.strip() for x in line.split(":", 1)]
+        if k == "model name" and model is None:
+            model = v
+        elif k == "physical id":
+            phys = v
+        elif k == "core id":
+            core = v
+            cores.add((phys, core))
+    desc["physical_cores"] = len(cores) if cores else None
+    desc["model"] = model
+    return desc
+
+
 def cheb_step_flops(info, nrhs):
     """Multiply-adds of the block products of one Chebyshev step, as flops:
     each stored block is used twice for a face (both orientations)."""
@@ -321,11 +367,96 @@ def cpu_baseline(pr, tol, nsteps):
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    # cores: the threads the oracle kept busy on average (process CPU time
+    # over wall time; scipy's sparse products run on one thread, numpy's
+    # dense kernels on the BLAS pool)
     return dict(value=pr["N"] / (wall / nsteps), unit="DoFs/s", cores=max(1, round(cpu / wall)),
-                kind="oracle",
+                kind="oracle", cpu_seconds=round(cpu, 3), wall_seconds=round(wall, 3),
+                host=host_description(),
                 sample=f"first {nsteps} time steps of the same workload (scipy CSR PCG + "
                        f"V-cycle, FP64, tol {tol}); oracle setup excluded; "
                        f"its={[s['its'] for s in stats]}"), state[0]
+
+
+def measure(workload, pr, args, steps, warmup, nrhs):
+    """Mixed-precision time stepping of one workload (throughput, iteration
+    statistics, roofline of the level-0 Chebyshev step from HIP events on the
+    solver's stream) and, unless disabled, the FP64 solver beside it."""
+    import numpy as np
+    mfma = nrhs > 1 and not args.no_mfma
+    res = run_gpu(pr, "mixed", steps, warmup, args.tol, profile_kind="cheb_step",
+                  nrhs=nrhs, mfma=mfma, fine_layout=args.fine_layout, setup=args.setup,
+                  jacobi=args.jacobi)
+    info = res["info"]
+    prof = res["prof"]
+    in_run_s = prof["in_run_ms"] / 1e3
+    b2b_s = prof["back_to_back_ms"] / 1e3
+    alg = cheb_step_bytes(info, 4, nrhs)
+    ws = level0_working_set(info, 4, nrhs)
+    b_ = info["b"]
+    achieved = alg / in_run_s / 1e9
+    if nrhs == 1:
+        kname = f"k_cheb_step<float,{b_},{info['fine_layout']}> (level 0)"
+    elif mfma:
+        kname = f"k_cheb_step_mfma8<{info['fine_layout']}> (level 0, 8 columns, v_mfma_f32_4x4x1f32)"
+    else:
+        kname = f"k_cheb_step_m<float,{b_},8,{info['fine_layout']}> (level 0, 8 columns)"
+    m = {
+        "value": pr["N"] * nrhs / (res["wall"] / steps),
+        "ms_per_step": res["wall"] / steps * 1e3,
+        "config": {"workload": WORKLOADS[workload],
+                   "n_dofs": int(pr["N"]), "rhs": nrhs, "cells_per_level": info["n_cells"],
+                   "precision": "mixed: FP32 V-cycle, FP64 PCG and coarse solve",
+                   "smoother": f"Chebyshev degree 3, 3 sweeps, {args.jacobi.replace('_', '-')} Jacobi",
+                   "dt": pr["dt"], "tol": args.tol},
+        "iters": _stats(res["its"]),
+        "setup_s": res["setup_s"],
+        "setup": {"where": args.setup,
+                  "phases_s": {k: round(v, 4) for k, v in info["t_setup"].items()}},
+        # achieved / frac: algorithmic bytes over the kernel's mean duration
+        # across its launches in time steps (HIP events on the solver's
+        # stream); the back-to-back figure repeats one launch on the same data
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(workload),
+                     "kernel": kname,
+                     "alg_bytes_per_launch": alg, "avg_launch_us": in_run_s * 1e6,
+                     "launches": prof["launches"],
+                     "avg_launch_us_back_to_back": b2b_s * 1e6,
+                     "frac_back_to_back": alg / b2b_s / 1e9 / HBM_PEAK_GBS,
+                     "working_set_bytes": ws,
+                     "residency": ("infinity_cache" if ws < INFINITY_CACHE_BYTES else "hbm")},
+    }
+    if m["roofline"]["residency"] == "infinity_cache":
+        m["roofline"]["note"] = ("the level-0 working set fits the 256 MB Infinity Cache: "
+                                 "the HBM peak is a reference, not the bound")
+    if info["fine_layout"] == "matrix_free":
+        # the sum-factorised kernel trades bytes for arithmetic: its FP32
+        # vector work (counted by rocprofv3) at the FP32 vector peak takes
+        # longer than its bytes at the HBM peak, so the arithmetic roofline
+        # is the binding one; the HBM figures stay alongside
+        fl = profiled_counters(workload).get("flops_per_launch")
+        if fl is not None:
+            hbm = {k: m["roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
+            tf = fl / in_run_s / 1e12
+            m["roofline"].update({"bound": "alu", "achieved": tf,
+                                  "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
+                                  "flops_per_launch": fl, "hbm": hbm})
+    if nrhs > 1:
+        fl = cheb_step_flops(info, nrhs) / in_run_s / 1e12
+        m["roofline"]["mfma" if mfma else "valu"] = {
+            "achieved_tflops": fl, "peak_tflops": MFMA_F32_PEAK_TFLOPS,
+            "utilisation": fl / MFMA_F32_PEAK_TFLOPS}
+    if not args.no_fp64:
+        r64 = run_gpu(pr, "fp64", steps, warmup, args.tol, nrhs=nrhs,
+                      fine_layout=args.fine_layout, setup=args.setup, jacobi=args.jacobi)
+        m["fp64"] = {"value": pr["N"] * nrhs / (r64["wall"] / steps),
+                     "ms_per_step": r64["wall"] / steps * 1e3,
+                     "iters": _stats(r64["its"])}
+        m["mixed_vs_fp64_rel_diff"] = float(np.abs(res["U"] - r64["U"]).max()
+                                            / np.abs(r64["U"]).max())
+    return res, m
 
 
 def main():
@@ -335,6 +466,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="default line without the 1.0M-hex shell sub-record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline", action="store_true",
                     help="time the oracle on the 3D workloads too (its set-up alone takes minutes "
@@ -385,73 +518,26 @@ def main():
         return
     from workloads import make_problem
     nrhs = 8 if args.workload == "c4x8" else 1
-    mfma = nrhs > 1 and not args.no_mfma
     pr = make_problem("c4" if args.workload == "c4x8" else args.workload)
-    res = run_gpu(pr, "mixed", args.steps, args.warmup, args.tol, profile_kind="cheb_step",
-                  nrhs=nrhs, mfma=mfma, fine_layout=args.fine_layout, setup=args.setup,
-                  jacobi=args.jacobi)
-    ms = res["wall"] / args.steps * 1e3
-    value = pr["N"] * nrhs / (res["wall"] / args.steps)
-    info = res["info"]
-    prof = res["prof"]
-    per_launch_s = prof["back_to_back_ms"] / 1e3
-    alg = cheb_step_bytes(info, 4, nrhs)
-    b_ = info["b"]
-    achieved = alg / per_launch_s / 1e9
-    if nrhs == 1:
-        kname = f"k_cheb_step<float,{b_},{info['fine_layout']}> (level 0)"
-    elif mfma:
-        kname = f"k_cheb_step_mfma8<{info['fine_layout']}> (level 0, 8 columns, v_mfma_f32_4x4x1f32)"
-    else:
-        kname = f"k_cheb_step_m<float,{b_},8,{info['fine_layout']}> (level 0, 8 columns)"
     out = {
-        "metric": METRIC, "value": value, "unit": "DoFs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "metric": METRIC, "value": None, "unit": "DoFs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
-                   "n_dofs": int(pr["N"]), "rhs": nrhs, "cells_per_level": info["n_cells"],
-                   "precision": "mixed: FP32 V-cycle, FP64 PCG and coarse solve",
-                   "smoother": f"Chebyshev degree 3, 3 sweeps, {args.jacobi.replace('_', '-')} Jacobi",
-                   "dt": pr["dt"], "tol": args.tol},
-        "iters": _stats(res["its"]),
-        "setup_s": res["setup_s"],
-        "setup": {"where": args.setup,
-                  "phases_s": {k: round(v, 4) for k, v in info["t_setup"].items()}},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(args.workload),
-                     "kernel": kname,
-                     "alg_bytes_per_launch": alg, "avg_launch_us": per_launch_s * 1e6,
-                     "avg_launch_us_in_run": prof["in_run_ms"] * 1e3,
-                     "launches_in_run": prof["launches"]},
     }
-    if info["fine_layout"] == "matrix_free":
-        # the sum-factorised kernel trades bytes for arithmetic: its FP32
-        # vector work (counted by rocprofv3) at the FP32 vector peak takes
-        # longer than its bytes at the HBM peak, so the arithmetic roofline
-        # is the binding one; the HBM figures stay alongside
-        fl = profiled_counters(args.workload).get("flops_per_launch")
-        if fl is not None:
-            hbm = {k: out["roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
-            tf = fl / per_launch_s / 1e12
-            out["roofline"].update({"bound": "alu", "achieved": tf,
-                                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                    "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
-                                    "flops_per_launch": fl, "hbm": hbm})
-    if nrhs > 1:
-        fl = cheb_step_flops(info, nrhs) / per_launch_s / 1e12
-        out["roofline"]["mfma" if mfma else "valu"] = {
-            "achieved_tflops": fl, "peak_tflops": MFMA_F32_PEAK_TFLOPS,
-            "utilisation": fl / MFMA_F32_PEAK_TFLOPS}
-    if not args.no_fp64:
-        r64 = run_gpu(pr, "fp64", args.steps, args.warmup, args.tol, nrhs=nrhs,
-                      fine_layout=args.fine_layout, setup=args.setup, jacobi=args.jacobi)
-        out["fp64"] = {"value": pr["N"] * nrhs / (r64["wall"] / args.steps),
-                       "ms_per_step": r64["wall"] / args.steps * 1e3,
-                       "iters": _stats(r64["its"])}
-        out["mixed_vs_fp64_rel_diff"] = float(np.abs(res["U"] - r64["U"]).max()
-                                              / np.abs(r64["U"]).max())
+    res, m = measure(args.workload, pr, args, args.steps, args.warmup, nrhs)
+    out["value"], out["ms_per_step"] = m.pop("value"), m.pop("ms_per_step")
+    out.update(m)
+    if args.workload == "c2" and not args.no_c4:
+        # the same measurement on the 1.0M-hex shell (HBM-resident level 0),
+        # single column, 20 time steps
+        log("shell sub-record")
+        pr4 = make_problem("c4")
+        k4 = min(args.steps, 20)
+        _, m4 = measure("c4", pr4, args, k4, min(args.warmup, 2), 1)
+        m4["steps"], m4["warmup"] = k4, min(args.warmup, 2)
+        out["c4"] = m4
+        del pr4
     if not args.no_cpu_baseline and args.workload != "c2" and not args.cpu_baseline:
         out["cpu_baseline"] = {"skipped": "the oracle's set-up on this 3D workload takes minutes; "
                                           "pass --cpu-baseline to time it (the c2 line carries it)"}

@@ -86,6 +86,15 @@ typedef struct {
 } dgmg_agglo_opts;
 
 /* Builds the nested agglomerated hierarchy {T_l} (host only, no device work).
+ * The caller's cell numbering is kept: no depth-first permutation of the
+ * R-tree's leaves is returned or applied, and vectors stay in the caller's
+ * order.  Agglomerates are described by parent arrays
+ * (dgmg_hierarchy_parents), which need no contiguity.  The fine level's
+ * device layout reads each lower face block transposed from the lower
+ * neighbour and coalesces those reads when consecutive cells have
+ * consecutive lower neighbours, which a grid (voxel) numbering gives and a
+ * tree or space-filling-curve order breaks (a Morton order measured 12%
+ * slower on the 1.0M-hex shell).
  * Errors: DGMG_EINVAL for bad sizes, empty agglomerates or a non-nested
  * partition; DGMG_ENOMEM. */
 int dgmg_build_hierarchy(const dgmg_mesh* mesh, const dgmg_agglo_opts* opts,
@@ -211,7 +220,11 @@ enum { DGMG_MULTI_RHS = 8 };
 /* Assembles A_0 = 3 chi C_m/(2 dt) M + A (eq. fully_discrete; bdf = 1 uses
  * chi C_m/dt), the prolongations, the Galerkin operators A_{l+1} = P^T A_l P
  * (eq. inherited_matrices, Algorithm 3), the smoother data and the dense
- * Cholesky factor of the coarsest operator, and uploads them.  Errors:
+ * Cholesky factor of the coarsest operator, and uploads them.  Set-up takes
+ * no stream and no separate allocator argument: it mixes host phases with
+ * blocking copies and device kernels on the current device's null stream,
+ * synchronises the device before returning, and takes the device allocator
+ * (if any) from mg->allocator, which it copies.  Errors:
  * DGMG_EINVAL (non-positive Jacobian, bad options), DGMG_ENOTSPD (coarse
  * pivot <= 0), DGMG_EUNSUPPORTED (dim, p), DGMG_EHIP, DGMG_ENOMEM. */
 int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc,
@@ -239,6 +252,10 @@ typedef struct {
      * distinct values (nested boxes) and are stored as a table of those with
      * a type per entity; 0 when every entity's block is stored */
     int32_t prolong_types[DGMG_MAX_LEVELS];
+    /* tile-ELL levels: 1 when the cells are assigned to tiles by descending
+     * neighbour count within runs of tiles (a tile-to-cell map, kept when it
+     * saves at least 3% of the padded slots), 0 for the identity order */
+    int32_t level_grouped[DGMG_MAX_LEVELS];
 } dgmg_solver_info;
 int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info);
 
@@ -256,14 +273,20 @@ typedef struct {
 } dgmg_pcg_stats;
 
 /* PCG on A_0 x = b with one V-cycle per iteration (section 6; section 3.1).
- * device b (N), device x (N; in: initial guess, out: solution).  Stops when
+ * device b (N), device x (N; in: initial guess, out: solution).  One
+ * right-hand side: several columns go through dgmg_pcg_solve_multi, whose
+ * kernels are compiled for a fixed column count (DGMG_MULTI_RHS) and whose
+ * stats are per column.  Stops when
  * ||r_k|| <= tol * ||r_0|| (REL_R0), tol * ||b|| (REL_B) or tol (ABS).
  * Errors: DGMG_ENOTSPD on (p, A p) <= 0 or (r, z) <= 0, DGMG_ENAN on a
  * non-finite residual, DGMG_NOT_CONVERGED after max_it. */
 int dgmg_pcg_solve(dgmg_solver* s, const double* b, double* x,
                    const dgmg_pcg_opts* opts, dgmg_pcg_stats* stats, void* stream);
 
-/* Ionic update at every DoF (section 3.1; models of section 2.2): with
+/* Ionic update at every DoF (section 3.1; models of section 2.2).  Takes the
+ * four state arrays as separate pointers rather than a dgmg_state, so that the
+ * caller chooses where W_{n+1} goes (it may overwrite W_{n-1}, as
+ * dgmg_time_step does).  With
  * U* = 2 U - Uprev (BDF2) or U (bdf 1), writes the BDF2 gate update
  * Wnext = (4 W - Wprev + 2 dt c0(U*)) / (3 - 2 dt c1(U*)) for dw/dt = c1 w + c0
  * and g = I_ion(U*, Wnext).  device U, Uprev, g: N; W, Wprev, Wnext: S x N
@@ -283,7 +306,9 @@ typedef struct {
 
 /* One time step t_n -> t_next (section 3.1): ionic update, load vector
  * M f with f = chi C_m/(2 dt)(4 U_n - U_{n-1}) + I_app - chi g (ICI), PCG
- * warm-started from U_n.  device iapp: N nodal applied current or NULL.  On
+ * warm-started from U_n.  device iapp: N nodal applied current or NULL,
+ * already evaluated at t_next by the caller; t_next itself is not read (the
+ * scheme's coefficients do not depend on t, and the caller owns the clock).  On
  * return the pointer pairs of *state are rotated: U holds U_{n+1}, Uprev
  * U_n, W holds W_{n+1}, Wprev W_n (no data is copied).  Errors as for
  * dgmg_pcg_solve. */

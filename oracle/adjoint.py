@@ -21,8 +21,10 @@ Ubar_{n+1}, Wbar_{n+1} accumulated from the loss and from later steps:
 The first step's history U_{-1} = U_0 is fixed data.  Forward states are
 recomputed segment by segment from checkpoints.
 
-Pin (tests/test_oracle_adjoint.py): central finite differences of the
-oracle's forward loss along random directions.
+Pins (tests/test_oracle_adjoint.py): central finite differences of the
+oracle's forward loss along random directions; the evaluation functionals
+e_k reproduce Q_p polynomials of the sensor cell's reference coordinates and
+linear physical fields at the mapped sensor points.
 """
 import numpy as np
 import scipy.sparse as sp

@@ -16,10 +16,15 @@ Readings of the paper used here (listed in the design notes):
 * Gauss-Legendre rules with p+1 points per direction on cells and faces,
   multilinear (Q1) geometry.
 
-Pins (tests/test_oracle_assembly.py): 1^T M 1 = |Omega|, closed-form mass on
-boxes, A 1 = 0, u^T A u = c^T D c |Omega| for linear u, v^T A u = int D grad
-u . grad v for continuous polynomials, symmetry, positive spectrum of
-c_M M + A, manufactured-solution convergence rates.
+Pins (tests/test_oracle_assembly.py, tests/test_oracle_geometry3d.py,
+tests/test_oracle_penalty.py): 1^T M 1 = |Omega|, closed-form mass on boxes,
+A 1 = 0, u^T A u = c^T D c |Omega| for linear u, v^T A u = int D grad u .
+grad v for continuous polynomials, symmetry, positive spectrum of c_M M + A,
+manufactured-solution convergence rates in 2D and on jittered hexahedra; on
+curved hexahedral faces the consistency term against exact vector areas of
+bilinear faces and the penalty term against tangent-cross-product normals
+and area elements; the indefiniteness of the paper's penalty on the seeded
+jittered square (and the inertia of the doubled one).
 """
 import numpy as np
 import scipy.sparse as sp

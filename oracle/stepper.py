@@ -14,7 +14,8 @@ assembled matrix serves every step.  bdf=1 selects backward Euler
 
 Pins (tests/test_oracle_stepper.py): spatially uniform data reduces to the
 per-DoF ODE integrator (second-order convergence against a fine reference
-integration); zero conductivity makes every DoF independent.
+integration); zero conductivity makes every DoF independent, including the
+applied-current term and the chi, C_m scalings of the load vector.
 """
 import time
 

@@ -83,7 +83,8 @@ class SolverInfo(C.Structure):
                 ("t_upload", C.c_double), ("device_bytes", C.c_int64),
                 ("fine_layout", C.c_int32),
                 ("level_layout", C.c_int32 * MAX_LEVELS),
-                ("prolong_types", C.c_int32 * MAX_LEVELS)]
+                ("prolong_types", C.c_int32 * MAX_LEVELS),
+                ("level_grouped", C.c_int32 * MAX_LEVELS)]
 
 
 class PCGOpts(C.Structure):

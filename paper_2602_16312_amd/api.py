@@ -164,7 +164,8 @@ class Solver:
                     device_bytes=i.device_bytes,
                     fine_layout=_LAYOUT_NAMES.get(i.fine_layout, "none"),
                     level_layout=[_LAYOUT_NAMES.get(v, "none") for v in i.level_layout[:L]],
-                    prolong_types=list(i.prolong_types[:L]))
+                    prolong_types=list(i.prolong_types[:L]),
+                    level_grouped=[bool(v) for v in i.level_grouped[:L]])
 
     def export_level(self, level, blocks=True):
         """Host copies of a level's FP64 operator and transfer blocks

@@ -3,6 +3,7 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -29,15 +30,18 @@ def _run(cmd):
 def build(verbose=False):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     for src in HOST_SOURCES:
         o = os.path.join(objdir, src + ".o")
-        _run([HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", o], o))
     for src in HIP_SOURCES:
         o = os.path.join(objdir, src + ".o")
-        _run([HIPCC, "-x", "hip"] + DEVICE_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC, "-x", "hip"] + DEVICE_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", o],
+                     o))
+    # the translation units are independent: compile them concurrently
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [o for _, o in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC] + DEVICE_FLAGS + ["-shared", "-fopenmp", "-o", tmp] + objs +
          ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"])

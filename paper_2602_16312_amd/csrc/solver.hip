@@ -542,27 +542,41 @@ static void apply_vcycle(dgmg_solver* s, const double* r, double* z, hipStream_t
     }
 }
 
-static double read_scalars(dgmg_solver* s, hipStream_t st, int R = 1) {
-    HIPCHK(hipMemcpyAsync(s->sc_host, s->sc, 8 * (size_t)R * sizeof(double), hipMemcpyDeviceToHost, st));
+static double read_scalars(dgmg_solver* s, hipStream_t st, int R = 1, const double* sc = nullptr) {
+    HIPCHK(hipMemcpyAsync(s->sc_host, sc ? sc : s->sc, 8 * (size_t)R * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
     HIPCHK(hipStreamSynchronize(st));
     return s->sc_host[0];
 }
 
+// Names the failed CG quantity: (p, A p) <= 0 means A_0 is not positive
+// definite along p; (r, z) <= 0 means the V-cycle is not.
+static std::string breakdown_msg(int its, int col, double pq, double gam) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "PCG breakdown at iteration %d%s%s: (p, A p) = %.6e, (r, z) = %.6e (%s)", its,
+                  col >= 0 ? " of column " : "", col >= 0 ? std::to_string(col).c_str() : "", pq, gam,
+                  !(pq > 0.0) ? "operator not positive definite along p" : "preconditioner not positive definite");
+    return buf;
+}
+
+// The reduction scratch (block partials and the 8 scalar slots: 0 ||r||^2,
+// 1 gamma = (r, z), 2 (p, A p), 3 the new (r, z), 4 beta, 5 (r_new, z_old),
+// 6 ||b||^2) is passed in (the solver's own buffers by default).
 static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& o, dgmg_pcg_stats* stats,
-               hipStream_t st) {
+               hipStream_t st, double* partial, double* sc) {
     const int64_t N = s->N;
     const unsigned nb = blocks_for(N);
     DevLevel& L0 = s->lv[0];
     const unsigned nt = level_tiles<double>(s, L0);   // partials of the block kernels
     // r = b - A x, ||r||^2
-    launch_residual<double>(s, L0, x, nullptr, b, s->r, nullptr, 1.0, nullptr, s->partial, st);
-    k_finalize<<<1, kWG, 0, st>>>(nt, s->partial, s->sc, 0, 0);
+    launch_residual<double>(s, L0, x, nullptr, b, s->r, nullptr, 1.0, nullptr, partial, st);
+    k_finalize<<<1, kWG, 0, st>>>(nt, partial, sc, 0, 0);
     double bnorm = 0.0;
     if (o.tol_mode == DGMG_TOL_REL_B) {
-        k_dot<<<nb, kWG, 0, st>>>(N, b, b, s->partial);
-        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 6, 0);
+        k_dot<<<nb, kWG, 0, st>>>(N, b, b, partial);
+        k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 6, 0);
     }
-    read_scalars(s, st);
+    read_scalars(s, st, 1, sc);
     const double r0 = std::sqrt(s->sc_host[0]);
     if (o.tol_mode == DGMG_TOL_REL_B) bnorm = std::sqrt(s->sc_host[6]);
     if (!std::isfinite(r0)) fail(DGMG_ENAN, "non-finite initial residual");
@@ -576,18 +590,18 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
         return DGMG_OK;
     }
     apply_vcycle(s, s->r, s->z, st);
-    k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
-    k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 1, 0);
-    k_update_p<<<nb, kWG, 0, st>>>(N, s->sc, s->z, s->pv, 1);
+    k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, partial);
+    k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 1, 0);
+    k_update_p<<<nb, kWG, 0, st>>>(N, sc, s->z, s->pv, 1);
     int its = 0;
     // mixed precision: the update also writes the FP32 right-hand side of the next V-cycle
     float* rb = s->prec == DGMG_PREC_MIXED ? (float*)L0.vb : nullptr;
     while (its < o.max_it) {
-        launch_apply<double>(s, L0, s->pv, s->q, s->pv, s->partial, st);
-        k_finalize<<<1, kWG, 0, st>>>(nt, s->partial, s->sc, 2, 0);
-        k_update_xr<<<nb, kWG, 0, st>>>(N, s->sc, s->pv, s->q, x, s->r, s->partial, rb);
-        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 0, 0);
-        read_scalars(s, st);
+        launch_apply<double>(s, L0, s->pv, s->q, s->pv, partial, st);
+        k_finalize<<<1, kWG, 0, st>>>(nt, partial, sc, 2, 0);
+        k_update_xr<<<nb, kWG, 0, st>>>(N, sc, s->pv, s->q, x, s->r, partial, rb);
+        k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 0, 0);
+        read_scalars(s, st, 1, sc);
         ++its;
         const double gam = s->sc_host[1], pq = s->sc_host[2];
         const double rn = std::sqrt(s->sc_host[0]);
@@ -595,7 +609,7 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
         stats->rfin = rn;
         if (!(pq > 0.0) || !(gam > 0.0)) {
             if (!std::isfinite(pq) || !std::isfinite(gam)) fail(DGMG_ENAN, "non-finite PCG scalar");
-            fail(DGMG_ENOTSPD, "PCG breakdown: (p, A p) <= 0 or (r, z) <= 0");
+            fail(DGMG_ENOTSPD, breakdown_msg(its, -1, pq, gam));
         }
         if (!std::isfinite(rn)) fail(DGMG_ENAN, "non-finite residual");
         if (rn <= thresh) {
@@ -605,15 +619,15 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
         if (o.flexible) {
             std::swap(s->z, s->zold);
             apply_vcycle(s, s->r, s->z, st, true);
-            k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->zold, s->partial);
-            k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 5, 0);
-            k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, s->partial);
+            k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->zold, partial);
+            k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 5, 0);
+            k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, partial);
         } else {
             // z = V(r) with the partials of (r, z) from the exit cast
-            apply_vcycle(s, s->r, s->z, st, true, s->partial);
+            apply_vcycle(s, s->r, s->z, st, true, partial);
         }
-        k_finalize<<<1, kWG, 0, st>>>(nb, s->partial, s->sc, 3, o.flexible ? 2 : 1);
-        k_update_p<<<nb, kWG, 0, st>>>(N, s->sc, s->z, s->pv, 0);
+        k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 3, o.flexible ? 2 : 1);
+        k_update_p<<<nb, kWG, 0, st>>>(N, sc, s->z, s->pv, 0);
     }
     return DGMG_NOT_CONVERGED;
 }
@@ -674,7 +688,7 @@ static int pcg_multi(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_
             stats[c].rfin = rn;
             if (!(pq > 0.0) || !(gam > 0.0)) {
                 if (!std::isfinite(pq) || !std::isfinite(gam)) fail(DGMG_ENAN, "non-finite PCG scalar");
-                fail(DGMG_ENOTSPD, "PCG breakdown: (p, A p) <= 0 or (r, z) <= 0");
+                fail(DGMG_ENOTSPD, breakdown_msg(its, c, pq, gam));
             }
             if (!std::isfinite(rn)) fail(DGMG_ENAN, "non-finite residual");
             if (rn <= thresh[c]) {
@@ -1184,6 +1198,12 @@ static void upload_level(dgmg_solver* s, int l) {
 }  // namespace dgmg
 
 // ====================================================================== C ABI
+// Number of block partials the single-column PCG reduces (the larger of the
+// vector kernels' and the level-0 block kernels' workgroup counts, plus slack).
+static int64_t pcg_partials(const dgmg_solver* s) {
+    return (int64_t)std::max(blocks_for(s->N), level_tiles<double>(s, s->lv[0])) + 16;
+}
+
 #define API_BEGIN try {
 #define API_END                                                          \
     }                                                                    \
@@ -1602,7 +1622,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         s->bwork = s->dalloc<double>(N * R);
         s->tmp64a = s->dalloc<double>(N);
         s->tmp64b = s->dalloc<double>(N);
-        s->partial = s->dalloc<double>((std::max(blocks_for(N), level_tiles<double>(s, s->lv[0])) + 16) * R);
+        s->partial = s->dalloc<double>(pcg_partials(s) * R);
         s->sc = s->dalloc<double>(8 * R);
         HIPCHK(hipMemset(s->sc, 0, 8 * R * sizeof(double)));
         HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * R * sizeof(double), hipHostMallocDefault));
@@ -1646,6 +1666,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     }
     s->info.fine_layout = s->info.level_layout[0];
     for (int l = 0; l < s->L; ++l) s->info.prolong_types[l] = s->on_device ? s->lv[l].ntypes : 0;
+    for (int l = 0; l < s->L; ++l) s->info.level_grouped[l] = s->on_device && s->lv[l].cmap ? 1 : 0;
     *out = guard.release();
     return DGMG_OK;
     API_END
@@ -1671,7 +1692,7 @@ int dgmg_pcg_solve(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_op
     API_BEGIN
     need_device(s);
     if (!b || !x || !o || !st) fail(DGMG_EINVAL, "null argument");
-    return pcg(s, b, x, *o, st, (hipStream_t)stream);
+    return pcg(s, b, x, *o, st, (hipStream_t)stream, s->partial, s->sc);
     API_END
 }
 
@@ -1701,7 +1722,7 @@ int dgmg_time_step(dgmg_solver* s, dgmg_state* z, double t_next, const double* i
     DISPATCH_B(s->b, k_rhs<BV><<<nblk, cells_per * BV, 0, hs>>>(s->lv[0].n, s->ip, s->cU, s->mass, z->U,
                                                                  z->Uprev, iapp, z->g, s->bwork, z->Uprev));
     HIPCHK(hipGetLastError());
-    int rc = pcg(s, s->bwork, z->Uprev, *o, st, hs);
+    int rc = pcg(s, s->bwork, z->Uprev, *o, st, hs, s->partial, s->sc);
     std::swap(z->U, z->Uprev);
     std::swap(z->W, z->Wprev);
     return rc;

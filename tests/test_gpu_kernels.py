@@ -88,6 +88,27 @@ def test_irregular_agglomerates_keep_tile_layout():
     say("apply shell level 1")
     api.apply(s, 1, dev(x), y, "fp64")
     assert rel(host(y), mg.A[1] @ x) <= 1e-13
+    # the STR levels' cells are grouped into tiles by neighbour count
+    grouped = s.info()["level_grouped"]
+    assert not grouped[0] and any(grouped[1:-1]), grouped
+
+
+def test_point_jacobi_vcycle_on_grouped_str_levels():
+    """The paper's point-Jacobi V-cycle on the shell (axis layout on level 0,
+    tile layout with grouped tiles on the STR levels) equals the oracle's
+    V-cycle, FP64 and mixed."""
+    pr = make_problem("c4", h=0.09)
+    A0 = system_matrix(pr)[0]
+    mg = VCycle(A0, oracle_hierarchy(pr)["P"])
+    r = np.random.default_rng(16).standard_normal(pr["N"])
+    ref = mg(r)
+    for prec, tol in (("fp64", 1e-11), ("mixed", 2e-5)):
+        h, s = problem.build(pr, precision=prec, lam_override=mg.lam)
+        assert any(s.info()["level_grouped"][1:-1])
+        z = torch.empty(pr["N"], dtype=torch.float64, device="cuda")
+        say("vcycle shell grouped STR levels", prec)
+        api.vcycle(s, dev(r), z)
+        assert rel(host(z), ref) <= tol, prec
 
 
 @pytest.mark.parametrize("layout", ["auto", "axis_ell", "tile_ell"])

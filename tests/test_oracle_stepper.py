@@ -72,3 +72,32 @@ def test_zero_conductivity_decouples_dofs():
         U, Um = 2 * dt * f / 3, U
         W, Wm = Wn, W
         assert np.allclose(hist[n], U, rtol=1e-12, atol=1e-13)
+
+
+def test_zero_conductivity_with_applied_current_and_scalings():
+    """sigma = 0 with chi, C_m != 1 and a constant applied current on part of
+    the mesh: c_M M U' = M f with c_M = 3 chi C_m / (2 dt) gives, per DoF,
+    U' = 2 dt f / (3 chi C_m) with
+    f = chi C_m / (2 dt) (4 U - U_prev) + I_app - chi g (eq. fully_discrete,
+    ionic current interpolation)."""
+    chi, Cm, amp = 2.5, 0.8, 0.7
+    pr = make_problem("c1", n=4, sigma=("iso", 0.0), chi=chi, Cm=Cm)
+    rng = np.random.default_rng(9)
+    pr["U0"] = rng.uniform(0, 1, pr["N"])
+    stim = np.zeros(pr["n_cells"], dtype=bool)
+    stim[[0, 3, 5, 10]] = True
+    iapp = np.repeat(stim, pr["b"]) * amp
+    sim = Simulation(pr)
+    st, hist, _ = sim.run(4, 1e-14, iapp_fn=lambda t: iapp)
+    U, Um = pr["U0"].copy(), pr["U0"].copy()
+    W, Wm = pr["W0"].copy(), pr["W0"].copy()
+    k, a, eps, gam = pr["params"]
+    dt = pr["dt"]
+    for n in range(4):
+        us = 2 * U - Um
+        Wn = (4 * W - Wm + 2 * dt * eps * us) / (3 + 2 * dt * eps * gam)
+        g = k * us * (us - a) * (us - 1) + Wn[0]
+        f = chi * Cm / (2 * dt) * (4 * U - Um) + iapp - chi * g
+        U, Um = 2 * dt * f / (3 * chi * Cm), U
+        W, Wm = Wn, W
+        assert np.allclose(hist[n], U, rtol=1e-12, atol=1e-13)

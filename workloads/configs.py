@@ -49,8 +49,10 @@ CONFIGS = {
                penalty=("fixed", 10.0 * 1 ** 2 * 32), ic="corner_disc",
                stim=None, tol=1e-10),
     # 256x256 jittered Q2, Aliev-Panfilov, three levels (4x4 grouping twice).
-    # The paper's penalty (factor 1) leaves A_0 indefinite on a few of the
-    # most distorted cells of this seeded mesh; factor 2 restores coercivity.
+    # The paper's penalty (factor 1) leaves A_0 indefinite on this seeded
+    # mesh (negative diagonal entries at the most distorted cells); factor 2
+    # makes it positive definite (no negative pivot in a symmetric
+    # factorisation).
     "c2": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
                sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=100,
                model="ap", params=[8.0, 0.15, 0.002],
@@ -65,7 +67,12 @@ CONFIGS = {
     # ventricle-like truncated ellipsoidal shell (~1.0M voxel hexes, interior
     # nodes jittered +-0.15 h), Q1, transmural fibres, Bueno-Orovio (ms),
     # five STR R-tree levels of fanout 8, eight stimulus sites (apex + 7
-    # endocardial) for the multi-right-hand-side runs.
+    # endocardial) for the multi-right-hand-side runs.  The paper's penalty
+    # (factor 1) leaves A_0 indefinite on this mesh: the 16 x 16 principal
+    # submatrix of a pair of face-neighbour cells next to the surface has a
+    # negative eigenvalue (and CG meets (p, A p) < 0); factor 2 as on the
+    # jittered square.  On a coarser shell of the same construction
+    # (h = 0.06) factor 1 is provably positive definite.
     "c4": dict(kind="shell", dim=3, h=0.0147, p=1, jitter=0.15, seed=2603,
                agglo=("rtree_str", 8, 5), group=[],
                sigma=("fibre_shell", 1.2e-3, 2.5e-4), chi=1.0, Cm=1.0, dt=5e-2,
