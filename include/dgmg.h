@@ -283,6 +283,23 @@ typedef struct {
 int dgmg_pcg_solve(dgmg_solver* s, const double* b, double* x,
                    const dgmg_pcg_opts* opts, dgmg_pcg_stats* stats, void* stream);
 
+/* dgmg_pcg_solve for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same solve, bit-identical results, with the
+ * reduction scratch (block partials and the 8 CG scalar slots) in a static
+ * per-GPU device array of 1 MiB instead of the solver's buffers.  It calls
+ * no hipMalloc, hipFree or allocating library routine; the solver's set-up
+ * resolved the array's device address.  Every call on one GPU shares that
+ * array and its contents persist between calls (the scalar slots are
+ * cleared by a fill kernel on `stream` at entry), so calls that overlap on
+ * one GPU, from any solver or stream, race and must be serialised by the
+ * caller.  Limit: the solve needs 48 + max(ceil(N / 256), level-0
+ * workgroups) doubles of the array's 131,072 (N up to about 31M DoFs);
+ * larger solvers get DGMG_EINVAL and must use dgmg_pcg_solve.  Other
+ * errors as for dgmg_pcg_solve. */
+int dgmg_pcg_solve_noalloc(dgmg_solver* s, const double* b, double* x,
+                           const dgmg_pcg_opts* opts, dgmg_pcg_stats* stats, void* stream);
+
 /* Ionic update at every DoF (section 3.1; models of section 2.2).  Takes the
  * four state arrays as separate pointers rather than a dgmg_state, so that the
  * caller chooses where W_{n+1} goes (it may overwrite W_{n-1}, as

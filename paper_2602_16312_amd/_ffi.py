@@ -20,6 +20,7 @@ EXPORTS = [
     "dgmg_apply", "dgmg_vcycle", "dgmg_mass_apply", "dgmg_export_level",
     "dgmg_profile_begin", "dgmg_profile_end", "dgmg_kernel_bench", "dgmg_last_error",
     "dgmg_set_sensors", "dgmg_sensor_misfit", "dgmg_adjoint_step", "dgmg_grad_accumulate",
+    "dgmg_pcg_solve_noalloc",
 ]
 
 dp = C.POINTER(C.c_double)
@@ -126,6 +127,7 @@ def lib():
         L.dgmg_destroy_solver.restype = None
         L.dgmg_get_info.argtypes = [vp, C.POINTER(SolverInfo)]
         L.dgmg_pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PCGOpts), C.POINTER(PCGStats), vp]
+        L.dgmg_pcg_solve_noalloc.argtypes = [vp, vp, vp, C.POINTER(PCGOpts), C.POINTER(PCGStats), vp]
         L.dgmg_ionic_step.argtypes = [vp] * 7 + [vp]
         L.dgmg_time_step.argtypes = [vp, C.POINTER(State), C.c_double, vp,
                                      C.POINTER(PCGOpts), C.POINTER(PCGStats), vp]

@@ -262,6 +262,18 @@ def pcg_solve(solver, b, x, tol=1e-8, tol_mode="rel_r0", max_it=500, flexible=Fa
     return _stats(st, rc)
 
 
+def pcg_solve_noalloc(solver, b, x, tol=1e-8, tol_mode="rel_r0", max_it=500, flexible=False,
+                      stream=None):
+    """dgmg_pcg_solve_noalloc: pcg_solve with the reduction scratch in the
+    library's static per-GPU array (no device allocation during the call;
+    overlapping calls on one GPU race)."""
+    st = F.PCGStats()
+    o = _pcg_opts(tol, tol_mode, max_it, flexible)
+    rc = F.check(F.lib().dgmg_pcg_solve_noalloc(solver.handle, _dev(b), _dev(x), C.byref(o),
+                                                C.byref(st), _stream(stream)))
+    return _stats(st, rc)
+
+
 def pcg_solve_multi(solver, b, x, tol=1e-8, tol_mode="rel_r0", max_it=500, flexible=False,
                     stream=None):
     """dgmg_pcg_solve_multi: MULTI_RHS independent solves; b, x are [N, MULTI_RHS]

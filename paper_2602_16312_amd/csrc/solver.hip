@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <type_traits>
@@ -155,6 +156,7 @@ struct dgmg_solver {
     double* partial = nullptr;
     double* sc = nullptr;
     double* sc_host = nullptr;
+    double* scratch = nullptr;     // this device's static PCG scratch (dgmg_pcg_solve_noalloc)
     int32_t* act = nullptr;        // per-column active mask of multi-column PCG
     int32_t* act_host = nullptr;   // pinned staging of that mask
     double* mass = nullptr;
@@ -561,7 +563,8 @@ static std::string breakdown_msg(int its, int col, double pq, double gam) {
 
 // The reduction scratch (block partials and the 8 scalar slots: 0 ||r||^2,
 // 1 gamma = (r, z), 2 (p, A p), 3 the new (r, z), 4 beta, 5 (r_new, z_old),
-// 6 ||b||^2) is passed in (the solver's own buffers by default).
+// 6 ||b||^2) is passed in: the solver's own buffers, or the static array of
+// the non-allocating entry point.
 static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& o, dgmg_pcg_stats* stats,
                hipStream_t st, double* partial, double* sc) {
     const int64_t N = s->N;
@@ -1204,6 +1207,37 @@ static int64_t pcg_partials(const dgmg_solver* s) {
     return (int64_t)std::max(blocks_for(s->N), level_tiles<double>(s, s->lv[0])) + 16;
 }
 
+// ------------------------------------------------- static PCG scratch
+// Reduction scratch of dgmg_pcg_solve_noalloc: the 8 scalar slots of pcg()
+// at offset 0 and its block partials from kScratchPartial on.  A file-scope
+// device array: every GPU the library runs on holds its own copy, at its own
+// address, until the process ends.  Host code never passes `scratch` itself
+// (in host code the name is a stand-in, not a device address); it uses the
+// address hipGetSymbolAddress returns for the device, resolved once per
+// device at set-up.
+constexpr int64_t kScratchDoubles = 131072;   // 1 MiB per GPU
+constexpr int64_t kScratchPartial = 32;       // partials start 256 bytes in
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Address of `scratch` on the current device (resolved on the first call
+// for that device, with it current).
+static double* scratch_address() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) fail(DGMG_EUNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(DGMG_EHIP, "hipGetSymbolAddress returned a null address for the PCG scratch");
+        g_scratch_dev[dev] = (double*)p;
+    }
+    return g_scratch_dev[dev];
+}
+
 #define API_BEGIN try {
 #define API_END                                                          \
     }                                                                    \
@@ -1623,6 +1657,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         s->tmp64a = s->dalloc<double>(N);
         s->tmp64b = s->dalloc<double>(N);
         s->partial = s->dalloc<double>(pcg_partials(s) * R);
+        s->scratch = scratch_address();
         s->sc = s->dalloc<double>(8 * R);
         HIPCHK(hipMemset(s->sc, 0, 8 * R * sizeof(double)));
         HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * R * sizeof(double), hipHostMallocDefault));
@@ -1693,6 +1728,26 @@ int dgmg_pcg_solve(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_op
     need_device(s);
     if (!b || !x || !o || !st) fail(DGMG_EINVAL, "null argument");
     return pcg(s, b, x, *o, st, (hipStream_t)stream, s->partial, s->sc);
+    API_END
+}
+
+int dgmg_pcg_solve_noalloc(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts* o,
+                           dgmg_pcg_stats* st, void* stream) {
+    API_BEGIN
+    need_device(s);
+    if (!b || !x || !o || !st) fail(DGMG_EINVAL, "null argument");
+    const int64_t need = kScratchPartial + pcg_partials(s);
+    if (need > kScratchDoubles)
+        fail(DGMG_EINVAL, "dgmg_pcg_solve_noalloc: this solver needs " + std::to_string(need) +
+                              " doubles of reduction scratch; the static array holds " +
+                              std::to_string(kScratchDoubles) + " (use dgmg_pcg_solve)");
+    if (!s->scratch) fail(DGMG_EINVAL, "the static PCG scratch was not resolved at set-up");
+    hipStream_t hs = (hipStream_t)stream;
+    // the array keeps the previous call's contents: clear the scalar slots
+    // with a fill kernel (every partial is written before it is read)
+    k_fill<double><<<1, kWG, 0, hs>>>(kScratchPartial, s->scratch, 0.0);
+    HIPCHK(hipGetLastError());
+    return pcg(s, b, x, *o, st, hs, s->scratch + kScratchPartial, s->scratch);
     API_END
 }
 
