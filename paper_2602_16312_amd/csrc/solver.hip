@@ -11,6 +11,7 @@
 // sweep's last step also applies its final "x += d" (for degree 1 that
 // correction is carried as pending and fused into the next kernel that
 // reads x).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -261,14 +262,13 @@ static const T* PofT(const DevLevel& L, int b) {
     return Pof<T>(L) + (L.ptype ? (size_t)L.ntypes * b * b : 0);
 }
 
-// Brackets one launch with a pair of events when that kernel kind/level is
-// being timed (see dgmg_profile_begin).
+// Selects the event pair of one launch when that kernel kind/level is being
+// timed (see dgmg_profile_begin); klaunch attaches the pair to the launch.
 struct ProfScope {
     dgmg_solver* s;
-    hipStream_t st;
     bool on = false;
     size_t idx = 0;
-    ProfScope(dgmg_solver* s_, int kind, int level, hipStream_t st_) : s(s_), st(st_) {
+    ProfScope(dgmg_solver* s_, int kind, int level, hipStream_t) : s(s_) {
         if (s->prof_kind != kind || s->prof_level != level) return;
         if (s->prof_used == s->prof_ev.size()) {
             hipEvent_t a, b;
@@ -278,12 +278,20 @@ struct ProfScope {
         }
         idx = s->prof_used++;
         on = true;
-        HIPCHK(hipEventRecord(s->prof_ev[idx].first, st));
-    }
-    ~ProfScope() {
-        if (on) (void)hipEventRecord(s->prof_ev[idx].second, st);
     }
 };
+
+// Launches kernel k on st.  When the scope is timing this launch, the start
+// and stop events ride on the kernel's own dispatch (hipExtLaunchKernelGGL),
+// so their interval is the kernel's execution alone, without the dispatch
+// gaps that separately recorded events would add.
+template <typename... KA, typename... A>
+static void klaunch(const ProfScope& ps, void (*k)(KA...), dim3 grid, dim3 block, hipStream_t st,
+                    A&&... a) {
+    hipEvent_t e0 = ps.on ? ps.s->prof_ev[ps.idx].first : nullptr;
+    hipEvent_t e1 = ps.on ? ps.s->prof_ev[ps.idx].second : nullptr;
+    hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, static_cast<KA>(a)...);
+}
 enum { PK_CHEB_STEP = 0, PK_RESIDUAL = 1, PK_APPLY = 2, PK_RESTRICT = 3, PK_PROLONG = 4,
        PK_COARSE = 5 };
 
@@ -308,12 +316,12 @@ static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, c
     ProfScope ps(s, PK_APPLY, level_index(s, L), st);
     DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
-            DISPATCH_B(s->b, k_apply<T, BV, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y, w,
+            DISPATCH_B(s->b, klaunch(ps, k_apply<T, BV, LYV>, tiles_for<T, BV>(L), kWG, st, largs<T>(L), va, y, w,
                                                                                         partial));
         } else if constexpr (LYV == LY_MF) {
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
-            DISPATCH_B(s->b, k_apply_m<T, BV, R, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), va, y,
+            DISPATCH_B(s->b, klaunch(ps, k_apply_m<T, BV, R, AXV>, tiles_for<T, BV>(L), kWG, st, largs<T>(L), va, y,
                                                                                             w, partial));
         }
     });
@@ -326,10 +334,10 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
     DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
             if (vb) {
-                DISPATCH_B(s->b, k_residual<T, BV, true, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                DISPATCH_B(s->b, klaunch(ps, k_residual<T, BV, true, LYV>, tiles_for<T, BV>(L), kWG, st,
                                      largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
             } else {
-                DISPATCH_B(s->b, k_residual<T, BV, false, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                DISPATCH_B(s->b, klaunch(ps, k_residual<T, BV, false, LYV>, tiles_for<T, BV>(L), kWG, st,
                                      largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
             }
         } else if constexpr (LYV == LY_MF) {
@@ -339,20 +347,20 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
             if constexpr (std::is_same<T, float>::value && R == 8) {
                 if (s->mfma && s->b == 8) {
                     if (vb)
-                        k_residual_m<float, 8, 8, true, AXV, true><<<tiles_for<float, 8>(L), kWG, 0, st>>>(
+                        klaunch(ps, k_residual_m<float, 8, 8, true, AXV, true>, tiles_for<float, 8>(L), kWG, st,
                             largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype);
                     else
-                        k_residual_m<float, 8, 8, false, AXV, true><<<tiles_for<float, 8>(L), kWG, 0, st>>>(
+                        klaunch(ps, k_residual_m<float, 8, 8, false, AXV, true>, tiles_for<float, 8>(L), kWG, st,
                             largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype);
                     done = true;
                 }
             }
             if (!done) {
                 if (vb) {
-                    DISPATCH_B(s->b, k_residual_m<T, BV, R, true, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                    DISPATCH_B(s->b, klaunch(ps, k_residual_m<T, BV, R, true, AXV>, tiles_for<T, BV>(L), kWG, st,
                                          largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
                 } else {
-                    DISPATCH_B(s->b, k_residual_m<T, BV, R, false, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                    DISPATCH_B(s->b, klaunch(ps, k_residual_m<T, BV, R, false, AXV>, tiles_for<T, BV>(L), kWG, st,
                                          largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
                 }
             }
@@ -365,7 +373,7 @@ static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* 
     ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
     DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
-            DISPATCH_B(s->b, k_cheb_step<T, BV, LYV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(largs<T>(L), d, x, r,
+            DISPATCH_B(s->b, klaunch(ps, k_cheb_step<T, BV, LYV>, tiles_for<T, BV>(L), kWG, st, largs<T>(L), d, x, r,
                                                                                            dn, cd, cr, assign,
                                                                                            last));
         } else if constexpr (LYV == LY_MF) {
@@ -374,13 +382,13 @@ static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* 
             bool done = false;
             if constexpr (std::is_same<T, float>::value && R == 8) {
                 if (s->mfma && s->b == 8) {
-                    k_cheb_step_mfma8<AXV><<<tiles_for<float, 8>(L), kWG, 0, st>>>(largs<float>(L), d, x, r, dn,
+                    klaunch(ps, k_cheb_step_mfma8<AXV>, tiles_for<float, 8>(L), kWG, st, largs<float>(L), d, x, r, dn,
                                                                                   cd, cr, assign, last);
                     done = true;
                 }
             }
             if (!done) {
-                DISPATCH_B(s->b, k_cheb_step_m<T, BV, R, AXV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                DISPATCH_B(s->b, klaunch(ps, k_cheb_step_m<T, BV, R, AXV>, tiles_for<T, BV>(L), kWG, st,
                                      largs<T>(L), d, x, r, dn, cd, cr, assign, last));
             }
         }
@@ -393,9 +401,9 @@ static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
     ProfScope ps(s, PK_COARSE, s->L - 1, st);
     const int rows_per_wg = kWG / 64;   // one row per wave
     if constexpr (R == 1)
-        k_coarse_solve<T, T><<<(n + rows_per_wg - 1) / rows_per_wg, kWG, 0, st>>>(n, s->Ainv, rc, xc);
+        klaunch(ps, k_coarse_solve<T, T>, (n + rows_per_wg - 1) / rows_per_wg, kWG, st, n, s->Ainv, rc, xc);
     else
-        k_coarse_solve_m<T, T, R><<<(n + rows_per_wg - 1) / rows_per_wg, kWG, 0, st>>>(n, s->Ainv, rc, xc);
+        klaunch(ps, k_coarse_solve_m<T, T, R>, (n + rows_per_wg - 1) / rows_per_wg, kWG, st, n, s->Ainv, rc, xc);
 }
 
 // One V-cycle from level l on R columns; the result is x + d (d may be null).
@@ -486,10 +494,10 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     {
     ProfScope ps(s, PK_RESTRICT, l, st);
     if constexpr (R == 1) {
-        DISPATCH_B(s->b, k_restrict_sum<T, BV><<<blocks_for(C.N), kWG, 0, st>>>(C.n, C.child_ptr, C.child_list,
+        DISPATCH_B(s->b, klaunch(ps, k_restrict_sum<T, BV>, blocks_for(C.N), kWG, st, C.n, C.child_ptr, C.child_list,
                                                                                  rp, (T*)C.vb));
     } else {
-        DISPATCH_B(s->b, k_restrict_sum_m<T, BV, R><<<blocks_for(C.N * R), kWG, 0, st>>>(
+        DISPATCH_B(s->b, klaunch(ps, k_restrict_sum_m<T, BV, R>, blocks_for(C.N * R), kWG, st,
                              C.n, C.child_ptr, C.child_list, rp, (T*)C.vb));
     }
     }
@@ -498,10 +506,10 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     {
     ProfScope ps(s, PK_PROLONG, l, st);
     if constexpr (R == 1) {
-        DISPATCH_B(s->b, k_prolong_add<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent, PofT<T>(L, s->b), xc,
+        DISPATCH_B(s->b, klaunch(ps, k_prolong_add<T, BV>, tiles_for<T, BV>(L), kWG, st, L.n, L.parent, PofT<T>(L, s->b), xc,
                                                                                      dc, x, L.ptype));
     } else {
-        DISPATCH_B(s->b, k_prolong_add_m<T, BV, R><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, L.parent,
+        DISPATCH_B(s->b, klaunch(ps, k_prolong_add_m<T, BV, R>, tiles_for<T, BV>(L), kWG, st, L.n, L.parent,
                                                                                          PofT<T>(L, s->b), xc, dc, x, L.ptype));
     }
     }
