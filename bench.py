@@ -295,6 +295,8 @@ def _its_stats(pr, precision, tol, tol_mode, **mg):
     import torch
     from paper_2602_16312_amd import api, problem
     t0 = time.perf_counter()
+    mg.setdefault("setup", "device")
+    mg.setdefault("allocator", "torch")
     h, s = problem.build(pr, precision=precision, **mg)
     setup = time.perf_counter() - t0
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
@@ -314,15 +316,19 @@ def _its_stats(pr, precision, tol, tol_mode, **mg):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     info = s.info()
-    return dict(its=_stats(its), levels=info["n_cells"], n_dofs=int(pr["N"]), setup_s=setup,
+    return dict(its=_stats(its), its_per_step=its, levels=info["n_cells"], n_dofs=int(pr["N"]),
+                setup_s=setup,
                 ms_per_step=wall / pr["steps"] * 1e3, u_max=float(st.U.max()))
 
 
-def run_sweep(kind, precision, fine_layout="auto"):
+def run_sweep(kind, precision, fine_layout="auto", mesh="c4"):
     """Iteration-count sweeps in the shape of the paper's tables: "e1" the
     two-dimensional FitzHugh-Nagumo test for p = 1..4 (iterations per step
-    over T = 0.4 s); "levels" and "dt" on a 125k-hex shell (number of
-    multigrid levels; time step)."""
+    over T = 0.4 s); "levels" (number of multigrid levels) and "dt" (time
+    step) over 5 ms of simulated time on the full 1.0M-hex shell (mesh "c4",
+    p = 1), the 64^3 Q2 cube (mesh "c3") or the 125k-hex shell (mesh
+    "c4half", p = 1 and 2).  The coarsest level is solved with its dense
+    inverse, so the level counts start where that fits."""
     from workloads import make_problem
     rows = []
     if kind == "e1":
@@ -335,22 +341,39 @@ def run_sweep(kind, precision, fine_layout="auto"):
         desc = ("128x128 Q1-Q4 FitzHugh-Nagumo, shock on [0.4,0.6]^2, dt 1e-4 s, 4000 steps, "
                 "PCG to absolute residual 1e-14, 3 grid-grouped levels (4x4)")
     elif kind in ("levels", "dt"):
-        cases = ([(1, 3, 0.05), (1, 4, 0.05), (1, 5, 0.05), (2, 4, 0.05), (2, 5, 0.05)]
-                 if kind == "levels" else
-                 [(p, 5, dt) for p in (1, 2) for dt in (0.5, 0.1, 0.05)])
+        if mesh == "c3":
+            # 2x2x2 grid grouping: 64^3 -> 32^3 -> ... ; L levels in all
+            cases = ([(2, L, 0.05) for L in (4, 5, 6)] if kind == "levels" else
+                     [(2, 4, dt) for dt in (0.5, 0.1, 0.05)])
+            mk = lambda p, L, dt: make_problem("c3", p=p, group=[2] * (L - 1), dt=dt,
+                                               steps=int(round(5.0 / dt)))
+            desc = ("64^3 Q2 cube (7.08M DoFs), rotating fibres, Bueno-Orovio, corner stimulus, "
+                    "2x2x2 grid levels, 5 ms of simulated time, PCG to relative residual 1e-8")
+        elif mesh == "c4":
+            cases = ([(1, L, 0.05) for L in (4, 5, 6)] if kind == "levels" else
+                     [(1, 5, dt) for dt in (0.5, 0.1, 0.05)])
+            mk = lambda p, L, dt: make_problem("c4", p=p, agglo=("rtree_str", 8, L), dt=dt,
+                                               steps=int(round(5.0 / dt)))
+            desc = ("1.0M-hex shell (h 0.0147, 8.0M DoFs), Bueno-Orovio, apex stimulus, STR levels, "
+                    "5 ms of simulated time, PCG to relative residual 1e-8")
+        else:
+            cases = ([(1, 3, 0.05), (1, 4, 0.05), (1, 5, 0.05), (2, 4, 0.05), (2, 5, 0.05)]
+                     if kind == "levels" else
+                     [(p, 5, dt) for p in (1, 2) for dt in (0.5, 0.1, 0.05)])
+            mk = lambda p, L, dt: make_problem("c4", h=0.0294, p=p, agglo=("rtree_str", 8, L), dt=dt,
+                                               steps=int(round(5.0 / dt)))
+            desc = ("125k-hex shell (h 0.0294), Bueno-Orovio, apex stimulus, STR levels, 5 ms of "
+                    "simulated time, PCG to relative residual 1e-8")
         for p, L, dt in cases:
-            pr = make_problem("c4", h=0.0294, p=p, agglo=("rtree_str", 8, L), dt=dt,
-                              steps=int(round(5.0 / dt)))
-            r = _its_stats(pr, precision, 1e-8, "rel_r0")
+            pr = mk(p, L, dt)
+            r = _its_stats(pr, precision, 1e-8, "rel_r0", fine_layout=fine_layout)
             r.update(p=p, n_levels=L, dt=dt)
             rows.append(r)
-            log(f"{kind} p={p} L={L} dt={dt}: {r['its']}")
-        desc = ("125k-hex shell (h 0.0294), Bueno-Orovio, apex stimulus, STR levels, 5 ms of "
-                "simulated time, PCG to relative residual 1e-8")
+            log(f"{kind} {mesh} p={p} L={L} dt={dt}: {r['its']}")
     else:
         raise SystemExit(f"unknown sweep {kind}")
-    print(json.dumps({"sweep": kind, "precision": precision, "fine_layout": fine_layout,
-                      "workload": desc, "rows": rows}))
+    print(json.dumps({"sweep": kind, "mesh": mesh, "precision": precision,
+                      "fine_layout": fine_layout, "workload": desc, "rows": rows}))
 
 
 def cpu_baseline(pr, tol, nsteps):
@@ -489,6 +512,9 @@ def main():
     ap.add_argument("--sweep", choices=["e1", "levels", "dt"],
                     help="print PCG iteration statistics of a sweep instead of the bench line")
     ap.add_argument("--sweep-precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--sweep-mesh", default="c4", choices=["c4", "c3", "c4half"],
+                    help="mesh of the levels/dt sweeps: the full shell, the 64^3 cube or the "
+                         "125k-hex shell")
     ap.add_argument("--no-mfma", action="store_true",
                     help="c4x8: keep the 8-column Chebyshev step on the vector ALUs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -511,7 +537,7 @@ def main():
         return
 
     if args.sweep:
-        run_sweep(args.sweep, args.sweep_precision, args.fine_layout)
+        run_sweep(args.sweep, args.sweep_precision, args.fine_layout, args.sweep_mesh)
         return
     if args.workload == "c5":
         run_adjoint(args)

@@ -193,16 +193,20 @@ class VCycle:
     __call__ = apply
 
 
-def pcg(A, b, x0, prec, tol, max_it=500, flexible=False):
+def pcg(A, b, x0, prec, tol, max_it=500, flexible=False, tol_mode="rel"):
     """Preconditioned conjugate gradients from the warm start x0.
 
-    Returns (x, stats) with stats = dict(its, r0, rfin, converged).
+    Stops when ||r_k|| <= tol ||r_0|| (tol_mode "rel"), or ||r_k|| <= tol
+    ("abs", the absolute residual of the paper's two-dimensional test in
+    section 6).  Returns (x, stats) with stats = dict(its, r0, rfin,
+    converged).
     """
     x = x0.copy()
     r = b - A @ x
     r0 = np.linalg.norm(r)
-    if r0 == 0.0:
-        return x, dict(its=0, r0=0.0, rfin=0.0, converged=True)
+    thresh = tol if tol_mode == "abs" else tol * r0
+    if r0 == 0.0 or (tol_mode == "abs" and r0 <= thresh):
+        return x, dict(its=0, r0=r0, rfin=r0, converged=True)
     z = prec(r)
     p = z.copy()
     gamma = r @ z
@@ -218,7 +222,7 @@ def pcg(A, b, x0, prec, tol, max_it=500, flexible=False):
         r = r - alpha * q
         its += 1
         rn = np.linalg.norm(r)
-        if rn <= tol * r0:
+        if rn <= thresh:
             return x, dict(its=its, r0=r0, rfin=rn, converged=True)
         z_old = z
         z = prec(r)

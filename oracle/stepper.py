@@ -50,7 +50,7 @@ class Simulation:
             f = f + iapp
         return self.M @ f
 
-    def step(self, state, t_next, tol, iapp=None, max_it=500):
+    def step(self, state, t_next, tol, iapp=None, max_it=500, tol_mode="rel"):
         pr = self.prob
         Un, Unm1, Wn, Wnm1 = state
         ustar = 2.0 * Un - Unm1 if self.bdf == 2 else Un
@@ -58,10 +58,10 @@ class Simulation:
                          self.bdf)
         g = ionic_current(pr["model"], pr["params"], ustar, Wnew)
         b = self.rhs(Un, Unm1, g, t_next, iapp)
-        Unew, st = pcg(self.A0, b, Un, self.mg, tol, max_it, self.flexible)
+        Unew, st = pcg(self.A0, b, Un, self.mg, tol, max_it, self.flexible, tol_mode)
         return (Unew, Un, Wnew, Wn), st
 
-    def run(self, steps, tol, iapp_fn=None, state=None, record=True):
+    def run(self, steps, tol, iapp_fn=None, state=None, record=True, tol_mode="rel"):
         pr = self.prob
         if state is None:
             state = (pr["U0"].copy(), pr["U0"].copy(), pr["W0"].copy(),
@@ -71,7 +71,7 @@ class Simulation:
             t = (n + 1) * pr["dt"]
             iapp = iapp_fn(t) if iapp_fn is not None else None
             t0 = time.perf_counter()
-            state, st = self.step(state, t, tol, iapp)
+            state, st = self.step(state, t, tol, iapp, tol_mode=tol_mode)
             st["wall"] = time.perf_counter() - t0
             stats.append(st)
             if record:

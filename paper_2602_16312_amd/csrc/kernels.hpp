@@ -241,6 +241,30 @@ __device__ __forceinline__ void wg_sum_store(double v, double* partial) {
     }
 }
 
+// Cell-block Jacobi term of the smoother at the thread's row (i of `cell`):
+// z_i = sum_j (D_K^-1)_ij v_j over the cell's rows, with D_K^-1 symmetric and
+// row-major per cell (the lanes of a cell read consecutive words of column
+// j).  v is the workgroup's row values, staged in LDS here (the matrix-free
+// product passes its free region; the block layouts use their own), so every
+// thread of the workgroup must call this; inactive threads pass v = 0.
+template <typename T, int B, int LY>
+__device__ __forceinline__ T block_jacobi_row(const T* __restrict__ Dinv, T v, int lc, int cell,
+                                              bool active, T* lds_free) {
+    __shared__ T vs_own[LY == LY_MF ? 1 : kWG];
+    T* vs = LY == LY_MF ? lds_free : vs_own;
+    vs[threadIdx.x] = v;
+    __syncthreads();
+    T z = 0;
+    if (active) {
+        const int i = threadIdx.x - lc * B;
+        const T* Dc = Dinv + (size_t)cell * B * B + i;
+        const T* vc = vs + lc * B;
+#pragma unroll
+        for (int j = 0; j < B; ++j) z += Dc[(size_t)j * B] * vc[j];
+    }
+    return z;
+}
+
 // ---------------------------------------------------------------- apply
 // Thread (tile, lc, i) owns row i of cell tile * TC + lc, or, when MAPPED
 // (a tile-ELL level whose tiles group cells of similar neighbour count), of
@@ -269,26 +293,33 @@ __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restri
     if (partial) wg_sum_store(contrib, partial);
 }
 
-// Residual r = rhs - A (va + vb), with optional epilogues: d = dinv * r * c1,
+// Residual r = rhs - A (va + vb), with optional epilogues: d = dinv * r * c1
+// (with bj: d = c1 D_K^-1 r per cell, the cell-block Jacobi term),
 // xout = va + vb, partial of ||r||^2, and restriction partials
 // rp[cell, j] = sum_i P_cell(i, j) r[cell, i] (P in tile-interleaved layout)
 // for the coarse correction.  r may be null when only rp is wanted.
-template <typename T, int B, bool VB, int LY>
+template <typename T, int B, bool VB, int LY, bool BJ = false>
 __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __restrict__ va,
                                                   const T* __restrict__ vb, const T* __restrict__ rhs,
                                                   T* __restrict__ r, T* __restrict__ d, T c1,
                                                   T* __restrict__ xout, double* __restrict__ partial,
                                                   const T* __restrict__ P, T* __restrict__ rp,
-                                                  const int32_t* __restrict__ ptype) {
+                                                  const int32_t* __restrict__ ptype,
+                                                  const T* __restrict__ bj) {
     DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
     double contrib = 0.0;
     T rr = 0;
     T* lds_free = nullptr;
     const T a = row_apply<T, B, VB, LY>(L, tile, lc, cell, active, va, vb, &lds_free);
+    if (active) rr = rhs[t] - a;
+    // the block term stages the workgroup's residuals in LDS (uniform branch)
+    T zb = 0;
+    if constexpr (BJ) {
+        if (d) zb = block_jacobi_row<T, B, LY>(bj, rr, lc, cell, active, lds_free);
+    }
     if (active) {
-        rr = rhs[t] - a;
         if (r) r[t] = rr;
-        if (d) d[t] = L.dinv[t] * rr * c1;
+        if (d) d[t] = BJ ? c1 * zb : L.dinv[t] * rr * c1;
         if (xout) xout[t] = VB ? va[t] + vb[t] : va[t];
         contrib = (double)rr * (double)rr;
     }
@@ -319,22 +350,28 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
 }
 
 // One inner Chebyshev step (gather vector d):
-//   x += d (x = d when assign), r -= A d, dn = cd * d + cr * dinv * r.
+//   x += d (x = d when assign), r -= A d, dn = cd * d + cr * dinv * r
+// (with bj: cr * D_K^-1 r per cell, the cell-block Jacobi term).
 // On the last step of a sweep (last != 0) the sweep's final correction is
 // applied at once: x = (x + d) + dn, and r, dn are not stored (the next
 // sweep starts from the true residual).
-template <typename T, int B, int LY>
+template <typename T, int B, int LY, bool BJ = false>
 __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __restrict__ d,
                                                    T* __restrict__ x, T* __restrict__ r,
                                                    T* __restrict__ dn, T cd, T cr, int assign,
-                                                   int last) {
+                                                   int last, const T* __restrict__ bj) {
     DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
-    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, d, nullptr);
+    T* lds_free = nullptr;
+    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, d, nullptr, BJ ? &lds_free : nullptr);
+    T rr = 0;
+    if (active) rr = r[t] - a;
+    // the block term stages the workgroup's residuals in LDS (all threads)
+    T zb = 0;
+    if constexpr (BJ) zb = block_jacobi_row<T, B, LY>(bj, rr, lc, cell, active, lds_free);
     if (!active) return;
     const T dt = d[t];
     const T x1 = assign ? dt : x[t] + dt;
-    const T rr = r[t] - a;
-    const T dnew = cd * dt + cr * L.dinv[t] * rr;
+    const T dnew = cd * dt + cr * (BJ ? zb : L.dinv[t] * rr);
     if (last) {
         x[t] = x1 + dnew;
     } else {
@@ -348,11 +385,12 @@ __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __re
 // D): y = alpha y + beta D_K^-1 v_K at row (K, i), D_K^-1 symmetric and
 // row-major per cell, so the lanes of a cell read consecutive words of
 // column j; alpha = 0 does not read y.  With x given also x += y (the last
-// Chebyshev step of a sweep).
+// Chebyshev step of a sweep); with vcopy given also vcopy = v (the first
+// sweep from x = 0: r = b, d = c1 D^-1 b in one pass).
 template <typename T, int B>
 __global__ __launch_bounds__(kWG) void k_block_jacobi(int32_t n, const T* __restrict__ Dinv,
                                                       const T* __restrict__ v, T* __restrict__ y, T alpha,
-                                                      T beta, T* __restrict__ x) {
+                                                      T beta, T* __restrict__ x, T* __restrict__ vcopy) {
     constexpr int TC = Tile<T, B>::TC;
     const int lc = threadIdx.x / B;
     const int cell = blockIdx.x * TC + lc;
@@ -367,6 +405,7 @@ __global__ __launch_bounds__(kWG) void k_block_jacobi(int32_t n, const T* __rest
     const T yn = alpha == T(0) ? beta * z : alpha * y[t] + beta * z;
     y[t] = yn;
     if (x) x[t] += yn;
+    if (vcopy) vcopy[t] = vc[i];
 }
 
 // First sweep from x = 0: r = b, d = dinv * b * c1.

@@ -329,16 +329,24 @@ static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, c
 template <typename T, int R = 1>
 static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, const T* vb, const T* rhs,
                             T* r, T* d, T c1, T* xout, double* partial, hipStream_t st,
-                            const T* P = nullptr, T* rp = nullptr, const int32_t* ptype = nullptr) {
+                            const T* P = nullptr, T* rp = nullptr, const int32_t* ptype = nullptr,
+                            const T* bj = nullptr) {
     ProfScope ps(s, PK_RESIDUAL, level_index(s, L), st);
+    if (R != 1 && bj) fail(DGMG_EUNSUPPORTED, "cell-block Jacobi is single-column only");
     DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
-            if (vb) {
+            if (vb && bj) {
+                DISPATCH_B(s->b, klaunch(ps, k_residual<T, BV, true, LYV, true>, tiles_for<T, BV>(L), kWG, st,
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype, bj));
+            } else if (vb) {
                 DISPATCH_B(s->b, klaunch(ps, k_residual<T, BV, true, LYV>, tiles_for<T, BV>(L), kWG, st,
-                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype, bj));
+            } else if (bj) {
+                DISPATCH_B(s->b, klaunch(ps, k_residual<T, BV, false, LYV, true>, tiles_for<T, BV>(L), kWG, st,
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype, bj));
             } else {
                 DISPATCH_B(s->b, klaunch(ps, k_residual<T, BV, false, LYV>, tiles_for<T, BV>(L), kWG, st,
-                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype));
+                                     largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype, bj));
             }
         } else if constexpr (LYV == LY_MF) {
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
@@ -369,13 +377,18 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
 }
 template <typename T, int R = 1>
 static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* r, T* dn, T cd, T cr,
-                        int assign, int last, hipStream_t st) {
+                        int assign, int last, hipStream_t st, const T* bj = nullptr) {
     ProfScope ps(s, PK_CHEB_STEP, level_index(s, L), st);
+    if (R != 1 && bj) fail(DGMG_EUNSUPPORTED, "cell-block Jacobi is single-column only");
     DISPATCH_LY(level_ly(L), {
         if constexpr (R == 1) {
-            DISPATCH_B(s->b, klaunch(ps, k_cheb_step<T, BV, LYV>, tiles_for<T, BV>(L), kWG, st, largs<T>(L), d, x, r,
-                                                                                           dn, cd, cr, assign,
-                                                                                           last));
+            if (bj) {
+                DISPATCH_B(s->b, klaunch(ps, k_cheb_step<T, BV, LYV, true>, tiles_for<T, BV>(L), kWG, st,
+                                         largs<T>(L), d, x, r, dn, cd, cr, assign, last, bj));
+            } else {
+                DISPATCH_B(s->b, klaunch(ps, k_cheb_step<T, BV, LYV>, tiles_for<T, BV>(L), kWG, st, largs<T>(L), d,
+                                         x, r, dn, cd, cr, assign, last, bj));
+            }
         } else if constexpr (LYV == LY_MF) {
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
@@ -424,34 +437,31 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     T *x = (T*)L.vx, *x2 = (T*)L.vx2, *r = (T*)L.vr, *d = (T*)L.vd, *d2 = (T*)L.vd2;
     bool xzero = true, pending = false;
     const T* dinv = largs<T>(L).dinv;
-    // cell-block Jacobi (single column): the fused kernels run with their
-    // Jacobi term off (zero coefficient, no final correction) and
-    // k_block_jacobi then adds beta D^-1 v per cell (and x += d on a sweep's
-    // last step)
-    const bool bj = R == 1 && s->jacobi == DGMG_JACOBI_CELL_BLOCK;
-    auto bjac = [&](const T* v, T* y, T alpha, T beta, T* xo) {
-        if constexpr (R == 1)
-            DISPATCH_B(s->b, k_block_jacobi<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(L.n, BJof<T>(L), v, y,
-                                                                                          alpha, beta, xo));
-    };
-    const T cj = bj ? T(0) : c1;
+    // cell-block Jacobi (single column): the fused kernels apply the cells'
+    // inverse diagonal blocks D_K^-1 in their epilogue instead of 1/diag
+    const T* bjp = (R == 1 && s->jacobi == DGMG_JACOBI_CELL_BLOCK) ? BJof<T>(L) : nullptr;
     auto sweep = [&]() {
         if (xzero && !pending) {
-            if constexpr (R == 1)
-                k_cheb_init0<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, b, dinv, r, d, cj);
-            else
+            if constexpr (R == 1) {
+                if (bjp) {   // r = b and d = c1 D^-1 b in one pass
+                    DISPATCH_B(s->b, k_block_jacobi<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
+                                         L.n, bjp, b, d, T(0), c1, (T*)nullptr, r));
+                } else {
+                    k_cheb_init0<T><<<blocks_for(L.N), kWG, 0, st>>>(L.N, b, dinv, r, d, c1);
+                }
+            } else {
                 k_cheb_init0_m<T, R><<<blocks_for(NR), kWG, 0, st>>>(NR, b, dinv, r, d, c1);
-            if (bj) bjac(r, d, T(0), c1, nullptr);
+            }
         } else if (pending) {
             // r = b - A(x + d), materialise x + d into x2
-            launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, d2, cj, x2, nullptr, st);
-            if (bj) bjac(r, d2, T(0), c1, nullptr);
+            launch_residual<T, R>(s, L, xzero ? d : x, xzero ? nullptr : d, b, r, d2, c1, x2, nullptr, st,
+                                  nullptr, nullptr, nullptr, bjp);
             std::swap(x, x2);
             std::swap(d, d2);
             xzero = false;
         } else {
-            launch_residual<T, R>(s, L, x, (const T*)nullptr, b, r, d, cj, (T*)nullptr, nullptr, st);
-            if (bj) bjac(r, d, T(0), c1, nullptr);
+            launch_residual<T, R>(s, L, x, (const T*)nullptr, b, r, d, c1, (T*)nullptr, nullptr, st, nullptr,
+                                  nullptr, nullptr, bjp);
         }
         double rho = 1.0 / sigma1;
         for (int i = 1; i < s->cheb_k; ++i) {
@@ -460,9 +470,7 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
             // correction x += d (it needs only the row's own new d)
             const int last = i == s->cheb_k - 1;
             const T cr = (T)(2.0 * rn / delta);
-            launch_step<T, R>(s, L, d, x, r, d2, (T)(rn * rho), bj ? T(0) : cr, xzero ? 1 : 0, bj ? 0 : last,
-                              st);
-            if (bj) bjac(r, d2, T(1), cr, last ? x : nullptr);
+            launch_step<T, R>(s, L, d, x, r, d2, (T)(rn * rho), cr, xzero ? 1 : 0, last, st, bjp);
             xzero = false;
             if (!last) std::swap(d, d2);
             rho = rn;
@@ -2023,6 +2031,8 @@ int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t nrhs,
         const int64_t NR = L.N * R;
         T *x = (T*)L.vx, *r = (T*)L.vr, *d = (T*)L.vd, *d2 = (T*)L.vd2, *x2 = (T*)L.vx2;
         const T* bb = (const T*)L.vb;
+        // the kernel the solver runs: with the cells' block inverses when set
+        const T* bjk = (R == 1 && s->jacobi == DGMG_JACOBI_CELL_BLOCK) ? BJof<T>(L) : nullptr;
         // defined inputs
         k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, x, (T)1e-3);
         k_fill<T><<<blocks_for(NR), kWG, 0, st>>>(NR, d, (T)1e-3);
@@ -2030,10 +2040,11 @@ int dgmg_kernel_bench(dgmg_solver* s, int32_t kind, int32_t level, int32_t nrhs,
         HIPCHK(hipEventRecord(a, st));
         for (int k = 0; k < reps; ++k) {
             if (kind == PK_CHEB_STEP) {
-                launch_step<T, R>(s, L, d, x, r, d2, (T)0.5, (T)0.1, 0, 0, st);
+                launch_step<T, R>(s, L, d, x, r, d2, (T)0.5, (T)0.1, 0, 0, st, bjk);
                 std::swap(d, d2);
             } else {
-                launch_residual<T, R>(s, L, x, d, bb ? bb : r, r, d2, (T)0.5, x2, nullptr, st);
+                launch_residual<T, R>(s, L, x, d, bb ? bb : r, r, d2, (T)0.5, x2, nullptr, st, nullptr,
+                                      nullptr, nullptr, bjk);
             }
         }
         HIPCHK(hipEventRecord(b, st));

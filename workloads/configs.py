@@ -89,12 +89,14 @@ CONFIGS = {
                model="fhn", params=[19.5, 0.013, 40.0, 0.1],
                penalty=("paper",), ic="rest", stim=("box", 0.4, 0.6, 2e6, 1e-3),
                tol=1e-14, tol_mode="abs"),
-    # adjoint problem: mesh and physics of c2, 50 steps
+    # adjoint problem: mesh and physics of c2, 50 steps; the 64 sensors lie in
+    # cells whose centroids are 0.08 to 0.16 from the stimulated corner, the
+    # band the excitation front crosses within the 50 steps
     "c5": dict(dim=2, n=256, p=2, jitter=0.2, seed=2602, group=[4, 4],
                sigma=("iso", 1e-3), chi=1.0, Cm=1.0, dt=1e-2, steps=50,
                model="ap", params=[8.0, 0.15, 0.002],
                penalty=("paper", 2.0), ic="corner_disc", stim=None, tol=1e-8,
-               sensors=(64, 2605), target_seed=2606),
+               sensors=(64, 2605, (0.08, 0.16)), target_seed=2606),
 }
 
 
@@ -213,13 +215,28 @@ def make_problem(name, n=None, steps=None, **overrides):
                 params=np.asarray(cfg["params"], dtype=np.float64),
                 node_xyz=nodes)
     if cfg.get("sensors"):
-        ns, seed = cfg["sensors"]
+        ns, seed = cfg["sensors"][:2]
         rng = np.random.default_rng(seed)
-        prob["sensor_cell"] = rng.integers(0, nc, size=ns).astype(np.int64)
-        prob["sensor_ref"] = rng.uniform(0.0, 1.0, size=(ns, dim))
+        if len(cfg["sensors"]) > 2:
+            # distinct cells drawn from a band of centroid distances to the origin
+            lo, hi = cfg["sensors"][2]
+            r = np.linalg.norm(cen, axis=1)
+            pool = np.flatnonzero((r >= lo) & (r <= hi))
+            prob["sensor_cell"] = np.sort(rng.choice(pool, size=min(ns, len(pool)),
+                                                     replace=False)).astype(np.int64)
+        else:
+            prob["sensor_cell"] = rng.integers(0, nc, size=ns).astype(np.int64)
+        prob["sensor_ref"] = rng.uniform(0.0, 1.0, size=(len(prob["sensor_cell"]), dim))
         rng2 = np.random.default_rng(cfg["target_seed"])
         prob["s_true"] = np.exp(np.log(1.3) * rng2.standard_normal(nc))
     return prob
+
+
+def probe_vector(n, seed):
+    """Seeded unit vector of length n (entries uniform in [-1, 1] before
+    normalisation), used to project a solution onto one number."""
+    v = np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+    return v / np.linalg.norm(v)
 
 
 def iapp_nodal(prob, t):
