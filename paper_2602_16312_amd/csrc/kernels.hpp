@@ -97,6 +97,17 @@ constexpr int slot_group() {
     return (48 / B) < 1 ? 1 : ((48 / B) > 5 ? 5 : (48 / B));
 }
 
+// Block sizes whose cells the block layouts keep inside one wave: lane l of
+// wave w holds row l % B of tile cell w (64/B) + l / B, the lanes past
+// (64/B) B stay idle, and the tile keeps its 256/B cells.  A cell's B lanes
+// then share gathered vector values by lane shuffles (ds_bpermute, the LDS
+// crossbar) instead of each loading all B values through the address unit.
+template <int B>
+constexpr bool whole_wave_cells() {
+    return B == 4 || B == 8 || B == 9 || B == 16 || B == 64;
+}
+static_assert(4 * (64 / 9) == 256 / 9 && 4 * (64 / 8) == 256 / 8, "wave-aligned tiles keep 256/B cells");
+
 // (A v) at row (tile*TC + lc, i) of the tile's thread (lc, i), v = va (+ vb
 // when VB).  Loads of a group of G slots -- block values and the gathered
 // vector segments -- are all issued before the group is accumulated; slots
@@ -115,12 +126,32 @@ __device__ __forceinline__ void gather_group(const T* __restrict__ va, const T* 
     }
 }
 
+// The lane's own element of cell nb's segment: (va + vb)[nb B + i].
 template <typename T, int B, bool VB>
-__device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int lc,
+__device__ __forceinline__ T gather_own(const T* __restrict__ va, const T* __restrict__ vb, int nb,
+                                        int i) {
+    const size_t k = (size_t)nb * B + i;
+    if constexpr (VB)
+        return va[k] + vb[k];
+    else
+        return va[k];
+}
+
+// v[j] = the element of lane base + j (whole-wave cells: the cell's B lanes
+// hold one segment between them).
+template <typename T, int B>
+__device__ __forceinline__ void share_segment(T x, int base, T* v) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[j] = __shfl(x, base + j, 64);
+}
+
+template <typename T, int B, bool VB, bool WW>
+__device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int lc, int ri, int i,
                                            const T* __restrict__ va, const T* __restrict__ vb) {
     constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, G = slot_group<B>();
     const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;
-    const T* __restrict__ A = L.vals + (size_t)s0 * B * TR + threadIdx.x;
+    const int base = ((int)threadIdx.x & 63) - i;   // lane of the cell's row 0 (whole-wave cells)
+    const T* __restrict__ A = L.vals + (size_t)s0 * B * TR + ri;
     const int32_t* __restrict__ nbp = L.snb + (size_t)s0 * TC + lc;
     T acc = 0;
     for (int g = 0; g < ns; g += G) {
@@ -134,8 +165,16 @@ __device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int 
 #pragma unroll
             for (int j = 0; j < B; ++j) a[q][j] = As[(size_t)j * TR];
         }
+        if constexpr (WW) {
+            T xq[G];
 #pragma unroll
-        for (int q = 0; q < G; ++q) gather_group<T, B, VB>(va, vb, nbq[q], v[q]);
+            for (int q = 0; q < G; ++q) xq[q] = gather_own<T, B, VB>(va, vb, nbq[q], i);
+#pragma unroll
+            for (int q = 0; q < G; ++q) share_segment<T, B>(xq[q], base, v[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gather_group<T, B, VB>(va, vb, nbq[q], v[q]);
+        }
 #pragma unroll
         for (int q = 0; q < G; ++q)
             if (g + q < ns) {
@@ -149,13 +188,13 @@ __device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int 
 // The same row product on the axis-ELL layout: the 1 + d own slots (cell
 // block, upper faces) in groups as above, then each lower face as the
 // transposed column of the neighbour's stored block.
-template <typename T, int B, bool VB>
-__device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int lc, int cell,
+template <typename T, int B, bool VB, bool WW>
+__device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int cell, int ri, int i,
                                           const T* __restrict__ va, const T* __restrict__ vb) {
     constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>(), NS = 1 + D;
     constexpr int G = slot_group<B>() < NS ? slot_group<B>() : NS;
-    const int i = threadIdx.x - lc * B;
-    const T* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + threadIdx.x;
+    const int base = ((int)threadIdx.x & 63) - i;   // lane of the cell's row 0 (whole-wave cells)
+    const T* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + ri;
     T acc = 0;
 #pragma unroll
     for (int g = 0; g < NS; g += G) {
@@ -172,8 +211,16 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int l
 #pragma unroll
             for (int j = 0; j < B; ++j) a[q][j] = As[(size_t)j * TR];
         }
+        if constexpr (WW) {
+            T xq[G];
 #pragma unroll
-        for (int q = 0; q < G; ++q) gather_group<T, B, VB>(va, vb, nbq[q], v[q]);
+            for (int q = 0; q < G; ++q) xq[q] = gather_own<T, B, VB>(va, vb, nbq[q], i);
+#pragma unroll
+            for (int q = 0; q < G; ++q) share_segment<T, B>(xq[q], base, v[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gather_group<T, B, VB>(va, vb, nbq[q], v[q]);
+        }
 #pragma unroll
         for (int q = 0; q < G; ++q)
             if (g + q < NS) {
@@ -190,7 +237,10 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int l
             T a[B], v[B];
 #pragma unroll
             for (int r = 0; r < B; ++r) a[r] = At[r];
-            gather_group<T, B, VB>(va, vb, c0, v);
+            if constexpr (WW)
+                share_segment<T, B>(gather_own<T, B, VB>(va, vb, c0, i), base, v);
+            else
+                gather_group<T, B, VB>(va, vb, c0, v);
 #pragma unroll
             for (int r = 0; r < B; ++r) acc += a[r] * v[r];
         }
@@ -211,18 +261,21 @@ enum { LY_TILE = 0, LY_AXIS = 1, LY_MF = 2 };
 // threads are not used.  When lds_free is given, the matrix-free product
 // stores there an LDS region of at least kWG values that no thread reads
 // any more (usable by the caller's epilogue without a further barrier).
+// ri is the thread's row within the tile (lc B + i), i its row of the cell.
 template <typename T, int B, bool VB, int LY>
-__device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int tile, int lc, int cell, bool active,
-                                       const T* __restrict__ va, const T* __restrict__ vb,
+__device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int tile, int lc, int cell, int ri, int i,
+                                       bool active, const T* __restrict__ va, const T* __restrict__ vb,
                                        T** lds_free = nullptr) {
     if constexpr (LY == LY_MF) {
         return mf_row_apply<T, B, VB>(L, lc, cell, active, va, vb, lds_free);
     } else {
+        // a cell's lanes are all active or all inactive, so the shuffles of
+        // an active cell read active lanes only
         if (!active) return T(0);
         if constexpr (LY == LY_AXIS)
-            return ax_row_apply<T, B, VB>(L, tile, lc, cell, va, vb);
+            return ax_row_apply<T, B, VB, whole_wave_cells<B>()>(L, tile, cell, ri, i, va, vb);
         else
-            return ell_row_apply<T, B, VB>(L, tile, lc, va, vb);
+            return ell_row_apply<T, B, VB, whole_wave_cells<B>()>(L, tile, lc, ri, i, va, vb);
     }
 }
 
@@ -248,15 +301,14 @@ __device__ __forceinline__ void wg_sum_store(double v, double* partial) {
 // product passes its free region; the block layouts use their own), so every
 // thread of the workgroup must call this; inactive threads pass v = 0.
 template <typename T, int B, int LY>
-__device__ __forceinline__ T block_jacobi_row(const T* __restrict__ Dinv, T v, int lc, int cell,
-                                              bool active, T* lds_free) {
+__device__ __forceinline__ T block_jacobi_row(const T* __restrict__ Dinv, T v, int lc, int cell, int ri,
+                                              int i, bool active, T* lds_free) {
     __shared__ T vs_own[LY == LY_MF ? 1 : kWG];
     T* vs = LY == LY_MF ? lds_free : vs_own;
-    vs[threadIdx.x] = v;
+    if (ri < Tile<T, B>::TR) vs[ri] = v;
     __syncthreads();
     T z = 0;
     if (active) {
-        const int i = threadIdx.x - lc * B;
         const T* Dc = Dinv + (size_t)cell * B * B + i;
         const T* vc = vs + lc * B;
 #pragma unroll
@@ -269,23 +321,33 @@ __device__ __forceinline__ T block_jacobi_row(const T* __restrict__ Dinv, T v, i
 // Thread (tile, lc, i) owns row i of cell tile * TC + lc, or, when MAPPED
 // (a tile-ELL level whose tiles group cells of similar neighbour count), of
 // cell cmap[tile * TC + lc]; vectors stay in cell order either way.
-#define DGMG_TILE_THREAD_M(T, B, MAPPED)                                          \
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);                           \
-    const int lc = threadIdx.x / B;                                             \
-    const int pos = tile * Tile<T, B>::TC + lc;                                 \
-    const bool active = lc < Tile<T, B>::TC && pos < L.n;                       \
-    const int cell = ((MAPPED) && L.cmap && active) ? L.cmap[pos] : pos;        \
-    const int t = cell * B + (threadIdx.x - lc * B);
-#define DGMG_TILE_THREAD(T, B) DGMG_TILE_THREAD_M(T, B, false)
+// With WW (whole-wave cells, block layouts) lane l of wave w holds row
+// l % B of tile cell w (64/B) + l / B and the lanes past (64/B) B are idle
+// (lc = TC); otherwise thread x holds row x % B of tile cell x / B.  ri is
+// the thread's row within the tile (>= TR for idle lanes), ti its row of the
+// cell.
+#define DGMG_TILE_THREAD_M(T, B, MAPPED, WW)                                                   \
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);                                          \
+    const int lane_ = (int)threadIdx.x & 63, lcw_ = lane_ / B;                                 \
+    const int lc = (WW) ? (lcw_ < 64 / B ? ((int)threadIdx.x >> 6) * (64 / B) + lcw_ : Tile<T, B>::TC) \
+                        : (int)threadIdx.x / B;                                                \
+    const int ti = (WW) ? lane_ - lcw_ * B : (int)threadIdx.x - lc * B;                        \
+    const int ri = lc * B + ti;                                                                \
+    const int pos = tile * Tile<T, B>::TC + lc;                                                \
+    const bool active = lc < Tile<T, B>::TC && pos < L.n;                                      \
+    const int cell = ((MAPPED) && L.cmap && active) ? L.cmap[pos] : pos;                       \
+    const int t = cell * B + ti;
+#define DGMG_TILE_WW(B, LY) (whole_wave_cells<B>() && (LY) != LY_MF)
+#define DGMG_TILE_THREAD(T, B) DGMG_TILE_THREAD_M(T, B, false, false)
 
 // y = A va; optional partial of dot(w, y).
 template <typename T, int B, int LY>
 __global__ __launch_bounds__(kWG) void k_apply(LevelArgs<T> L, const T* __restrict__ va,
                                                T* __restrict__ y,
                                                const T* __restrict__ w, double* __restrict__ partial) {
-    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
+    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE, DGMG_TILE_WW(B, LY))
     double contrib = 0.0;
-    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, va, nullptr);
+    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, ri, ti, active, va, nullptr);
     if (active) {
         y[t] = a;
         if (w) contrib = (double)w[t] * (double)a;
@@ -306,16 +368,16 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
                                                   const T* __restrict__ P, T* __restrict__ rp,
                                                   const int32_t* __restrict__ ptype,
                                                   const T* __restrict__ bj) {
-    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
+    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE, DGMG_TILE_WW(B, LY))
     double contrib = 0.0;
     T rr = 0;
     T* lds_free = nullptr;
-    const T a = row_apply<T, B, VB, LY>(L, tile, lc, cell, active, va, vb, &lds_free);
+    const T a = row_apply<T, B, VB, LY>(L, tile, lc, cell, ri, ti, active, va, vb, &lds_free);
     if (active) rr = rhs[t] - a;
     // the block term stages the workgroup's residuals in LDS (uniform branch)
     T zb = 0;
     if constexpr (BJ) {
-        if (d) zb = block_jacobi_row<T, B, LY>(bj, rr, lc, cell, active, lds_free);
+        if (d) zb = block_jacobi_row<T, B, LY>(bj, rr, lc, cell, ri, ti, active, lds_free);
     }
     if (active) {
         if (r) r[t] = rr;
@@ -328,14 +390,14 @@ __global__ __launch_bounds__(kWG) void k_residual(LevelArgs<T> L, const T* __res
         // occupancy is LDS-bound); the block layouts use their own
         __shared__ T rs_own[LY == LY_MF ? 1 : kWG];
         T* rs = LY == LY_MF ? lds_free : rs_own;
-        rs[threadIdx.x] = rr;
+        if (ri < Tile<T, B>::TR) rs[ri] = rr;
         __syncthreads();
         if (active) {
             // thread (lc, j): column j of P_cell, contiguous in i (tile
             // layout, at the cell's own tile position) or strided by B
             // (row-major block of the cell's type)
             constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
-            const int j = threadIdx.x - lc * B;
+            const int j = ti;
             const int ht = cell / TC, hl = cell - ht * TC;
             const T* Pc = ptype ? P + (size_t)ptype[cell] * B * B + j : P + ((size_t)ht * B + j) * TR + hl * B;
             const int ks = ptype ? B : 1;
@@ -360,14 +422,15 @@ __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __re
                                                    T* __restrict__ x, T* __restrict__ r,
                                                    T* __restrict__ dn, T cd, T cr, int assign,
                                                    int last, const T* __restrict__ bj) {
-    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE)
+    DGMG_TILE_THREAD_M(T, B, LY == LY_TILE, DGMG_TILE_WW(B, LY))
     T* lds_free = nullptr;
-    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, active, d, nullptr, BJ ? &lds_free : nullptr);
+    const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, ri, ti, active, d, nullptr,
+                                           BJ ? &lds_free : nullptr);
     T rr = 0;
     if (active) rr = r[t] - a;
     // the block term stages the workgroup's residuals in LDS (all threads)
     T zb = 0;
-    if constexpr (BJ) zb = block_jacobi_row<T, B, LY>(bj, rr, lc, cell, active, lds_free);
+    if constexpr (BJ) zb = block_jacobi_row<T, B, LY>(bj, rr, lc, cell, ri, ti, active, lds_free);
     if (!active) return;
     const T dt = d[t];
     const T x1 = assign ? dt : x[t] + dt;
