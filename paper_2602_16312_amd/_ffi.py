@@ -3,7 +3,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdgmg.so")
+# DGMG_LIB selects another build of the same library (the host-sanitizer build)
+LIB_PATH = os.environ.get("DGMG_LIB") or os.path.join(HERE, "libdgmg.so")
 
 MAX_LEVELS = 8
 MULTI_RHS = 8          # DGMG_MULTI_RHS

@@ -27,29 +27,44 @@ def _run(cmd):
     return r
 
 
-def build(verbose=False):
-    objdir = os.path.join(HERE, "_build")
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host code only
+# (each flag behind -Xarch_host: no device code is instrumented)
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all", "-g"]
+
+
+def build(verbose=False, sanitize=False):
+    """Compiles libdgmg.so; sanitize=True builds _build_san/libdgmg_san.so
+    with the host code under ASan + UBSan instead (load it with
+    DGMG_LIB=<path> and the clang ASan runtime preloaded)."""
+    objdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
+    extra = SANITIZE if sanitize else []
     jobs = []
     for src in HOST_SOURCES:
         o = os.path.join(objdir, src + ".o")
-        jobs.append(([HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", o], o))
+        jobs.append(([HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", o], o))
     for src in HIP_SOURCES:
         o = os.path.join(objdir, src + ".o")
-        jobs.append(([HIPCC, "-x", "hip"] + DEVICE_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", o],
-                     o))
+        jobs.append(([HIPCC, "-x", "hip"] + DEVICE_FLAGS + COMMON + extra +
+                     ["-c", os.path.join(CSRC, src), "-o", o], o))
     # the translation units are independent: compile them concurrently
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         list(ex.map(lambda j: _run(j[0]), jobs))
     objs = [o for _, o in jobs]
-    tmp = LIB + ".tmp"
-    _run([HIPCC] + DEVICE_FLAGS + ["-shared", "-fopenmp", "-o", tmp] + objs +
+    out = os.path.join(objdir, "libdgmg_san.so") if sanitize else LIB
+    tmp = out + ".tmp"
+    link_extra = (["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                   "-Xarch_host", "-shared-libsan"] if sanitize else [])
+    _run([HIPCC] + DEVICE_FLAGS + link_extra + ["-shared", "-fopenmp", "-o", tmp] + objs +
          ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"])
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+    if sanitize:
+        return out
     if verbose:
         print("built", LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv)
