@@ -485,11 +485,15 @@ __global__ __launch_bounds__(kWG) void k_cheb_init0(int64_t N, const T* __restri
 
 // ----------------------------------------------------------- transfers
 // Restriction, second half: rc[K, j] = sum over children e of rp[e, j]
-// (child ids of a group are loaded before their values).
+// (child ids of a group are loaded before their values).  With r given it
+// also starts the coarse level's first smoothing sweep from x = 0:
+// r = rc, d = cj dinv rc (point Jacobi, cj = 1 / theta of that level).
 template <typename T, int B>
 __global__ __launch_bounds__(kWG) void k_restrict_sum(int32_t nC, const int32_t* __restrict__ cptr,
                                                       const int32_t* __restrict__ clist,
-                                                      const T* __restrict__ rp, T* __restrict__ rc) {
+                                                      const T* __restrict__ rp, T* __restrict__ rc,
+                                                      const T* __restrict__ dinv, T* __restrict__ r,
+                                                      T* __restrict__ d, T cj) {
     constexpr int G = 8;
     const int t = blockIdx.x * kWG + threadIdx.x;
     const int K = t / B, j = t - K * B;
@@ -508,6 +512,10 @@ __global__ __launch_bounds__(kWG) void k_restrict_sum(int32_t nC, const int32_t*
             if (c + q < c1) acc += v[q];
     }
     rc[t] = acc;
+    if (r) {
+        r[t] = acc;
+        d[t] = dinv[t] * acc * cj;
+    }
 }
 
 // Prolongation with correction: x[e, i] += sum_j P_e(i, j) (xc + dc)[parent(e), j]
@@ -645,13 +653,18 @@ __global__ __launch_bounds__(kWG) void k_finalize(int32_t np, const double* __re
 }
 
 // x += alpha p; r -= alpha q with alpha = sc[1] / sc[2]; partial ||r||^2.
-// When rb is set it also receives the new residual in FP32 (the next
-// V-cycle's right-hand side in mixed precision).
+// The next V-cycle's level 0 in its precision T: when rb is set it receives
+// the new residual (the right-hand side in mixed precision; in FP64 the
+// V-cycle reads r itself), and when r0 is set the first smoothing sweep from
+// x = 0 starts here: r0 = r, d0 = c1 dinv0 r (point Jacobi).
+template <typename T>
 __global__ __launch_bounds__(kWG) void k_update_xr(int64_t N, const double* __restrict__ sc,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ q,
                                                    double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ partial, float* __restrict__ rb) {
+                                                   double* __restrict__ partial, T* __restrict__ rb,
+                                                   T* __restrict__ r0, T* __restrict__ d0,
+                                                   const T* __restrict__ dinv0, T c1) {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
     const double alpha = sc[1] / sc[2];
     double v = 0.0;
@@ -659,7 +672,12 @@ __global__ __launch_bounds__(kWG) void k_update_xr(int64_t N, const double* __re
         x[t] += alpha * p[t];
         const double rn = r[t] - alpha * q[t];
         r[t] = rn;
-        if (rb) rb[t] = (float)rn;
+        const T rt = (T)rn;
+        if (rb) rb[t] = rt;
+        if (r0) {
+            r0[t] = rt;
+            d0[t] = dinv0[t] * rt * c1;
+        }
         v = rn * rn;
     }
     wg_sum_store(v, partial);

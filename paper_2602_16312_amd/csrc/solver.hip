@@ -420,8 +420,11 @@ static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
 }
 
 // One V-cycle from level l on R columns; the result is x + d (d may be null).
+// init_done: the producer of the level's right-hand side already started the
+// first smoothing sweep from x = 0 (r = b, d = c1 dinv b in the level's r
+// and d buffers), so that sweep skips its init kernel.
 template <typename T, int R = 1>
-static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
+static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres, bool init_done = false) {
     DevLevel& L = s->lv[l];
     T* b = (T*)L.vb;
     if (l == s->L - 1) {
@@ -441,7 +444,9 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
     // inverse diagonal blocks D_K^-1 in their epilogue instead of 1/diag
     const T* bjp = (R == 1 && s->jacobi == DGMG_JACOBI_CELL_BLOCK) ? BJof<T>(L) : nullptr;
     auto sweep = [&]() {
-        if (xzero && !pending) {
+        if (xzero && !pending && init_done) {
+            init_done = false;   // r and d were written by the right-hand side's producer
+        } else if (xzero && !pending) {
             if constexpr (R == 1) {
                 if (bjp) {   // r = b and d = c1 D^-1 b in one pass
                     DISPATCH_B(s->b, k_block_jacobi<T, BV><<<tiles_for<T, BV>(L), kWG, 0, st>>>(
@@ -499,18 +504,23 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
         launch_residual<T, R>(s, L, x, (const T*)nullptr, b, (T*)nullptr, (T*)nullptr, c1, (T*)nullptr,
                               nullptr, st, Pof<T>(L), rp, L.ptype);
     }
+    // the coarse level's first sweep (point Jacobi, single column) starts in
+    // the restriction kernel
+    const bool init_c = R == 1 && l + 1 < s->L - 1 && s->cheb_s > 0 && s->jacobi != DGMG_JACOBI_CELL_BLOCK;
     {
     ProfScope ps(s, PK_RESTRICT, l, st);
     if constexpr (R == 1) {
+        const T c1c = (T)(1.0 / (0.5 * (C.lam_hi + C.lam_lo)));
         DISPATCH_B(s->b, klaunch(ps, k_restrict_sum<T, BV>, blocks_for(C.N), kWG, st, C.n, C.child_ptr, C.child_list,
-                                                                                 rp, (T*)C.vb));
+                                 rp, (T*)C.vb, largs<T>(C).dinv, init_c ? (T*)C.vr : (T*)nullptr,
+                                 init_c ? (T*)C.vd : (T*)nullptr, c1c));
     } else {
         DISPATCH_B(s->b, klaunch(ps, k_restrict_sum_m<T, BV, R>, blocks_for(C.N * R), kWG, st,
                              C.n, C.child_ptr, C.child_list, rp, (T*)C.vb));
     }
     }
     T *xc, *dc;
-    vcycle<T, R>(s, l + 1, st, &xc, &dc);
+    vcycle<T, R>(s, l + 1, st, &xc, &dc, init_c);
     {
     ProfScope ps(s, PK_PROLONG, l, st);
     if constexpr (R == 1) {
@@ -537,13 +547,13 @@ static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres) {
 // cast also write the partials of (r, z).
 template <int R = 1>
 static void apply_vcycle(dgmg_solver* s, const double* r, double* z, hipStream_t st, bool rb_ready = false,
-                         double* rz_partial = nullptr) {
+                         double* rz_partial = nullptr, bool init_done = false) {
     DevLevel& L0 = s->lv[0];
     const int64_t NR = s->N * R;
     if (s->prec == DGMG_PREC_FP64) {
         L0.vb = (void*)r;
         double *x, *d;
-        vcycle<double, R>(s, 0, st, &x, &d);
+        vcycle<double, R>(s, 0, st, &x, &d, R == 1 && init_done);
         if (R == 1 && rz_partial)
             k_cast_dot<double><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z, r, rz_partial);
         else
@@ -552,7 +562,7 @@ static void apply_vcycle(dgmg_solver* s, const double* r, double* z, hipStream_t
         if (!(R == 1 && rb_ready))
             k_cast<double, float><<<blocks_for(NR), kWG, 0, st>>>(NR, r, nullptr, (float*)L0.vb);
         float *x, *d;
-        vcycle<float, R>(s, 0, st, &x, &d);
+        vcycle<float, R>(s, 0, st, &x, &d, R == 1 && init_done);
         if (R == 1 && rz_partial)
             k_cast_dot<float><<<blocks_for(NR), kWG, 0, st>>>(NR, x, d, z, r, rz_partial);
         else
@@ -613,12 +623,22 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
     k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 1, 0);
     k_update_p<<<nb, kWG, 0, st>>>(N, sc, s->z, s->pv, 1);
     int its = 0;
-    // mixed precision: the update also writes the FP32 right-hand side of the next V-cycle
+    // mixed precision: the update also writes the FP32 right-hand side of the next V-cycle;
+    // with point Jacobi it also starts that V-cycle's first level-0 sweep (r, d)
     float* rb = s->prec == DGMG_PREC_MIXED ? (float*)L0.vb : nullptr;
+    const bool init0 = s->L > 1 && s->cheb_s > 0 && s->jacobi != DGMG_JACOBI_CELL_BLOCK;
+    const double c1_0 = 1.0 / (0.5 * (L0.lam_hi + L0.lam_lo));
     while (its < o.max_it) {
         launch_apply<double>(s, L0, s->pv, s->q, s->pv, partial, st);
         k_finalize<<<1, kWG, 0, st>>>(nt, partial, sc, 2, 0);
-        k_update_xr<<<nb, kWG, 0, st>>>(N, sc, s->pv, s->q, x, s->r, partial, rb);
+        if (s->prec == DGMG_PREC_MIXED)
+            k_update_xr<float><<<nb, kWG, 0, st>>>(N, sc, s->pv, s->q, x, s->r, partial, rb,
+                                                   init0 ? (float*)L0.vr : nullptr, init0 ? (float*)L0.vd : nullptr,
+                                                   L0.dinv32, (float)c1_0);
+        else
+            k_update_xr<double><<<nb, kWG, 0, st>>>(N, sc, s->pv, s->q, x, s->r, partial, (double*)nullptr,
+                                                    init0 ? (double*)L0.vr : nullptr,
+                                                    init0 ? (double*)L0.vd : nullptr, L0.dinv64, c1_0);
         k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 0, 0);
         read_scalars(s, st, 1, sc);
         ++its;
@@ -637,13 +657,13 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
         }
         if (o.flexible) {
             std::swap(s->z, s->zold);
-            apply_vcycle(s, s->r, s->z, st, true);
+            apply_vcycle(s, s->r, s->z, st, true, nullptr, init0);
             k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->zold, partial);
             k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 5, 0);
             k_dot<<<nb, kWG, 0, st>>>(N, s->r, s->z, partial);
         } else {
             // z = V(r) with the partials of (r, z) from the exit cast
-            apply_vcycle(s, s->r, s->z, st, true, partial);
+            apply_vcycle(s, s->r, s->z, st, true, partial, init0);
         }
         k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 3, o.flexible ? 2 : 1);
         k_update_p<<<nb, kWG, 0, st>>>(N, sc, s->z, s->pv, 0);
