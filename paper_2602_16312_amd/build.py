@@ -43,7 +43,8 @@ def build(verbose=False, sanitize=False):
     jobs = []
     for src in HOST_SOURCES:
         o = os.path.join(objdir, src + ".o")
-        jobs.append(([HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", o], o))
+        # plain C++ (hipcc would otherwise compile .cpp files as HIP for a default target)
+        jobs.append(([HIPCC, "-x", "c++"] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", o], o))
     for src in HIP_SOURCES:
         o = os.path.join(objdir, src + ".o")
         jobs.append(([HIPCC, "-x", "hip"] + DEVICE_FLAGS + COMMON + extra +
