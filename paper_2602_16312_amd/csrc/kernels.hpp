@@ -616,8 +616,11 @@ __global__ __launch_bounds__(kWG) void k_dot(int64_t N, const double* __restrict
 // Final reduction of partials into sc[slot]; mode 1 also forms
 // beta = value / sc[1] into sc[4] and moves value into sc[1] (gamma update);
 // mode 2 (flexible) uses sc[5] = (r_new, z_old): beta = (value - sc[5]) / sc[1].
+// With mirror (mapped pinned host memory) the 8 slots are also written there
+// for the host's stopping test, instead of a separate device-to-host copy.
 __global__ __launch_bounds__(kWG) void k_finalize(int32_t np, const double* __restrict__ partial,
-                                                  double* __restrict__ sc, int slot, int mode) {
+                                                  double* __restrict__ sc, int slot, int mode,
+                                                  double* __restrict__ mirror = nullptr) {
     __shared__ double red[kWG];
     // eight independent running sums keep eight loads in flight per thread
     constexpr int U = 8;
@@ -648,6 +651,11 @@ __global__ __launch_bounds__(kWG) void k_finalize(int32_t np, const double* __re
             sc[4] = beta;
             sc[slot] = v;
             sc[1] = v;
+        }
+        if (mirror) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) mirror[k] = sc[k];
+            __threadfence_system();
         }
     }
 }

@@ -157,6 +157,7 @@ struct dgmg_solver {
     double* partial = nullptr;
     double* sc = nullptr;
     double* sc_host = nullptr;
+    double* sc_host_dev = nullptr;   // device address of the pinned sc_host (mapped)
     double* scratch = nullptr;     // this device's static PCG scratch (dgmg_pcg_solve_noalloc)
     int32_t* act = nullptr;        // per-column active mask of multi-column PCG
     int32_t* act_host = nullptr;   // pinned staging of that mask
@@ -576,6 +577,12 @@ static double read_scalars(dgmg_solver* s, hipStream_t st, int R = 1, const doub
     HIPCHK(hipStreamSynchronize(st));
     return s->sc_host[0];
 }
+// The last finalize kernel before this already wrote the 8 scalars into the
+// mapped pinned host buffer: wait for it.
+static double wait_scalars(dgmg_solver* s, hipStream_t st) {
+    HIPCHK(hipStreamSynchronize(st));
+    return s->sc_host[0];
+}
 
 // Names the failed CG quantity: (p, A p) <= 0 means A_0 is not positive
 // definite along p; (r, z) <= 0 means the V-cycle is not.
@@ -599,13 +606,14 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
     const unsigned nt = level_tiles<double>(s, L0);   // partials of the block kernels
     // r = b - A x, ||r||^2
     launch_residual<double>(s, L0, x, nullptr, b, s->r, nullptr, 1.0, nullptr, partial, st);
-    k_finalize<<<1, kWG, 0, st>>>(nt, partial, sc, 0, 0);
+    const bool relb = o.tol_mode == DGMG_TOL_REL_B;
+    k_finalize<<<1, kWG, 0, st>>>(nt, partial, sc, 0, 0, relb ? nullptr : s->sc_host_dev);
     double bnorm = 0.0;
-    if (o.tol_mode == DGMG_TOL_REL_B) {
+    if (relb) {
         k_dot<<<nb, kWG, 0, st>>>(N, b, b, partial);
-        k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 6, 0);
+        k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 6, 0, s->sc_host_dev);
     }
-    read_scalars(s, st, 1, sc);
+    wait_scalars(s, st);
     const double r0 = std::sqrt(s->sc_host[0]);
     if (o.tol_mode == DGMG_TOL_REL_B) bnorm = std::sqrt(s->sc_host[6]);
     if (!std::isfinite(r0)) fail(DGMG_ENAN, "non-finite initial residual");
@@ -639,8 +647,8 @@ static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& 
             k_update_xr<double><<<nb, kWG, 0, st>>>(N, sc, s->pv, s->q, x, s->r, partial, (double*)nullptr,
                                                     init0 ? (double*)L0.vr : nullptr,
                                                     init0 ? (double*)L0.vd : nullptr, L0.dinv64, c1_0);
-        k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 0, 0);
-        read_scalars(s, st, 1, sc);
+        k_finalize<<<1, kWG, 0, st>>>(nb, partial, sc, 0, 0, s->sc_host_dev);
+        wait_scalars(s, st);
         ++its;
         const double gam = s->sc_host[1], pq = s->sc_host[2];
         const double rn = std::sqrt(s->sc_host[0]);
@@ -1696,7 +1704,8 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         s->scratch = scratch_address();
         s->sc = s->dalloc<double>(8 * R);
         HIPCHK(hipMemset(s->sc, 0, 8 * R * sizeof(double)));
-        HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * R * sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&s->sc_host, 8 * R * sizeof(double), hipHostMallocMapped));
+        HIPCHK(hipHostGetDevicePointer((void**)&s->sc_host_dev, s->sc_host, 0));
         s->act = s->dalloc<int32_t>(R);
         HIPCHK(hipHostMalloc((void**)&s->act_host, R * sizeof(int32_t), hipHostMallocDefault));
         s->mass = s->upload(to_colmajor<double>(s->mass_h, s->b));
