@@ -289,30 +289,61 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __
 // (acc[0..7] = the row's 8 columns).  On the axis-ELL layout the lower faces
 // contribute the transposed stored block (A operand = column of the
 // neighbour's block, zero where the cell has no lower neighbour).
+//
+// The B operands of a lane are 16 values at a stride of 4 floats inside the
+// neighbour's 8x8 segment (256 contiguous bytes).  Gathering them directly
+// costs 16 vector-memory instructions per neighbour, each touching 8 cache
+// lines, which saturates the texture-address unit.  Instead the 8 lanes of
+// a cell read the segment with two 16-byte loads each into a wave-private
+// LDS buffer and every lane reads its 16 operands back from there (8
+// two-address LDS reads).  Only lanes of one wave exchange data through the
+// buffer, and LDS executes a wave's instructions in issue order, so a
+// wave-level compiler fence is all the ordering needed.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool AX, bool VB>
 __device__ __forceinline__ void mfma8_tile_product(const LevelArgs<float>& L, int tile,
                                                    const float* __restrict__ va,
                                                    const float* __restrict__ vb, float* acc) {
     constexpr int B = 8, R = 8, TC = Tile<float, 8>::TC, TR = Tile<float, 8>::TR;
+    // cell stride in the staging buffer: 64 floats + 4 of padding, so that
+    // the 8 cells' reads at one offset land in distinct banks
+    constexpr int XS = 68;
+    __shared__ __align__(16) float xstage[(kWG / 64) * 8 * XS];
     const int lane = threadIdx.x & 63;
     const int lc = threadIdx.x / B;
     const int row = threadIdx.x - lc * B;
     const int cell0 = tile * TC;
     const int mycell = min(cell0 + lc, L.n - 1);    // padding lanes reuse a valid cell
     const int jj = lane & 3;                        // B operand / result column in block
+    const int g = lane >> 3, q8 = lane & 7;         // the lane's cell in the wave, its 16-byte chunk
+    float* xw = xstage + (threadIdx.x >> 6) * 8 * XS + g * XS;
     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    auto mma = [&](const float* a, int nb) {
-        const float* xv = va + (size_t)nb * B * R;
-        const float* yv = VB ? vb + (size_t)nb * B * R : nullptr;
+    // the lane's two 16-byte chunks of the neighbour segment (va + vb)
+    auto load_seg = [&](int nb, v4f& u0, v4f& u1) {
+        const v4f* xv = reinterpret_cast<const v4f*>(va + (size_t)nb * B * R) + q8;
+        u0 = xv[0];
+        u1 = xv[8];
+        if constexpr (VB) {
+            const v4f* yv = reinterpret_cast<const v4f*>(vb + (size_t)nb * B * R) + q8;
+            u0 += yv[0];
+            u1 += yv[8];
+        }
+    };
+    auto mma_seg = [&](const float* a, const v4f& u0, const v4f& u1) {
+        wave_lds_fence();   // the previous neighbour's reads stay before these writes
+        *reinterpret_cast<v4f*>(xw + 4 * q8) = u0;
+        *reinterpret_cast<v4f*>(xw + 32 + 4 * q8) = u1;
+        wave_lds_fence();
         float b0[B], b1[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-            b0[j] = xv[j * R + jj];
-            b1[j] = xv[j * R + 4 + jj];
-            if constexpr (VB) {
-                b0[j] += yv[j * R + jj];
-                b1[j] += yv[j * R + 4 + jj];
-            }
+            b0[j] = xw[j * R + jj];
+            b1[j] = xw[j * R + 4 + jj];
         }
 #pragma unroll
         for (int j = 0; j < B; ++j) {
@@ -320,25 +351,57 @@ __device__ __forceinline__ void mfma8_tile_product(const LevelArgs<float>& L, in
             acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[j], b1[j], acc1, 0, 0, 0);
         }
     };
+    auto mma = [&](const float* a, int nb) {
+        v4f u0, u1;
+        load_seg(nb, u0, u1);
+        mma_seg(a, u0, u1);
+    };
     if constexpr (AX) {
+        // 7 neighbours: self and the three upper faces (stored blocks), the
+        // three lower faces (transposed blocks of the lower neighbour).
+        // Without vb all 7 segments are requested at the start: a wave then
+        // touches each cache line within one memory round trip instead of
+        // over its whole lifetime, so the waves of adjacent tiles running at
+        // the same time meet their shared lines in L2 before eviction.
         constexpr int NS = 4;
+        int nbs[7], c0s[3];
+        nbs[0] = mycell;
+#pragma unroll
+        for (int s = 1; s < NS; ++s) nbs[s] = L.up[(size_t)(s - 1) * L.n + mycell];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            c0s[ax] = L.lo[(size_t)ax * L.n + mycell];
+            nbs[NS + ax] = c0s[ax] >= 0 ? c0s[ax] : mycell;
+        }
+        v4f u[7][2];
+        if constexpr (!VB) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) load_seg(nbs[k], u[k][0], u[k][1]);
+        }
+        // the transposed lower-face blocks are requested up front as well:
+        // 4 consecutive cells share each of their cache lines
+        float alo[3][B];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int c0 = c0s[ax], cs = nbs[NS + ax];
+            const int t0 = cs / TC, l0 = cs - t0 * TC;
+            const float* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + row) * TR + (size_t)l0 * B;
+#pragma unroll
+            for (int q = 0; q < B; ++q) alo[ax][q] = c0 >= 0 ? At[q] : 0.f;
+        }
         const float* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + threadIdx.x;
+#pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const int nb = s == 0 ? mycell : L.up[(size_t)(s - 1) * L.n + mycell];
             float a[B];
 #pragma unroll
             for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
-            mma(a, nb);
+            if constexpr (VB) load_seg(nbs[s], u[s][0], u[s][1]);
+            mma_seg(a, u[s][0], u[s][1]);
         }
-        for (int ax = 0; ax < 3; ++ax) {
-            const int c0 = L.lo[(size_t)ax * L.n + mycell];
-            const int cs = c0 >= 0 ? c0 : mycell;
-            const int t0 = cs / TC, l0 = cs - t0 * TC;
-            const float* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + row) * TR + (size_t)l0 * B;
-            float a[B];
 #pragma unroll
-            for (int q = 0; q < B; ++q) a[q] = c0 >= 0 ? At[q] : 0.f;
-            mma(a, cs);
+        for (int ax = 0; ax < 3; ++ax) {
+            if constexpr (VB) load_seg(nbs[NS + ax], u[NS + ax][0], u[NS + ax][1]);
+            mma_seg(alo[ax], u[NS + ax][0], u[NS + ax][1]);
         }
     } else {
         const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;

@@ -355,6 +355,8 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
             bool done = false;
             if constexpr (std::is_same<T, float>::value && R == 8) {
                 if (s->mfma && s->b == 8) {
+                    if (((uintptr_t)va | (uintptr_t)vb) & 15)
+                        fail(DGMG_EINVAL, "8-column vectors must be 16-byte aligned");
                     if (vb)
                         klaunch(ps, k_residual_m<float, 8, 8, true, AXV, true>, tiles_for<float, 8>(L), kWG, st,
                             largs<float>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype);
@@ -396,6 +398,7 @@ static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* 
             bool done = false;
             if constexpr (std::is_same<T, float>::value && R == 8) {
                 if (s->mfma && s->b == 8) {
+                    if ((uintptr_t)d & 15) fail(DGMG_EINVAL, "8-column vectors must be 16-byte aligned");
                     klaunch(ps, k_cheb_step_mfma8<AXV>, tiles_for<float, 8>(L), kWG, st, largs<float>(L), d, x, r, dn,
                                                                                   cd, cr, assign, last);
                     done = true;
