@@ -51,20 +51,31 @@ def _stats(v):
 
 
 def cheb_step_bytes(info, prec_bytes, nrhs=1):
-    """Algorithmic bytes of one fused Chebyshev step on level 0: every cell
-    and face block once (matrix-free: the packed conductivity of every cell
-    instead), the adjacency lists, and the vector streams of every column
-    (gather d, x r/w, r r/w, new d) plus D^-1 once."""
+    """Algorithmic bytes of one fused Chebyshev step on level 0: every face
+    block once and every cell block once (the axis layout: its upper
+    triangle, the block being symmetric; matrix-free: the packed
+    conductivity of every cell instead), the adjacency lists, and the
+    vector streams of every column (gather d, x r/w, r r/w, new d) plus
+    D^-1 once."""
     b = info["b"]
     n, nf = info["n_cells"][0], info["n_faces"][0]
     N = n * b
     if info.get("fine_layout") == "matrix_free":
         d = info["dim"]
         return n * (d * (d + 1) // 2) * prec_bytes + 2 * d * 4 * n + (6 * nrhs + 1) * prec_bytes * N
-    blocks = (n + nf) * b * b * prec_bytes
+    blocks = (n * cell_block_values(info) + nf * b * b) * prec_bytes
     adjacency = 4 * (n + 1) + 2 * 2 * 4 * nf
     vectors = (6 * nrhs + 1) * prec_bytes * N
     return blocks + adjacency + vectors
+
+
+def cell_block_values(info):
+    """Values a level-0 cell block needs: the upper triangle of the symmetric
+    block on the axis layout (which stores b/2 + 1 cyclic planes of b, the
+    entries at distance b/2 twice when b is even), the full b x b block on
+    the tile layout."""
+    b = info["b"]
+    return b * (b + 1) // 2 if info.get("fine_layout") == "axis_ell" else b * b
 
 
 def level0_working_set(info, prec_bytes, nrhs=1):
@@ -80,7 +91,7 @@ def level0_working_set(info, prec_bytes, nrhs=1):
         d = info["dim"]
         ops = n * (d * (d + 1) // 2) * prec_bytes + 2 * d * 4 * n
     else:
-        ops = (n + nf) * b * b * prec_bytes + 4 * (n + 1) + 2 * 2 * 4 * nf
+        ops = (n * cell_block_values(info) + nf * b * b) * prec_bytes + 4 * (n + 1) + 2 * 2 * 4 * nf
     return ops + (6 * nrhs + 1) * prec_bytes * N
 
 

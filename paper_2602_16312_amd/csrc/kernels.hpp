@@ -16,15 +16,16 @@
 //    from the other side costs more in cache-line traffic than the second
 //    copy costs in bytes on this hardware;
 //  * "axis-ELL" (fine level of a conforming quad/hex mesh, where every cell
-//    has at most one face neighbour per axis direction): tile t holds 1 + d
-//    slots at a fixed stride -- the cell blocks and, per axis a, the block
-//    U_a(c) = A[c, up_a(c)] of the face on the cell's upper a-side (zero if
-//    none), interleaved as above.  Each face block is stored once.  The
-//    lower a-face of cell c is U_a(lo_a(c)) read transposed: thread (c, i)
-//    reads column i of that block, B contiguous values at
-//    ((tile0*(1+d) + 1 + a)*B + i)*TR + lc0*B; consecutive cells have
-//    consecutive lower neighbours, so a wave's reads stay within a few
-//    cache lines per column plane;
+//    has at most one face neighbour per axis direction): tile t holds
+//    TP = B/2 + 1 + d*B planes of TR values at a fixed stride -- the
+//    symmetric cell blocks in B/2 + 1 cyclic planes (ax_cell_planes below)
+//    and, per axis a, B planes of the block U_a(c) = A[c, up_a(c)] of the
+//    face on the cell's upper a-side (zero if none), interleaved as above.
+//    Each face block is stored once.  The lower a-face of cell c is
+//    U_a(lo_a(c)) read transposed: thread (c, i) reads column i of that
+//    block, B contiguous values at (tile0*TP + B/2 + 1 + a*B + i)*TR +
+//    lc0*B; consecutive cells have consecutive lower neighbours, so a wave's
+//    reads stay within a few cache lines per column plane;
 //  * prolongation blocks use the same interleaving with one slot per tile.
 // Workgroups are mapped XCD-aware: the 8 XCDs receive consecutive workgroup
 // ids round-robin, so tile = (id % 8) * per + id / 8 gives each XCD a
@@ -88,6 +89,16 @@ struct Tile {
     static constexpr int TC = kWG / B;   // cells per tile / workgroup
     static constexpr int TR = TC * B;    // rows per tile
 };
+
+// Axis-ELL storage of a cell's diagonal block, which is symmetric: plane k
+// (k = 0 .. b/2) holds at the tile row of (cell, i) the entry
+// A_K[i][(i + k) mod b].  Every pair {i, j} is stored once (both orders when
+// b is even and j - i = b/2), so the block takes b/2 + 1 planes instead of b.
+// Row i reads column (i - k) mod b from plane k at row (i - k) mod b of the
+// same cell: the same cache lines as the plane's own entries.  The d upper
+// face blocks follow with b planes each.
+constexpr int ax_cell_planes(int b) { return b / 2 + 1; }
+constexpr int ax_tile_planes(int b, int d) { return ax_cell_planes(b) + d * b; }
 
 // Slots whose loads are issued together before any of them is accumulated
 // (bounded so that G*B values stay in registers): all five slots of a 2D
@@ -185,29 +196,73 @@ __device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int 
     return acc;
 }
 
-// The same row product on the axis-ELL layout: the 1 + d own slots (cell
-// block, upper faces) in groups as above, then each lower face as the
-// transposed column of the neighbour's stored block.
+// The same row product on the axis-ELL layout: the d upper face slots in
+// groups as above, the cell block from its b/2 + 1 symmetric planes (the
+// cell's own vector values in the matching cyclic order), then each lower
+// face as the transposed column of the neighbour's stored block.
 template <typename T, int B, bool VB, bool WW>
 __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int cell, int ri, int i,
                                           const T* __restrict__ va, const T* __restrict__ vb) {
-    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>(), NS = 1 + D;
-    constexpr int G = slot_group<B>() < NS ? slot_group<B>() : NS;
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>();
+    constexpr int P0 = ax_cell_planes(B), TP = ax_tile_planes(B, D);
+    constexpr int G = slot_group<B>() < D ? slot_group<B>() : D;
+    // cell-block planes per load group (FP64: fewer, to keep 8 waves per SIMD)
+    constexpr int KG = B > 27 ? 8 : (sizeof(T) == 8 ? 3 : P0);
     const int base = ((int)threadIdx.x & 63) - i;   // lane of the cell's row 0 (whole-wave cells)
-    const T* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + ri;
+    const T* __restrict__ A = L.vals + (size_t)tile * TP * TR + ri;
     T acc = 0;
+    // cell block: plane k holds A[i][i+k] at row i.  Row i takes it times
+    // x[i+k]; the symmetric entry A[i][i-k] is the plane's value at row i-k,
+    // so row i-k's product A[i-k][i] x[i-k] is what row i needs from it:
+    // whole-wave cells hand it over by a lane shuffle, other cells read the
+    // entry at the mirrored row (same cache lines) and the column value
+    {
+        T xself = 0;
+        if constexpr (WW) xself = gather_own<T, B, VB>(va, vb, cell, i);
 #pragma unroll
-    for (int g = 0; g < NS; g += G) {
+        for (int k0 = 0; k0 < P0; k0 += KG) {
+            T ao[KG], t1[KG], t2[KG];
+#pragma unroll
+            for (int q = 0; q < KG; ++q) {
+                const int k = k0 + q;
+                if (k >= P0) break;
+                const int jp = i + k >= B ? i + k - B : i + k;
+                const int jm = i >= k ? i - k : i - k + B;
+                ao[q] = A[(size_t)k * TR];
+                if constexpr (WW) {
+                    t1[q] = __shfl(xself, base + jp, 64);
+                } else {
+                    t1[q] = gather_own<T, B, VB>(va, vb, cell, jp);
+                    t2[q] = (k > 0 && 2 * k != B)
+                                ? A[(ptrdiff_t)k * TR + (jm - i)] * gather_own<T, B, VB>(va, vb, cell, jm)
+                                : T(0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < KG; ++q) {
+                const int k = k0 + q;
+                if (k >= P0) break;
+                acc += ao[q] * t1[q];
+                if (k > 0 && 2 * k != B) {
+                    if constexpr (WW) {
+                        const int jm = i >= k ? i - k : i - k + B;
+                        acc += __shfl(ao[q] * xself, base + jm, 64);
+                    } else {
+                        acc += t2[q];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < D; g += G) {
         int nbq[G];
         T a[G][B], v[G][B];
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int sl = min(g + q, NS - 1);
-            nbq[q] = sl == 0 ? cell : L.up[(size_t)(sl - 1) * L.n + cell];
-        }
+        for (int q = 0; q < G; ++q) nbq[q] = L.up[(size_t)min(g + q, D - 1) * L.n + cell];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            const T* As = A + (size_t)min(g + q, NS - 1) * B * TR;
+            const T* As = A + (size_t)(P0 + min(g + q, D - 1) * B) * TR;
 #pragma unroll
             for (int j = 0; j < B; ++j) a[q][j] = As[(size_t)j * TR];
         }
@@ -223,7 +278,7 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int c
         }
 #pragma unroll
         for (int q = 0; q < G; ++q)
-            if (g + q < NS) {
+            if (g + q < D) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) acc += a[q][j] * v[q][j];
             }
@@ -233,7 +288,7 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int c
         const int c0 = L.lo[(size_t)ax * L.n + cell];
         if (c0 >= 0) {
             const int t0 = c0 / TC, l0 = c0 - t0 * TC;
-            const T* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + i) * TR + (size_t)l0 * B;
+            const T* At = L.vals + ((size_t)t0 * TP + P0 + ax * B + i) * TR + (size_t)l0 * B;
             T a[B], v[B];
 #pragma unroll
             for (int r = 0; r < B; ++r) a[r] = At[r];

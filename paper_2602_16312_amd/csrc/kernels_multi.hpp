@@ -41,37 +41,52 @@ __device__ __forceinline__ void ell_row_apply_m(const LevelArgs<T>& L, int tile,
     }
 }
 
-// Axis-ELL variant: own slots, then the lower faces read transposed.
+// Axis-ELL variant: the upper face slots, the cell block from its symmetric
+// planes (plane k: A[i][i+k] and, at row i-k, A[i][i-k]), then the lower
+// faces read transposed.
 template <typename T, int B, int R, bool VB>
 __device__ __forceinline__ void ax_row_apply_m(const LevelArgs<T>& L, int tile, int lc, int cell,
                                                const T* __restrict__ va, const T* __restrict__ vb,
                                                T* acc) {
-    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>(), NS = 1 + D;
+    constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>();
+    constexpr int P0 = ax_cell_planes(B), TP = ax_tile_planes(B, D);
     const int i = threadIdx.x - lc * B;
-    const T* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + threadIdx.x;
+    const T* __restrict__ A = L.vals + (size_t)tile * TP * TR + threadIdx.x;
+    auto column = [&](int nb, int j, int r) -> T {
+        const size_t k = ((size_t)nb * B + j) * R + r;
+        return VB ? va[k] + vb[k] : va[k];
+    };
     auto accumulate = [&](const T* a, int nb) {
-        const T* x = va + (size_t)nb * B * R;
-        const T* y = VB ? vb + (size_t)nb * B * R : nullptr;
 #pragma unroll
         for (int j = 0; j < B; ++j)
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T v = VB ? x[j * R + r] + y[j * R + r] : x[j * R + r];
-                acc[r] += a[j] * v;
-            }
+            for (int r = 0; r < R; ++r) acc[r] += a[j] * column(nb, j, r);
     };
-    for (int s = 0; s < NS; ++s) {
-        const int nb = s == 0 ? cell : L.up[(size_t)(s - 1) * L.n + cell];
+    for (int s = 0; s < D; ++s) {
+        const int nb = L.up[(size_t)s * L.n + cell];
         T a[B];
 #pragma unroll
-        for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+        for (int j = 0; j < B; ++j) a[j] = A[(size_t)(P0 + s * B + j) * TR];
         accumulate(a, nb);
+    }
+#pragma unroll
+    for (int k = 0; k < P0; ++k) {
+        const int jp = i + k >= B ? i + k - B : i + k;
+        const T ao = A[(size_t)k * TR];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += ao * column(cell, jp, r);
+        if (k > 0 && 2 * k != B) {
+            const int jm = i >= k ? i - k : i - k + B;
+            const T am = A[(ptrdiff_t)k * TR + (jm - i)];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += am * column(cell, jm, r);
+        }
     }
     for (int ax = 0; ax < D; ++ax) {
         const int c0 = L.lo[(size_t)ax * L.n + cell];
         if (c0 < 0) continue;
         const int t0 = c0 / TC, l0 = c0 - t0 * TC;
-        const T* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + i) * TR + (size_t)l0 * B;
+        const T* At = L.vals + ((size_t)t0 * TP + P0 + ax * B + i) * TR + (size_t)l0 * B;
         T a[B];
 #pragma unroll
         for (int r = 0; r < B; ++r) a[r] = At[r];
@@ -378,6 +393,7 @@ __device__ __forceinline__ void mfma8_tile_product(const LevelArgs<float>& L, in
 #pragma unroll
             for (int k = 0; k < 7; ++k) load_seg(nbs[k], u[k][0], u[k][1]);
         }
+        constexpr int P0 = ax_cell_planes(B), TP = ax_tile_planes(B, 3);
         // the transposed lower-face blocks are requested up front as well:
         // 4 consecutive cells share each of their cache lines
         float alo[3][B];
@@ -385,16 +401,37 @@ __device__ __forceinline__ void mfma8_tile_product(const LevelArgs<float>& L, in
         for (int ax = 0; ax < 3; ++ax) {
             const int c0 = c0s[ax], cs = nbs[NS + ax];
             const int t0 = cs / TC, l0 = cs - t0 * TC;
-            const float* At = L.vals + (((size_t)t0 * NS + 1 + ax) * B + row) * TR + (size_t)l0 * B;
+            const float* At = L.vals + ((size_t)t0 * TP + P0 + ax * B + row) * TR + (size_t)l0 * B;
 #pragma unroll
             for (int q = 0; q < B; ++q) alo[ax][q] = c0 >= 0 ? At[q] : 0.f;
         }
-        const float* __restrict__ A = L.vals + (size_t)tile * NS * B * TR + threadIdx.x;
+        const float* __restrict__ A = L.vals + (size_t)tile * TP * TR + threadIdx.x;
+        // the cell block's row in column order (the matrix cores take one
+        // column per step): plane k gives columns row + k and row - k, which
+        // the lane places in a private LDS row (stride 9 against conflicts)
+        __shared__ float arow[kWG * 9];
+        float a0[B];
+        {
+            float* w = arow + threadIdx.x * 9;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
+            for (int k = 0; k < P0; ++k) {
+                const int jp = row + k >= B ? row + k - B : row + k;
+                w[jp] = A[(size_t)k * TR];
+                if (k > 0 && 2 * k != B) {
+                    const int jm = row >= k ? row - k : row - k + B;
+                    w[jm] = A[(ptrdiff_t)k * TR + (jm - row)];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j) a0[j] = w[j];
+        }
+        if constexpr (VB) load_seg(nbs[0], u[0][0], u[0][1]);
+        mma_seg(a0, u[0][0], u[0][1]);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) {
             float a[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
+            for (int j = 0; j < B; ++j) a[j] = A[(size_t)(P0 + (s - 1) * B + j) * TR];
             if constexpr (VB) load_seg(nbs[s], u[s][0], u[s][1]);
             mma_seg(a, u[s][0], u[s][1]);
         }

@@ -871,8 +871,9 @@ static TileEll build_tile_ell(const BlockOp& A, int window = 0) {
 }
 
 // Axis-ELL layout of the fine operator (see kernels.hpp): per tile of TC
-// cells, slot 0 the cell blocks and slot 1 + a the block A[c, up_a(c)] of the
-// face on the upper a-side of each cell; up/lo map every cell to its upper /
+// cells, the symmetric cell blocks in b/2 + 1 cyclic planes, then b planes
+// per axis a of the block A[c, up_a(c)] of the face on the upper a-side of
+// each cell; up/lo map every cell to its upper /
 // lower neighbour along each axis.  Faces are (plus = lower cell, minus =
 // upper cell, axis) as found on the conforming mesh.
 struct AxisEll {
@@ -880,7 +881,7 @@ struct AxisEll {
     std::vector<double> vals;
 };
 static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, int d, bool with_vals) {
-    const int b = A.b, TC = kWG / b, TR = TC * b, NS = 1 + d;
+    const int b = A.b, TC = kWG / b, TR = TC * b, P0 = ax_cell_planes(b), TP = ax_tile_planes(b, d);
     const int64_t n = A.n, ntiles = (n + TC - 1) / TC;
     if ((int64_t)axis.size() != A.nf) fail(DGMG_EINVAL, "face axis list does not match the operator");
     AxisEll E;
@@ -900,20 +901,25 @@ static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, in
         upface[(size_t)a * n + p] = f;
     }
     if (!with_vals) return E;
-    E.vals.assign((size_t)ntiles * NS * b * TR, 0.0);
-    auto put = [&](int64_t c, int slot, const double* blk) {
-        const int64_t t = c / TC;
-        const int lc = (int)(c - t * TC);
-        for (int i = 0; i < b; ++i)
-            for (int j = 0; j < b; ++j)
-                E.vals[(((size_t)t * NS + slot) * b + j) * TR + (size_t)lc * b + i] = blk[(size_t)i * b + j];
-    };
+    // per tile: the cell blocks' symmetric planes (plane k, row (cell, i):
+    // entry [i][(i + k) mod b]), then b planes per upper face (plane j, row
+    // (cell, i): entry [i][j])
+    E.vals.assign((size_t)ntiles * TP * TR, 0.0);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
-        put(c, 0, &A.diag[(size_t)c * b * b]);
+        const int64_t t = c / TC;
+        const size_t row0 = (size_t)(c - t * TC) * b;
+        const double* D = &A.diag[(size_t)c * b * b];
+        for (int k = 0; k < P0; ++k)
+            for (int i = 0; i < b; ++i)
+                E.vals[((size_t)t * TP + k) * TR + row0 + i] = D[(size_t)i * b + (i + k) % b];
         for (int a = 0; a < d; ++a) {
             const int64_t f = upface[(size_t)a * n + c];
-            if (f >= 0) put(c, 1 + a, &A.fblk[(size_t)f * b * b]);
+            if (f < 0) continue;
+            const double* F = &A.fblk[(size_t)f * b * b];
+            for (int j = 0; j < b; ++j)
+                for (int i = 0; i < b; ++i)
+                    E.vals[((size_t)t * TP + P0 + (size_t)a * b + j) * TR + row0 + i] = F[(size_t)i * b + j];
         }
     }
     return E;
