@@ -166,11 +166,6 @@ def profiled_counters(workload):
     return {k: float(vals[k]) for k in ("traffic_bytes_per_launch", "flops_per_launch") if k in vals}
 
 
-def profiled_traffic(workload):
-    """HBM bytes per launch of the dominant kernel, or None (see profiled_counters)."""
-    return profiled_counters(workload).get("traffic_bytes_per_launch")
-
-
 def _iapp(pr, t, nrhs):
     """Nodal applied current at time t: one column, or one column per
     stimulus site (column-minor), or None when no stimulus is on."""
@@ -423,6 +418,10 @@ def measure(workload, pr, args, steps, warmup, nrhs):
                   jacobi=args.jacobi)
     info = res["info"]
     prof = res["prof"]
+    # the committed counter summaries profile the default configuration
+    # (point Jacobi, automatic fine layout, the MFMA step for 8 columns)
+    default_cfg = args.jacobi == "point" and args.fine_layout == "auto" and not args.no_mfma
+    counters = profiled_counters(workload) if default_cfg else {}
     in_run_s = prof["in_run_ms"] / 1e3
     b2b_s = prof["back_to_back_ms"] / 1e3
     alg = cheb_step_bytes(info, 4, nrhs)
@@ -452,7 +451,7 @@ def measure(workload, pr, args, steps, warmup, nrhs):
         # stream); the back-to-back figure repeats one launch on the same data
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(workload),
+                     "traffic": counters.get("traffic_bytes_per_launch"),
                      "kernel": kname,
                      "alg_bytes_per_launch": alg, "avg_launch_us": in_run_s * 1e6,
                      "launches": prof["launches"],
@@ -469,7 +468,7 @@ def measure(workload, pr, args, steps, warmup, nrhs):
         # vector work (counted by rocprofv3) at the FP32 vector peak takes
         # longer than its bytes at the HBM peak, so the arithmetic roofline
         # is the binding one; the HBM figures stay alongside
-        fl = profiled_counters(workload).get("flops_per_launch")
+        fl = counters.get("flops_per_launch")
         if fl is not None:
             hbm = {k: m["roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
             tf = fl / in_run_s / 1e12

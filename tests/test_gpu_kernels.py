@@ -16,7 +16,8 @@ from oracle.mg import VCycle, pcg
 pytestmark = pytest.mark.gpu
 
 SIZES = [("c1", 32, {}), ("c2", 64, {}), ("c2", 36, {"p": 3, "group": [3]}),
-         ("c3", 8, {}), ("c3", 6, {"p": 1, "group": [3]}), ("c2", 20, {"p": 4, "group": [4]})]
+         ("c3", 8, {}), ("c3", 6, {"p": 1, "group": [3]}), ("c2", 20, {"p": 4, "group": [4]}),
+         ("c3", 4, {"p": 3, "group": [2]})]
 
 
 def _setup(name, n, kw, precision="fp64", lam=True, layout="auto"):
