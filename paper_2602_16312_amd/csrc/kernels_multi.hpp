@@ -69,17 +69,44 @@ __device__ __forceinline__ void ax_row_apply_m(const LevelArgs<T>& L, int tile, 
         for (int j = 0; j < B; ++j) a[j] = A[(size_t)(P0 + s * B + j) * TR];
         accumulate(a, nb);
     }
+    if constexpr (64 % B == 0) {
+        // the cell's B lanes sit in one wave: each loads its own row of the
+        // segment, rows i + k arrive by lane shuffles, and so do the products
+        // A[i-k][i] x[i-k][r] of row i - k (the symmetric entries)
+        const int base = ((int)threadIdx.x & 63) - i;
+        T xs[R];
 #pragma unroll
-    for (int k = 0; k < P0; ++k) {
-        const int jp = i + k >= B ? i + k - B : i + k;
-        const T ao = A[(size_t)k * TR];
+        for (int r = 0; r < R; ++r) xs[r] = column(cell, i, r);
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += ao * column(cell, jp, r);
-        if (k > 0 && 2 * k != B) {
-            const int jm = i >= k ? i - k : i - k + B;
-            const T am = A[(ptrdiff_t)k * TR + (jm - i)];
+        for (int k = 0; k < P0; ++k) {
+            const T ao = A[(size_t)k * TR];
+            if (k == 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += am * column(cell, jm, r);
+                for (int r = 0; r < R; ++r) acc[r] += ao * xs[r];
+                continue;
+            }
+            const int jp = i + k >= B ? i + k - B : i + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += ao * __shfl(xs[r], base + jp, 64);
+            if (2 * k != B) {
+                const int jm = i >= k ? i - k : i - k + B;
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += __shfl(ao * xs[r], base + jm, 64);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < P0; ++k) {
+            const int jp = i + k >= B ? i + k - B : i + k;
+            const T ao = A[(size_t)k * TR];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += ao * column(cell, jp, r);
+            if (k > 0 && 2 * k != B) {
+                const int jm = i >= k ? i - k : i - k + B;
+                const T am = A[(ptrdiff_t)k * TR + (jm - i)];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += am * column(cell, jm, r);
+            }
         }
     }
     for (int ax = 0; ax < D; ++ax) {
