@@ -13,31 +13,77 @@ namespace dgmg {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Orders one wave's LDS accesses at the compiler level.  Only lanes of one
+// wave exchange data through the buffers it guards, and LDS executes a
+// wave's instructions in issue order, so no barrier is needed.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // acc[r] += (A (va + vb))[row, r] for the tile thread (lc, i), slot by slot:
 // one coalesced block column value per (slot, j) and the R contiguous
 // gathered values of the column cell.
+// Neighbour segments (B rows of R values) for cells whose B lanes share a
+// wave are staged in a wave-private LDS buffer: lane i loads row i and every
+// lane reads the B rows back (one address per cell: LDS broadcast), instead
+// of every lane loading the whole segment through the address unit.  The
+// cell buffers are padded by 16 bytes against bank conflicts.
+template <int B>
+constexpr bool stage_segments() { return 64 % B == 0; }
+template <typename T, int B, int R>
+__device__ __forceinline__ T* segment_buffer() {
+    constexpr int CS = B * R + 16 / (int)sizeof(T);
+    __shared__ __align__(16) T stage[stage_segments<B>() ? kWG / 64 * (64 / B) * CS : 1];
+    if constexpr (!stage_segments<B>()) return stage;
+    return stage + ((threadIdx.x >> 6) * (64 / B) + ((threadIdx.x & 63) / B)) * CS;
+}
+// acc[r] += sum_j a[j] (va + vb)[nb, j, r] at row i of the thread's cell
+// (cs: the cell's buffer from segment_buffer).
+template <typename T, int B, int R, bool VB>
+__device__ __forceinline__ void segment_accumulate(const T* __restrict__ va, const T* __restrict__ vb,
+                                                   int nb, int i, const T* a, T* acc, T* cs) {
+    auto column = [&](int j, int r) -> T {
+        const size_t k = ((size_t)nb * B + j) * R + r;
+        return VB ? va[k] + vb[k] : va[k];
+    };
+    if constexpr (stage_segments<B>()) {
+        T row[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) row[r] = column(i, r);
+        wave_lds_fence();   // the previous segment's reads stay before these writes
+#pragma unroll
+        for (int r = 0; r < R; ++r) cs[i * R + r] = row[r];
+        wave_lds_fence();
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += a[j] * cs[j * R + r];
+    } else {
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += a[j] * column(j, r);
+    }
+}
+
 template <typename T, int B, int R, bool VB>
 __device__ __forceinline__ void ell_row_apply_m(const LevelArgs<T>& L, int tile, int lc,
                                                 const T* __restrict__ va, const T* __restrict__ vb,
                                                 T* acc) {
     constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR;
+    const int i = threadIdx.x - lc * B;
     const int s0 = L.slot_ptr[tile], ns = L.slot_ptr[tile + 1] - s0;
     const T* __restrict__ A = L.vals + (size_t)s0 * B * TR + threadIdx.x;
     const int32_t* __restrict__ nbp = L.snb + (size_t)s0 * TC + lc;
+    T* cs = segment_buffer<T, B, R>();
     for (int s = 0; s < ns; ++s) {
         const int nb = nbp[(size_t)s * TC];
         T a[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) a[j] = A[((size_t)s * B + j) * TR];
-        const T* x = va + (size_t)nb * B * R;
-        const T* y = VB ? vb + (size_t)nb * B * R : nullptr;
-#pragma unroll
-        for (int j = 0; j < B; ++j)
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T v = VB ? x[j * R + r] + y[j * R + r] : x[j * R + r];
-                acc[r] += a[j] * v;
-            }
+        segment_accumulate<T, B, R, VB>(va, vb, nb, i, a, acc, cs);
     }
 }
 
@@ -56,12 +102,8 @@ __device__ __forceinline__ void ax_row_apply_m(const LevelArgs<T>& L, int tile, 
         const size_t k = ((size_t)nb * B + j) * R + r;
         return VB ? va[k] + vb[k] : va[k];
     };
-    auto accumulate = [&](const T* a, int nb) {
-#pragma unroll
-        for (int j = 0; j < B; ++j)
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += a[j] * column(nb, j, r);
-    };
+    T* cs = segment_buffer<T, B, R>();
+    auto accumulate = [&](const T* a, int nb) { segment_accumulate<T, B, R, VB>(va, vb, nb, i, a, acc, cs); };
     for (int s = 0; s < D; ++s) {
         const int nb = L.up[(size_t)s * L.n + cell];
         T a[B];
@@ -69,7 +111,7 @@ __device__ __forceinline__ void ax_row_apply_m(const LevelArgs<T>& L, int tile, 
         for (int j = 0; j < B; ++j) a[j] = A[(size_t)(P0 + s * B + j) * TR];
         accumulate(a, nb);
     }
-    if constexpr (64 % B == 0) {
+    if constexpr (stage_segments<B>()) {
         // the cell's B lanes sit in one wave: each loads its own row of the
         // segment, rows i + k arrive by lane shuffles, and so do the products
         // A[i-k][i] x[i-k][r] of row i - k (the symmetric entries)
@@ -341,11 +383,6 @@ __global__ __launch_bounds__(kWG) void k_cheb_step_m(LevelArgs<T> L, const T* __
 // two-address LDS reads).  Only lanes of one wave exchange data through the
 // buffer, and LDS executes a wave's instructions in issue order, so a
 // wave-level compiler fence is all the ordering needed.
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <bool AX, bool VB>
 __device__ __forceinline__ void mfma8_tile_product(const LevelArgs<float>& L, int tile,
