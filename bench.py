@@ -183,7 +183,7 @@ def _iapp(pr, t, nrhs):
 
 
 def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None, nrhs=1, mfma=False,
-            fine_layout="auto", setup="device", jacobi="point"):
+            fine_layout="auto", setup="device", jacobi="point", step_log=None, workload=None):
     import numpy as np
     import torch
     from paper_2602_16312_amd import api, problem
@@ -237,7 +237,48 @@ def run_gpu(pr, precision, steps, warmup, tol, profile_kind=None, nrhs=1, mfma=F
         n, ms = api.profile_end(s)
         b2b = api.kernel_bench(s, profile_kind, 0, 200, nrhs=nrhs)
         prof = dict(launches=n, in_run_ms=ms / max(1, n), back_to_back_ms=b2b)
+    if step_log is not None:
+        write_step_log(step_log, workload, precision, s, st, step, pr, k, steps, tol, nrhs, setup_s, dev)
     return dict(wall=wall, its=its, setup_s=setup_s, info=s.info(), prof=prof, U=U)
+
+
+def write_step_log(f, workload, precision, s, st, step, pr, k, steps, tol, nrhs, setup_s, dev):
+    """One JSON line for the set-up (phase buckets, operator complexity,
+    level sizes) and one per time step of a further `steps` steps after the
+    timed and profiled ones (iterations, initial and final residual norms,
+    wall time, the ionic / load-vector / PCG phase times from HIP events on
+    the solver's stream, DoFs/s).  The logged steps synchronise after every
+    step and carry the phase events, so they are not the timed ones."""
+    import torch
+    from paper_2602_16312_amd import api
+    info = s.info()
+    f.write(json.dumps({"record": "setup", "workload": workload, "precision": precision,
+                        "setup_s": round(setup_s, 4),
+                        "phases_s": {a: round(b, 4) for a, b in info["t_setup"].items()},
+                        "op_complexity": info["op_complexity"], "cells_per_level": info["n_cells"],
+                        "n_dofs": int(pr["N"]), "rhs": nrhs}) + "\n")
+    api.set_phase_timing(s, True)
+    try:
+        for _ in range(steps):
+            k += 1
+            a = _iapp(pr, k * pr["dt"], nrhs)
+            ia = None if a is None else dev(a)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = step(s, st, k * pr["dt"], iapp=ia, tol=tol)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            cols = [r] if nrhs == 1 else r
+            rec = {"record": "step", "workload": workload, "precision": precision, "step": k,
+                   "t": k * pr["dt"], "its": [c["its"] for c in cols], "r0": [c["r0"] for c in cols],
+                   "r_final": [c["rfin"] for c in cols], "converged": all(c["converged"] for c in cols),
+                   "ms": round(ms, 4), "dofs_per_s": pr["N"] * nrhs / (ms / 1e3)}
+            if nrhs == 1:
+                rec["phase_ms"] = {a: round(b, 4) for a, b in api.step_phase_ms(s).items()}
+            f.write(json.dumps(rec) + "\n")
+    finally:
+        api.set_phase_timing(s, False)
+    f.flush()
 
 
 def run_adjoint(args):
@@ -414,6 +455,7 @@ def measure(workload, pr, args, steps, warmup, nrhs):
     import numpy as np
     mfma = nrhs > 1 and not args.no_mfma
     res = run_gpu(pr, "mixed", steps, warmup, args.tol, profile_kind="cheb_step",
+                  step_log=args.step_log_file, workload=workload,
                   nrhs=nrhs, mfma=mfma, fine_layout=args.fine_layout, setup=args.setup,
                   jacobi=args.jacobi)
     info = res["info"]
@@ -483,7 +525,8 @@ def measure(workload, pr, args, steps, warmup, nrhs):
             "utilisation": fl / MFMA_F32_PEAK_TFLOPS}
     if not args.no_fp64:
         r64 = run_gpu(pr, "fp64", steps, warmup, args.tol, nrhs=nrhs,
-                      fine_layout=args.fine_layout, setup=args.setup, jacobi=args.jacobi)
+                      fine_layout=args.fine_layout, setup=args.setup, jacobi=args.jacobi,
+                      step_log=args.step_log_file, workload=workload)
         m["fp64"] = {"value": pr["N"] * nrhs / (r64["wall"] / steps),
                      "ms_per_step": r64["wall"] / steps * 1e3,
                      "iters": _stats(r64["its"])}
@@ -496,6 +539,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--step-log", default=None, metavar="PATH",
+                    help="write JSON lines to PATH: one per solver set-up (phase buckets, operator "
+                         "complexity), one per time step of a further --steps logged steps after the "
+                         "timed ones (iterations, r0, r_final, phase times, DoFs/s), one for the run")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true")
@@ -533,6 +580,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    args.step_log_file = open(args.step_log, "w") if args.step_log else None
 
     import numpy as np
     import torch
@@ -589,6 +637,9 @@ def main():
                 err[prec] = float(np.linalg.norm(rg["U"] - U_oracle) / np.linalg.norm(U_oracle))
             out["rel_err_vs_oracle"] = err
     print(json.dumps(out))
+    if args.step_log_file:
+        args.step_log_file.write(json.dumps({"record": "run", **out}) + "\n")
+        args.step_log_file.close()
 
 
 if __name__ == "__main__":

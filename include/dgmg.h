@@ -411,6 +411,18 @@ int dgmg_grad_accumulate(dgmg_solver* s, const double* lambda, const double* U, 
 int dgmg_profile_begin(dgmg_solver* s, int32_t kind, int32_t level);
 int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms);
 
+/* Per-phase times of the time step (the semi-implicit step of section 3.1:
+ * ionic update, load vector, PCG solve), for per-step logs.  With on = 1
+ * every following dgmg_time_step records HIP events on its stream at the
+ * phase boundaries (extra event packets: leave it off in timed runs);
+ * on = 0 stops that.  dgmg_step_phase_ms waits for the last such step's
+ * final event and writes its three durations in ms to ms[0] (ionic update),
+ * ms[1] (load vector) and ms[2] (PCG solve, host stopping tests included).
+ * Errors: DGMG_EINVAL for a null argument, or from dgmg_step_phase_ms when
+ * no step was timed since phase timing was switched on. */
+int dgmg_set_phase_timing(dgmg_solver* s, int32_t on);
+int dgmg_step_phase_ms(dgmg_solver* s, double* ms);
+
 /* Average duration (ms, HIP events on `stream`) of `reps` back-to-back
  * launches of one smoother kernel (kind 0: fused Chebyshev step, 1: fused
  * residual) on `level` < n_levels - 1, in the solver's V-cycle precision,

@@ -21,7 +21,7 @@ EXPORTS = [
     "dgmg_apply", "dgmg_vcycle", "dgmg_mass_apply", "dgmg_export_level",
     "dgmg_profile_begin", "dgmg_profile_end", "dgmg_kernel_bench", "dgmg_last_error",
     "dgmg_set_sensors", "dgmg_sensor_misfit", "dgmg_adjoint_step", "dgmg_grad_accumulate",
-    "dgmg_pcg_solve_noalloc",
+    "dgmg_pcg_solve_noalloc", "dgmg_set_phase_timing", "dgmg_step_phase_ms",
 ]
 
 dp = C.POINTER(C.c_double)
@@ -137,6 +137,8 @@ def lib():
         L.dgmg_mass_apply.argtypes = [vp, vp, vp, vp]
         L.dgmg_export_level.argtypes = [vp, C.c_int32, dp, i64p, dp, dp, i64p]
         L.dgmg_profile_begin.argtypes = [vp, C.c_int32, C.c_int32]
+        L.dgmg_set_phase_timing.argtypes = [vp, C.c_int32]
+        L.dgmg_step_phase_ms.argtypes = [vp, dp]
         L.dgmg_profile_end.argtypes = [vp, i64p, dp]
         L.dgmg_kernel_bench.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, dp]
         L.dgmg_pcg_solve_multi.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(PCGOpts),

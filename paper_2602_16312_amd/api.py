@@ -285,6 +285,20 @@ def pcg_solve_multi(solver, b, x, tol=1e-8, tol_mode="rel_r0", max_it=500, flexi
     return [_stats(st[c], rc) for c in range(F.MULTI_RHS)]
 
 
+def set_phase_timing(solver, on=True):
+    """dgmg_set_phase_timing: record HIP events at the phase boundaries of
+    every following time_step (for per-step logs; not for timed runs)."""
+    F.check(F.lib().dgmg_set_phase_timing(solver.handle, 1 if on else 0))
+
+
+def step_phase_ms(solver):
+    """dgmg_step_phase_ms: the last timed step's ionic update, load vector and
+    PCG solve durations in ms (waits for the step's final event)."""
+    ms = (C.c_double * 3)()
+    F.check(F.lib().dgmg_step_phase_ms(solver.handle, ms))
+    return dict(ionic=ms[0], load_vector=ms[1], pcg=ms[2])
+
+
 def ionic_step(solver, U, Uprev, W, Wprev, Wnext, g, stream=None):
     """dgmg_ionic_step: BDF2 gate update at U* and nodal ionic current."""
     F.check(F.lib().dgmg_ionic_step(solver.handle, _dev(U), _dev(Uprev), _dev(W),

@@ -182,6 +182,10 @@ struct dgmg_solver {
     std::vector<std::vector<int64_t>> parents;
     std::vector<double> mass_h;
     dgmg_solver_info info{};
+    // per-phase events of the time step (ionic, load vector, PCG), created
+    // when phase timing is first switched on; phase_n: steps timed since
+    int phase_on = 0, phase_n = 0;
+    hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // kernel timing with HIP events (one kernel kind on one level at a time)
     int prof_kind = -1, prof_level = -1;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -203,6 +207,8 @@ struct dgmg_solver {
         return d;
     }
     ~dgmg_solver() {
+        for (hipEvent_t e : phase_ev)
+            if (e) (void)hipEventDestroy(e);
         for (auto& e : prof_ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -1823,15 +1829,23 @@ int dgmg_time_step(dgmg_solver* s, dgmg_state* z, double t_next, const double* i
     need_device(s);
     if (!z || !o || !st || !z->U || !z->Uprev || !z->W || !z->Wprev || !z->g) fail(DGMG_EINVAL, "null argument");
     hipStream_t hs = (hipStream_t)stream;
+    auto mark = [&](int k) {
+        if (s->phase_on) HIPCHK(hipEventRecord(s->phase_ev[k], hs));
+    };
+    mark(0);
     // gates W_{n+1} into the W_{n-1} buffer, nodal ionic current g
     k_ionic<<<blocks_for(s->N), 256, 0, hs>>>(s->N, s->ip, z->U, z->Uprev, z->W, z->Wprev, z->Wprev, z->g);
+    mark(1);
     // load vector; the warm start U_n is written into the U_{n-1} buffer
     const int cells_per = 256 / s->b;
     const unsigned nblk = (unsigned)((s->lv[0].n + cells_per - 1) / cells_per);
     DISPATCH_B(s->b, k_rhs<BV><<<nblk, cells_per * BV, 0, hs>>>(s->lv[0].n, s->ip, s->cU, s->mass, z->U,
                                                                  z->Uprev, iapp, z->g, s->bwork, z->Uprev));
     HIPCHK(hipGetLastError());
+    mark(2);
     int rc = pcg(s, s->bwork, z->Uprev, *o, st, hs, s->partial, s->sc);
+    mark(3);
+    if (s->phase_on) ++s->phase_n;
     std::swap(z->U, z->Uprev);
     std::swap(z->W, z->Wprev);
     return rc;
@@ -1980,6 +1994,32 @@ int dgmg_profile_end(dgmg_solver* s, int64_t* launches, double* total_ms) {
     s->prof_kind = -1;
     s->prof_level = -1;
     s->prof_used = 0;
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_set_phase_timing(dgmg_solver* s, int32_t on) {
+    API_BEGIN
+    need_device(s);
+    if (on && !s->phase_ev[0])
+        for (hipEvent_t& e : s->phase_ev) HIPCHK(hipEventCreate(&e));
+    s->phase_on = on ? 1 : 0;
+    s->phase_n = 0;
+    return DGMG_OK;
+    API_END
+}
+
+int dgmg_step_phase_ms(dgmg_solver* s, double* ms) {
+    API_BEGIN
+    need_device(s);
+    if (!ms) fail(DGMG_EINVAL, "null argument");
+    if (!s->phase_on || s->phase_n == 0) fail(DGMG_EINVAL, "no time step was timed since phase timing was switched on");
+    HIPCHK(hipEventSynchronize(s->phase_ev[3]));
+    for (int k = 0; k < 3; ++k) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, s->phase_ev[k], s->phase_ev[k + 1]));
+        ms[k] = t;
+    }
     return DGMG_OK;
     API_END
 }

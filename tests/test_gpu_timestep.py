@@ -62,3 +62,41 @@ def test_production_tolerance_and_mixed_precision(name, n, steps, tol):
         print(f"{name} {prec}: its={its} max rel err vs oracle={err:.2e}")
         # a solve stopped at relative residual tol lands within ~kappa*tol
         assert err <= 1e3 * tol
+
+
+def test_phase_timing_of_a_step():
+    """dgmg_set_phase_timing / dgmg_step_phase_ms: three positive phase
+    durations per timed step whose sum stays within the step's wall time, an
+    error before any step is timed, and the same trajectory with the events
+    on as without them."""
+    import time
+    from paper_2602_16312_amd import _ffi as F
+    pr = make_problem("c2", n=32)
+    _, s = problem.build(pr, precision="mixed")
+    _, s2 = problem.build(pr, precision="mixed")
+    st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()),
+                   dev(pr["W0"].ravel()), torch.empty(pr["N"], dtype=torch.float64, device="cuda"))
+    st2 = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()),
+                    dev(pr["W0"].ravel()), torch.empty(pr["N"], dtype=torch.float64, device="cuda"))
+    api.set_phase_timing(s, True)
+    with pytest.raises(F.DGMGError) as e:
+        api.step_phase_ms(s)
+    assert e.value.code == -1
+    for k in range(3):
+        t = (k + 1) * pr["dt"]
+        say("phase timing step", k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.time_step(s, st, t, tol=1e-8)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        ph = api.step_phase_ms(s)
+        assert r["converged"]
+        assert all(v > 0 for v in ph.values()), ph
+        assert sum(ph.values()) <= wall_ms * 1.05 + 0.05, (ph, wall_ms)
+        r2 = api.time_step(s2, st2, t, tol=1e-8)
+        assert r2["its"] == r["its"]
+        assert torch.equal(st.U, st2.U)
+    api.set_phase_timing(s, False)
+    with pytest.raises(F.DGMGError):
+        api.step_phase_ms(s)
