@@ -58,7 +58,7 @@ def build(verbose=False, sanitize=False):
     link_extra = (["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                    "-Xarch_host", "-shared-libsan"] if sanitize else [])
     _run([HIPCC] + DEVICE_FLAGS + link_extra + ["-shared", "-fopenmp", "-o", tmp] + objs +
-         ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"])
+         ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, out)
     if sanitize:
         return out

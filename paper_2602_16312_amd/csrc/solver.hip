@@ -14,12 +14,14 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -182,6 +184,9 @@ struct dgmg_solver {
     std::vector<std::vector<int64_t>> parents;
     std::vector<double> mass_h;
     dgmg_solver_info info{};
+    // roctx ranges (time step, PCG solve, V-cycle level) for rocprofv3's
+    // marker trace: on when DGMG_ROCTX=1 at set-up
+    bool roctx = false;
     // per-phase events of the time step (ionic, load vector, PCG), created
     // when phase timing is first switched on; phase_n: steps timed since
     int phase_on = 0, phase_n = 0;
@@ -429,12 +434,31 @@ static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
         klaunch(ps, k_coarse_solve_m<T, T, R>, (n + rows_per_wg - 1) / rows_per_wg, kWG, st, n, s->Ainv, rc, xc);
 }
 
+// A roctx range (host timeline of rocprofv3's marker trace) for the scope's
+// lifetime when the solver has them switched on.
+struct RangeScope {
+    bool on;
+    RangeScope(const dgmg_solver* s, const char* name) : on(s->roctx) {
+        if (on) roctxRangePushA(name);
+    }
+    ~RangeScope() {
+        if (on) roctxRangePop();
+    }
+};
+static const char* vcycle_range_name(int l) {
+    static const char* names[DGMG_MAX_LEVELS] = {"dgmg V-cycle level 0", "dgmg V-cycle level 1",
+        "dgmg V-cycle level 2", "dgmg V-cycle level 3", "dgmg V-cycle level 4", "dgmg V-cycle level 5",
+        "dgmg V-cycle level 6", "dgmg V-cycle level 7"};
+    return l < DGMG_MAX_LEVELS ? names[l] : "dgmg V-cycle level";
+}
+
 // One V-cycle from level l on R columns; the result is x + d (d may be null).
 // init_done: the producer of the level's right-hand side already started the
 // first smoothing sweep from x = 0 (r = b, d = c1 dinv b in the level's r
 // and d buffers), so that sweep skips its init kernel.
 template <typename T, int R = 1>
 static void vcycle(dgmg_solver* s, int l, hipStream_t st, T** xres, T** dres, bool init_done = false) {
+    RangeScope range(s, vcycle_range_name(l));
     DevLevel& L = s->lv[l];
     T* b = (T*)L.vb;
     if (l == s->L - 1) {
@@ -609,6 +633,7 @@ static std::string breakdown_msg(int its, int col, double pq, double gam) {
 // the non-allocating entry point.
 static int pcg(dgmg_solver* s, const double* b, double* x, const dgmg_pcg_opts& o, dgmg_pcg_stats* stats,
                hipStream_t st, double* partial, double* sc) {
+    RangeScope range(s, "dgmg PCG");
     const int64_t N = s->N;
     const unsigned nb = blocks_for(N);
     DevLevel& L0 = s->lv[0];
@@ -1545,6 +1570,10 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     s->L = h->n_levels;
     s->prec = mg->precision;
     s->bdf = ph->bdf;
+    {
+        const char* rx = std::getenv("DGMG_ROCTX");
+        s->roctx = rx && rx[0] == '1';
+    }
     s->cheb_k = mg->cheb_degree;
     s->cheb_s = mg->cheb_sweeps;
     if (mg->max_rhs != 0 && mg->max_rhs != 1 && mg->max_rhs != DGMG_MULTI_RHS)
@@ -1829,6 +1858,7 @@ int dgmg_time_step(dgmg_solver* s, dgmg_state* z, double t_next, const double* i
     need_device(s);
     if (!z || !o || !st || !z->U || !z->Uprev || !z->W || !z->Wprev || !z->g) fail(DGMG_EINVAL, "null argument");
     hipStream_t hs = (hipStream_t)stream;
+    RangeScope range(s, "dgmg time step");
     auto mark = [&](int k) {
         if (s->phase_on) HIPCHK(hipEventRecord(s->phase_ev[k], hs));
     };
