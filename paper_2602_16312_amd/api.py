@@ -315,6 +315,24 @@ class State:
         return F.State(self.U.data_ptr(), self.Uprev.data_ptr(), self.W.data_ptr(),
                        self.Wprev.data_ptr(), self.g.data_ptr())
 
+    def save(self, path, **meta):
+        """Checkpoint of the step state (U_n, U_{n-1}, W_n, W_{n-1}) with any
+        caller metadata (time, step index) via torch.save; a time step is a
+        pure function of this state, so load() resumes a run bit for bit."""
+        import torch
+        torch.save({"U": self.U.cpu(), "Uprev": self.Uprev.cpu(), "W": self.W.cpu(),
+                    "Wprev": self.Wprev.cpu(), "meta": meta}, path)
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        """(State, meta) from a save() file; the g workspace is fresh."""
+        import torch
+        d = torch.load(path, weights_only=True)
+        to = lambda t: t.to(device).contiguous()
+        st = cls(to(d["U"]), to(d["Uprev"]), to(d["W"]), to(d["Wprev"]),
+                 torch.empty_like(d["U"], device=device))
+        return st, d["meta"]
+
     def _adopt(self, s):
         # the library rotated the pointer pairs: follow it
         if s.U != self.U.data_ptr():

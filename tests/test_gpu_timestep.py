@@ -100,3 +100,36 @@ def test_phase_timing_of_a_step():
     api.set_phase_timing(s, False)
     with pytest.raises(F.DGMGError):
         api.step_phase_ms(s)
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    """A run stopped after 4 steps, saved with State.save and resumed by a
+    fresh solver from State.load, ends on the same U as an uninterrupted run,
+    bit for bit (a time step is a pure function of its state)."""
+    pr = make_problem("c2", n=32)
+    steps, stop = 8, 4
+
+    def fresh():
+        _, s = problem.build(pr, precision="mixed")
+        st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()),
+                       dev(pr["W0"].ravel()), torch.empty(pr["N"], dtype=torch.float64, device="cuda"))
+        return s, st
+
+    s, st = fresh()
+    for k in range(steps):
+        api.time_step(s, st, (k + 1) * pr["dt"], tol=1e-8)
+    U_ref = st.U.clone()
+    s, st = fresh()
+    for k in range(stop):
+        api.time_step(s, st, (k + 1) * pr["dt"], tol=1e-8)
+    path = tmp_path / "state.pt"
+    st.save(path, step=stop)
+    del s, st
+    say("resume from checkpoint")
+    s, _ = fresh()
+    st, meta = api.State.load(path)
+    assert meta["step"] == stop
+    for k in range(meta["step"], steps):
+        r = api.time_step(s, st, (k + 1) * pr["dt"], tol=1e-8)
+        assert r["converged"]
+    assert torch.equal(st.U, U_ref)
