@@ -2,7 +2,8 @@
 five STR R-tree levels) with the 8-column solver and the matrix-core
 Chebyshev step: sampled operator rows against the oracle's row assembly,
 per-column solve residuals, and time steps of the 8 stimulus-site
-simulations against the single-column stepper."""
+simulations against the single-column stepper; the single-column stepper's
+time steps against the oracle's step on sampled cells."""
 import time
 
 import numpy as np
@@ -12,6 +13,8 @@ from gpu_util import dev, host, need_gpu, rel, say, torch
 from paper_2602_16312_amd import api, problem
 from workloads import make_problem
 from oracle.assemble import assemble
+from oracle.ionic import gate_step, ionic_current
+from workloads.configs import iapp_nodal
 
 pytestmark = pytest.mark.gpu
 R = 8
@@ -108,3 +111,52 @@ def test_c4_time_steps_multi_vs_single(c4):
         if len(cells):
             assert U.reshape(-1, pr["b"], R)[cells, :, c].mean() > 0.0
     assert np.abs(U[:, 0] - U[:, 1]).max() > 0.0
+
+
+def test_c4_time_steps_against_oracle_rows(c4):
+    """Single-column mixed solver, 3 time steps of the apex simulation (section
+    3.1 step).  On 64 seeded cells (half of them stimulated): the gates equal the oracle's pointwise BDF2
+    gate step at U* = 2 U_n - U_{n-1} (1e-12), and the new U solves the
+    oracle's system there: the sampled rows of b_n - A_0 U_{n+1}, with the
+    load vector b_n and A_0 assembled by the oracle from the step's inputs,
+    stay at the PCG's residual level (a wrong load-vector term or operator
+    entry would leave them of the order of b_n)."""
+    pr, _, _ = c4
+    N, S, b = pr["N"], pr["S"], pr["b"]
+    # half of the cells in the stimulated region (where b_n is not zero in
+    # the first steps), half anywhere
+    rng = np.random.default_rng(17)
+    stim = np.nonzero(pr["stim_mask"])[0]
+    cells = np.unique(np.concatenate([rng.choice(stim, min(32, len(stim)), replace=False),
+                                      rng.choice(pr["n_cells"], 32, replace=False)]))
+    rows = (cells[:, None] * b + np.arange(b)).ravel()
+    M, A = assemble(pr, row_cells=cells)
+    cM = 1.5 * pr["chi"] * pr["Cm"] / pr["dt"]
+    A0 = (cM * M + A).tocsr()
+    M = M.tocsr()
+    say("c4 single-column set-up (mixed)")
+    _, s = problem.build(pr, precision="mixed")
+    st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()), dev(pr["W0"].ravel()),
+                   torch.empty(N, dtype=torch.float64, device="cuda"))
+    c = pr["chi"] * pr["Cm"]
+    for k in range(3):
+        t = (k + 1) * pr["dt"]
+        Un, Unm1 = host(st.U), host(st.Uprev)
+        Wn = host(st.W).reshape(S, N)[:, rows]
+        Wnm1 = host(st.Wprev).reshape(S, N)[:, rows]
+        ia = iapp_nodal(pr, t)
+        say("c4 single-column step", k)
+        r = api.time_step(s, st, t, iapp=dev(ia) if ia.any() else None, tol=1e-8)
+        assert r["converged"]
+        ustar = 2.0 * Un[rows] - Unm1[rows]
+        Wnew = gate_step(pr["model"], pr["params"], ustar, Wn, Wnm1, pr["dt"], 2)
+        g = ionic_current(pr["model"], pr["params"], ustar, Wnew)
+        f = np.zeros(N)
+        f[rows] = c / (2.0 * pr["dt"]) * (4.0 * Un[rows] - Unm1[rows]) - pr["chi"] * g + ia[rows]
+        bn = (M @ f)[rows]
+        Wg = host(st.W).reshape(S, N)[:, rows]
+        assert np.abs(Wg - Wnew).max() <= 1e-12 * max(1.0, np.abs(Wnew).max())
+        res = bn - (A0 @ host(st.U))[rows]
+        q = float(np.linalg.norm(res) / np.linalg.norm(bn))
+        print(f"c4 step {k}: its={r['its']} sampled |b - A0 U| / |b| = {q:.2e}", flush=True)
+        assert q <= 1e-7
