@@ -1,7 +1,8 @@
 """Full-size 64^3 Q2 cube (7,077,888 DoFs, Bueno-Orovio, four agglomerated
 levels, 13,824-DoF coarse problem factorised on the device): sampled operator
 rows against the oracle's row assembly, solve properties that hold at any size,
-and a few time steps with the corner stimulus."""
+and a few time steps with the corner stimulus checked against the oracle's
+step on sampled cells."""
 import time
 
 import numpy as np
@@ -62,16 +63,49 @@ def test_c3_solve_residual_property(c3):
 
 
 def test_c3_time_steps(c3):
+    """3 mixed time steps with the corner stimulus (section 3.1 step).  On 64
+    seeded cells (half of them stimulated) the gates equal the oracle's
+    pointwise BDF2 gate step (1e-12) and the new U solves the oracle's system:
+    the sampled rows of b_n - A_0 U_{n+1}, with b_n and A_0 assembled by the
+    oracle from the step's inputs, stay at the PCG's residual level."""
+    from oracle.ionic import gate_step, ionic_current
     pr, h, s = c3
+    N, S, b = pr["N"], pr["S"], pr["b"]
+    rng = np.random.default_rng(23)
+    stim = np.nonzero(pr["stim_mask"])[0]
+    cells = np.unique(np.concatenate([rng.choice(stim, min(32, len(stim)), replace=False),
+                                      rng.choice(pr["n_cells"], 32, replace=False)]))
+    rows = (cells[:, None] * b + np.arange(b)).ravel()
+    M, A = assemble(pr, row_cells=cells)
+    cM = 1.5 * pr["chi"] * pr["Cm"] / pr["dt"]
+    A0 = (cM * M + A).tocsr()
+    M = M.tocsr()
+    c = pr["chi"] * pr["Cm"]
     st = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()), dev(pr["W0"].ravel()),
                    torch.empty(pr["N"], dtype=torch.float64, device="cuda"))
     its = []
     for k in range(3):
         t = (k + 1) * pr["dt"]
+        Un, Unm1 = host(st.U), host(st.Uprev)
+        Wn = host(st.W).reshape(S, N)[:, rows]
+        Wnm1 = host(st.Wprev).reshape(S, N)[:, rows]
+        ia = iapp_nodal(pr, t)
         say("c3 time step", k)
-        r = api.time_step(s, st, t, iapp=dev(iapp_nodal(pr, t)), tol=1e-8)
+        r = api.time_step(s, st, t, iapp=dev(ia), tol=1e-8)
         assert r["converged"]
         its.append(r["its"])
+        ustar = 2.0 * Un[rows] - Unm1[rows]
+        Wnew = gate_step(pr["model"], pr["params"], ustar, Wn, Wnm1, pr["dt"], 2)
+        g = ionic_current(pr["model"], pr["params"], ustar, Wnew)
+        f = np.zeros(N)
+        f[rows] = c / (2.0 * pr["dt"]) * (4.0 * Un[rows] - Unm1[rows]) - pr["chi"] * g + ia[rows]
+        bn = (M @ f)[rows]
+        Wg = host(st.W).reshape(S, N)[:, rows]
+        assert np.abs(Wg - Wnew).max() <= 1e-12 * max(1.0, np.abs(Wnew).max())
+        res = bn - (A0 @ host(st.U))[rows]
+        q = float(np.linalg.norm(res) / np.linalg.norm(bn))
+        print(f"c3 step {k}: its={r['its']} sampled |b - A0 U| / |b| = {q:.2e}", flush=True)
+        assert q <= 1e-7
     u = host(st.U)
     print("c3 its", its, "U range", u.min(), u.max(), flush=True)
     # stimulus raises the potential only in and near the stimulated corner
