@@ -2,8 +2,8 @@
 five STR R-tree levels) with the 8-column solver and the matrix-core
 Chebyshev step: sampled operator rows against the oracle's row assembly,
 per-column solve residuals, and time steps of the 8 stimulus-site
-simulations against the single-column stepper; the single-column stepper's
-time steps against the oracle's step on sampled cells."""
+simulations against the single-column stepper and, column by column, against
+the oracle's step on sampled cells; the same for the single-column stepper."""
 import time
 
 import numpy as np
@@ -88,13 +88,43 @@ def test_c4_time_steps_multi_vs_single(c4):
     ia0 = dev(ia[:, 0])
     s1 = api.State(dev(pr["U0"]), dev(pr["U0"]), dev(pr["W0"].ravel()), dev(pr["W0"].ravel()),
                    torch.empty(N, dtype=torch.float64, device="cuda"))
+    # every column against the oracle's step on sampled cells: 6 from each
+    # column's stimulus site and 16 anywhere
+    rng = np.random.default_rng(29)
+    picks = [rng.choice(pr["n_cells"], 16, replace=False)]
+    for c in range(R):
+        sc = np.nonzero(pr["stim_masks"][c])[0]
+        if len(sc):
+            picks.append(rng.choice(sc, min(6, len(sc)), replace=False))
+    cells = np.unique(np.concatenate(picks))
+    rows = (cells[:, None] * pr["b"] + np.arange(pr["b"])).ravel()
+    M, A = assemble(pr, row_cells=cells)
+    cM = 1.5 * pr["chi"] * pr["Cm"] / pr["dt"]
+    A0 = (cM * M + A).tocsr()
+    M = M.tocsr()
+    cc = pr["chi"] * pr["Cm"]
     its = []
     for k in range(3):
         t = (k + 1) * pr["dt"]
+        Un, Unm1 = host(st.U).reshape(N, R), host(st.Uprev).reshape(N, R)
+        Wn = host(st.W).reshape(S, N, R)[:, rows]
+        Wnm1 = host(st.Wprev).reshape(S, N, R)[:, rows]
         say("c4 time_step_multi", k)
         r = api.time_step_multi(s, st, t, iapp=iam, tol=1e-8)
         assert all(c["converged"] for c in r)
         its.append([c["its"] for c in r])
+        Unew = host(st.U).reshape(N, R)
+        Wg = host(st.W).reshape(S, N, R)[:, rows]
+        for c in range(R):
+            ustar = 2.0 * Un[rows, c] - Unm1[rows, c]
+            Wnew = gate_step(pr["model"], pr["params"], ustar, Wn[:, :, c], Wnm1[:, :, c], pr["dt"], 2)
+            g = ionic_current(pr["model"], pr["params"], ustar, Wnew)
+            f = np.zeros(N)
+            f[rows] = cc / (2.0 * pr["dt"]) * (4.0 * Un[rows, c] - Unm1[rows, c]) - pr["chi"] * g + ia[rows, c]
+            bn = (M @ f)[rows]
+            assert np.abs(Wg[:, :, c] - Wnew).max() <= 1e-12 * max(1.0, np.abs(Wnew).max())
+            q = float(np.linalg.norm(bn - (A0 @ Unew[:, c])[rows]) / np.linalg.norm(bn))
+            assert q <= 1e-7, (k, c, q)
         say("c4 time_step single", k)
         r1 = api.time_step(s, s1, t, iapp=ia0, tol=1e-8)
         assert r1["converged"]
