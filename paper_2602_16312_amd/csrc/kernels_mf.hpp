@@ -24,6 +24,9 @@
 //   3. the cell terms tested against every basis function by d passes of
 //      1D contractions (z, y, x), plus the face terms times each test
 //      function's normal factor.
+// In phases 2a, 2 and 2b a thread takes one (axis, face node or point) pair
+// and both faces normal to that axis, so the pair's index arithmetic, table
+// rows and conductivity products are formed once for the two faces.
 // Included by solver.hip after kernels.hpp.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -165,6 +168,15 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
     const bool slot = lc < TC;                        // thread maps to a (possibly padded) cell slot
     // item coordinates of this thread (x fastest)
     const int c0 = i % Q, c1 = (i / Q) % Q, c2 = D == 3 ? i / (Q * Q) : 0;
+    // face items of this thread: it = i + r B (r < FR) of the D QN pairs
+    // (axis a, face node or point m), each for both faces normal to a
+    constexpr int FR = (D * QN + B - 1) / B;
+    int fa[FR];
+#pragma unroll
+    for (int r = 0; r < FR; ++r) fa[r] = (i + r * B) / QN;
+    // FP32 unrolls the outer face-point loops; FP64 keeps them rolled to hold
+    // its register count, and with it the occupancy
+    constexpr int UF = sizeof(T) == 4 ? (D == 3 ? Q : 1) : 1;
     // ---- phase 0: stage values.  Branch-free, so that all loads of a round
     //      are in flight together: the neighbour indices, then every value
     //      and conductivity (padded slots and missing neighbours read the
@@ -214,24 +226,36 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
         }
         A1[lc][0][i] = a0;
         A1[lc][1][i] = b0;
-        for (int it = i; it < NF * QN; it += B) {
-            const int f = it / QN, m = it - f * QN;
-            const int a = f >> 1, eK = f & 1, eN = 1 - eK;
-            const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-            const int sa = a == 0 ? 1 : (a == 1 ? Q : Q * Q);
-            const int st1 = t1 == 0 ? 1 : Q;
-            const int st2 = D == 3 ? (t2 == 1 ? Q : Q * Q) : 0;
-            const int J0 = (m % Q) * st1 + (D == 3 ? (m / Q) * st2 : 0);
-            T dK = 0, dN = 0;
 #pragma unroll
-            for (int ja = 0; ja < Q; ++ja) {
-                dK += Ed[eK * Q + ja] * xs[lc][J0 + ja * sa];
-                dN += Ed[eN * Q + ja] * xn[lc][f][J0 + ja * sa];
+        for (int r = 0; r < FR; ++r) {
+            const int it = i + r * B;
+            if (it >= D * QN) break;
+            const int a = fa[r], m = it - a * QN;
+            // strides of the normal (sa) and tangential (st1, st2) directions
+            const int sa = a == 0 ? 1 : (a == 1 ? Q : Q * Q);
+            const int st1 = a == 0 ? Q : 1;
+            const int st2 = D == 3 ? (a == 2 ? Q : Q * Q) : 0;
+            const int J0 = (m % Q) * st1 + (D == 3 ? (m / Q) * st2 : 0);
+            T xk[Q];
+#pragma unroll
+            for (int ja = 0; ja < Q; ++ja) xk[ja] = xs[lc][J0 + ja * sa];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {                 // lower (0) and upper (1) face
+                const int f = 2 * a + s;
+                T xm[Q];
+#pragma unroll
+                for (int ja = 0; ja < Q; ++ja) xm[ja] = xn[lc][f][J0 + ja * sa];
+                T dK = 0, dN = 0;
+#pragma unroll
+                for (int ja = 0; ja < Q; ++ja) {
+                    dK += C.Ed[s * Q + ja] * xk[ja];
+                    dN += C.Ed[(1 - s) * Q + ja] * xm[ja];
+                }
+                fn[lc][f][m][0] = xk[s * (Q - 1)];
+                fn[lc][f][m][1] = xm[(1 - s) * (Q - 1)];
+                fn[lc][f][m][2] = dK;
+                fn[lc][f][m][3] = dN;
             }
-            fn[lc][f][m][0] = xs[lc][J0 + eK * (Q - 1) * sa];
-            fn[lc][f][m][1] = xn[lc][f][J0 + eN * (Q - 1) * sa];
-            fn[lc][f][m][2] = dK;
-            fn[lc][f][m][3] = dN;
         }
     }
     __syncthreads();
@@ -269,64 +293,75 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             const T gr[3] = {ux, uy, T(0)};
             cell_terms(u0, gr);
         }
-        for (int it = i; it < NF * QN; it += B) {
-            const int f = it / QN, qf = it - f * QN;
-            const int a = f >> 1;
-            const int side = f & 1;                  // 1: neighbour on the upper side
-            const T sgn = side ? T(1) : T(-1);
+#pragma unroll
+        for (int r = 0; r < FR; ++r) {
+            const int it = i + r * B;
+            if (it >= D * QN) break;
+            const int a = fa[r], qf = it - a * QN;
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;   // tangential directions
             const int g1 = qf % Q, g2 = D == 3 ? qf / Q : 0;
-            T uK = 0, uN = 0, nK = 0, nN = 0, p1K = 0, p1N = 0, p2K = 0, p2N = 0;
-            // sums over m1 first, then weighted by the m2 factor (the
-            // tensor weights are never formed); FP64: partial unrolling keeps
-            // the register count, and with it the occupancy, in check
-#pragma unroll 1
-            for (int m2 = 0; m2 < (D == 3 ? Q : 1); ++m2) {
-                T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+            // D_K[a][k] / h_k of the normal (ka) and tangential (k1, k2) directions
+            const T ha = hinv[a], h1 = hinv[t1], h2 = D == 3 ? hinv[t2] : T(0);
+            const T daa = Dk[lc][pk<D>(a, a)];
+            const T ka = daa * ha, k1 = Dk[lc][pk<D>(a, t1)] * h1;
+            const T k2 = D == 3 ? Dk[lc][pk<D>(a, t2)] * h2 : T(0);
+            const T wq = area[a] * gw[g1] * (D == 3 ? gw[g2] : T(1));
+            const T eh = etaa[a] * T(0.5);
 #pragma unroll
-                for (int m1 = 0; m1 < Q; ++m1) {
-                    const T* nd = fn[lc][f][m1 + Q * m2];
-                    const T iy = Ig[g1 * Q + m1], dy = Dg[g1 * Q + m1];
-                    a0 += iy * nd[0];
-                    a1 += iy * nd[1];
-                    a2 += iy * nd[2];
-                    a3 += iy * nd[3];
-                    a4 += dy * nd[0];
-                    a5 += dy * nd[1];
+            for (int s = 0; s < 2; ++s) {                 // s = 1: neighbour on the upper side
+                const int f = 2 * a + s;
+                const T sgn = s ? T(1) : T(-1);
+                T uK = 0, uN = 0, nK = 0, nN = 0, p1K = 0, p1N = 0, p2K = 0, p2N = 0;
+                // sums over m1 first, then weighted by the m2 factor (the
+                // tensor weights are never formed)
+#pragma unroll UF
+                for (int m2 = 0; m2 < (D == 3 ? Q : 1); ++m2) {
+                    T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+#pragma unroll
+                    for (int m1 = 0; m1 < Q; ++m1) {
+                        const T* nd = fn[lc][f][m1 + Q * m2];
+                        const T iy = Ig[g1 * Q + m1], dy = Dg[g1 * Q + m1];
+                        a0 += iy * nd[0];
+                        a1 += iy * nd[1];
+                        a2 += iy * nd[2];
+                        a3 += iy * nd[3];
+                        a4 += dy * nd[0];
+                        a5 += dy * nd[1];
+                    }
+                    if (D == 3) {
+                        const T i2 = Ig[g2 * Q + m2], e2 = Dg[g2 * Q + m2];
+                        uK += i2 * a0;
+                        uN += i2 * a1;
+                        nK += i2 * a2;
+                        nN += i2 * a3;
+                        p1K += i2 * a4;
+                        p1N += i2 * a5;
+                        p2K += e2 * a0;
+                        p2N += e2 * a1;
+                    } else {
+                        uK = a0;
+                        uN = a1;
+                        nK = a2;
+                        nN = a3;
+                        p1K = a4;
+                        p1N = a5;
+                    }
                 }
+                const T* dn = Dn[lc][f];
+                T wK = ka * nK + k1 * p1K;
+                T wN = dn[a] * ha * nN + dn[t1] * h1 * p1N;
                 if (D == 3) {
-                    const T i2 = Ig[g2 * Q + m2], e2 = Dg[g2 * Q + m2];
-                    uK += i2 * a0;
-                    uN += i2 * a1;
-                    nK += i2 * a2;
-                    nN += i2 * a3;
-                    p1K += i2 * a4;
-                    p1N += i2 * a5;
-                    p2K += e2 * a0;
-                    p2N += e2 * a1;
-                } else {
-                    uK = a0;
-                    uN = a1;
-                    nK = a2;
-                    nN = a3;
-                    p1K = a4;
-                    p1N = a5;
+                    wK += k2 * p2K;
+                    wN += dn[t2] * h2 * p2N;
                 }
+                const T w = hasn[lc][f] ? wq : T(0);      // boundary face: no terms
+                const T sig = eh * (daa + dn[a]);
+                const T jmp = uK - uN;
+                // value flux, and the conormal flux factor: it is tested against
+                // n.D_K grad v, i.e. times D_K[a][k] / h_k for each direction k
+                ff[lc][f][qf][0] = (T(-0.5) * sgn * (wK + wN) + sig * jmp) * w;
+                ff[lc][f][qf][1] = T(-0.5) * sgn * jmp * w;
             }
-            T wK = Dk[lc][pk<D>(a, a)] * hinv[a] * nK + Dk[lc][pk<D>(a, t1)] * hinv[t1] * p1K;
-            T wN = Dn[lc][f][a] * hinv[a] * nN + Dn[lc][f][t1] * hinv[t1] * p1N;
-            if (D == 3) {
-                wK += Dk[lc][pk<D>(a, t2)] * hinv[t2] * p2K;
-                wN += Dn[lc][f][t2] * hinv[t2] * p2N;
-            }
-            T w = area[a] * gw[g1] * (D == 3 ? gw[g2] : T(1));
-            if (!hasn[lc][f]) w = 0;                  // boundary face: no terms
-            const T sig = etaa[a] * T(0.5) * (Dk[lc][pk<D>(a, a)] + Dn[lc][f][a]);
-            const T jmp = uK - uN;
-            // value flux, and the conormal flux factor: it is tested against
-            // n.D_K grad v, i.e. times D_K[a][k] / h_k for each direction k
-            ff[lc][f][qf][0] = (T(-0.5) * sgn * (wK + wN) + sig * jmp) * w;
-            ff[lc][f][qf][1] = T(-0.5) * sgn * jmp * w;
         }
     }
     __syncthreads();
@@ -362,38 +397,44 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
             A4[lc][0][i] = P;
             A4[lc][1][i] = X;
         }
-        for (int it = i; it < NF * QN; it += B) {
-            const int f = it / QN, m = it - f * QN;
-            const int a = f >> 1;
+#pragma unroll
+        for (int r = 0; r < FR; ++r) {
+            const int it = i + r * B;
+            if (it >= D * QN) break;
+            const int a = fa[r], m = it - a * QN;
             const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int m1 = m % Q, m2 = D == 3 ? m / Q : 0;
             // D_K[a][k] / h_k of the normal (ka) and tangential (k1, k2) directions
             const T ka = Dk[lc][pk<D>(a, a)] * hinv[a];
             const T k1 = Dk[lc][pk<D>(a, t1)] * hinv[t1];
             const T k2 = D == 3 ? Dk[lc][pk<D>(a, t2)] * hinv[t2] : T(0);
-            T sv = 0, sc = 0;
-            // sums over g1 first, then weighted by the g2 factor
-#pragma unroll 1
-            for (int g2 = 0; g2 < (D == 3 ? Q : 1); ++g2) {
-                T e0 = 0, e1 = 0;
 #pragma unroll
-                for (int g1 = 0; g1 < Q; ++g1) {
-                    const T* F = ff[lc][f][g1 + Q * g2];
-                    const T i1 = Ig[g1 * Q + m1], d1 = Dg[g1 * Q + m1];
-                    e0 += F[0] * i1 + k1 * F[1] * d1;
-                    e1 += F[1] * i1;
+            for (int s = 0; s < 2; ++s) {
+                const int f = 2 * a + s;
+                T sv = 0, sc = 0;
+                // sums over g1 first, then weighted by the g2 factor
+#pragma unroll UF
+                for (int g2 = 0; g2 < (D == 3 ? Q : 1); ++g2) {
+                    T e0 = 0, e1 = 0;
+#pragma unroll
+                    for (int g1 = 0; g1 < Q; ++g1) {
+                        const T* F = ff[lc][f][g1 + Q * g2];
+                        const T i1 = Ig[g1 * Q + m1], d1 = Dg[g1 * Q + m1];
+                        e0 += F[0] * i1 + k1 * F[1] * d1;
+                        e1 += F[1] * i1;
+                    }
+                    if (D == 3) {
+                        const T i2 = Ig[g2 * Q + m2], d2 = Dg[g2 * Q + m2];
+                        sv += i2 * e0 + k2 * e1 * d2;
+                        sc += i2 * e1;
+                    } else {
+                        sv = e0;
+                        sc = e1;
+                    }
                 }
-                if (D == 3) {
-                    const T i2 = Ig[g2 * Q + m2], d2 = Dg[g2 * Q + m2];
-                    sv += i2 * e0 + k2 * e1 * d2;
-                    sc += i2 * e1;
-                } else {
-                    sv = e0;
-                    sc = e1;
-                }
+                fT[lc][f][m][0] = sv;
+                fT[lc][f][m][1] = ka * sc;
             }
-            fT[lc][f][m][0] = sv;
-            fT[lc][f][m][1] = ka * sc;
         }
     }
     __syncthreads();
