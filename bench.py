@@ -506,18 +506,20 @@ def measure(workload, pr, args, steps, warmup, nrhs):
         m["roofline"]["note"] = ("the level-0 working set fits the 256 MB Infinity Cache: "
                                  "the HBM peak is a reference, not the bound")
     if info["fine_layout"] == "matrix_free":
-        # the sum-factorised kernel trades bytes for arithmetic: its FP32
-        # vector work (counted by rocprofv3) at the FP32 vector peak takes
-        # longer than its bytes at the HBM peak, so the arithmetic roofline
-        # is the binding one; the HBM figures stay alongside
+        # the sum-factorised kernel trades bytes for arithmetic: the binding
+        # roofline is the one whose peak takes longer for the launch's work,
+        # its FP32 vector work (counted by rocprofv3) at the FP32 vector peak
+        # or its algorithmic bytes at the HBM peak; the other stays alongside
         fl = counters.get("flops_per_launch")
         if fl is not None:
-            hbm = {k: m["roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
             tf = fl / in_run_s / 1e12
-            m["roofline"].update({"bound": "alu", "achieved": tf,
-                                  "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
-                                  "flops_per_launch": fl, "hbm": hbm})
+            alu = {"achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": tf / FP32_VECTOR_PEAK_TFLOPS, "flops_per_launch": fl}
+            if fl / (FP32_VECTOR_PEAK_TFLOPS * 1e12) > alg / (HBM_PEAK_GBS * 1e9):
+                hbm = {k: m["roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
+                m["roofline"].update(dict(alu, bound="alu", hbm=hbm))
+            else:
+                m["roofline"]["alu"] = alu
     if nrhs > 1:
         fl = cheb_step_flops(info, nrhs) / in_run_s / 1e12
         m["roofline"]["mfma" if mfma else "valu"] = {
