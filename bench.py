@@ -481,7 +481,7 @@ def measure(workload, pr, args, steps, warmup, nrhs):
         "ms_per_step": res["wall"] / steps * 1e3,
         "config": {"workload": WORKLOADS[workload],
                    "n_dofs": int(pr["N"]), "rhs": nrhs, "cells_per_level": info["n_cells"],
-                   "precision": "mixed: FP32 V-cycle, FP64 PCG and coarse solve",
+                   "precision": "mixed: FP32 V-cycle (coarse inverse computed in FP64, stored in FP32), FP64 PCG",
                    "smoother": f"Chebyshev degree 3, 3 sweeps, {args.jacobi.replace('_', '-')} Jacobi",
                    "dt": pr["dt"], "tol": args.tol},
         "iters": _stats(res["its"]),

@@ -161,7 +161,8 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * pre/post sweeps, Lanczos steps, lambda_hi = lam_safety * theta_max,
  * lambda_lo = lambda_hi / smooth_range; host lam_override (NULL or 2 values
  * (lo, hi) per smoothed level) replaces the estimate.  precision MIXED runs
- * the V-cycle in FP32 with the coarse solve and the outer PCG in FP64.
+ * the V-cycle in FP32 and the outer PCG in FP64; its coarse inverse is
+ * computed in FP64 and kept rounded to FP32 (the coarse GEMV sums in FP64).
  * device_setup = 0 stops after the host setup (inspection on machines
  * without a GPU; solve calls then fail with DGMG_EINVAL).  adjoint = 1 also
  * stores the conductivity derivatives dA/ds_K (cell stiffness and per-side

@@ -606,38 +606,45 @@ __global__ __launch_bounds__(kWG) void k_prolong_add(int32_t n, const int32_t* _
 }
 
 // ------------------------------------------------------------ coarse
-// x = Ainv r with the dense symmetric FP64 coarse inverse (row-major): each
-// wave owns one row and reads it with coalesced loads; r is staged in LDS
-// chunk by chunk (converted to FP64) and shared by the workgroup's 4 waves.
+// x = Ainv r with the dense symmetric coarse inverse (row-major, computed in
+// FP64; TA = float for the FP32 V-cycle, which reads it rounded to FP32):
+// each wave owns one row and reads it with coalesced loads, accumulating in
+// FP64; r is staged in LDS chunk by chunk (converted to FP64) and shared by
+// the workgroup's 4 waves.
 constexpr int kCoarseChunk = 4096;
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kWG) void k_coarse_solve(int32_t n, const double* __restrict__ Ainv,
+template <typename Tin, typename Tout, typename TA>
+__global__ __launch_bounds__(kWG) void k_coarse_solve(int32_t n, const TA* __restrict__ Ainv,
                                                       const Tin* __restrict__ r,
                                                       Tout* __restrict__ x) {
     __shared__ double rs[kCoarseChunk];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * (kWG / 64) + wave;
-    // four independent partial sums per lane keep four loads in flight;
-    // column c goes to sum (c / 64) % 4 (chunks are multiples of 256)
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    // U independent partial sums per lane keep U loads (32 bytes) in flight;
+    // column c goes to sum (c / 64) % U (chunks are multiples of 64 U)
+    constexpr int U = sizeof(TA) == 4 ? 8 : 4;
+    static_assert(kCoarseChunk % (64 * U) == 0, "chunk is not a multiple of a wave's sweep");
+    double s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = 0.0;
     for (int c0 = 0; c0 < n; c0 += kCoarseChunk) {
         const int len = min(kCoarseChunk, n - c0);
         __syncthreads();
         for (int k = threadIdx.x; k < len; k += kWG) rs[k] = (double)r[c0 + k];
         __syncthreads();
         if (row < n) {
-            const double* a = Ainv + (size_t)row * n + c0;
+            const TA* a = Ainv + (size_t)row * n + c0;
             int c = lane;
-            for (; c + 192 < len; c += 256) {
+            for (; c + 64 * (U - 1) < len; c += 64 * U) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) s[u] += a[c + 64 * u] * rs[c + 64 * u];
+                for (int u = 0; u < U; ++u) s[u] += (double)a[c + 64 * u] * rs[c + 64 * u];
             }
 #pragma unroll
-            for (int u = 0; u < 3; ++u)
-                if (c + 64 * u < len) s[u] += a[c + 64 * u] * rs[c + 64 * u];
+            for (int u = 0; u < U - 1; ++u)
+                if (c + 64 * u < len) s[u] += (double)a[c + 64 * u] * rs[c + 64 * u];
         }
     }
-    double v = (s[0] + s[1]) + (s[2] + s[3]);
+    double v = U == 8 ? ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))
+                      : (s[0] + s[1]) + (s[2] + s[3]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0 && row < n) x[row] = (Tout)v;

@@ -609,10 +609,11 @@ __global__ __launch_bounds__(kWG) void k_prolong_add_m(int32_t n, const int32_t*
 }
 
 // X = Ainv Rhs for R columns (row-per-wave, right-hand sides staged in LDS),
-// each column summed in the single-column kernel's order.
+// each column summed in the single-column kernel's order for an FP64 Ainv
+// (TA = double; an FP32 Ainv is summed in 4 partial sums here, 8 there).
 constexpr int kCoarseChunkM = 512;
-template <typename Tin, typename Tout, int R>
-__global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const double* __restrict__ Ainv,
+template <typename Tin, typename Tout, int R, typename TA>
+__global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const TA* __restrict__ Ainv,
                                                         const Tin* __restrict__ rin,
                                                         Tout* __restrict__ x) {
     __shared__ double rs[kCoarseChunkM * R];
@@ -629,12 +630,12 @@ __global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const double*
         for (int k = threadIdx.x; k < len * R; k += kWG) rs[k] = (double)rin[(size_t)c0 * R + k];
         __syncthreads();
         if (row < n) {
-            const double* a = Ainv + (size_t)row * n + c0;
+            const TA* a = Ainv + (size_t)row * n + c0;
             int c = lane;
             for (; c + 192 < len; c += 256) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const double av = a[c + 64 * u];
+                    const double av = (double)a[c + 64 * u];
 #pragma unroll
                     for (int q = 0; q < R; ++q) s[u][q] += av * rs[(c + 64 * u) * R + q];
                 }
@@ -643,7 +644,7 @@ __global__ __launch_bounds__(kWG) void k_coarse_solve_m(int32_t n, const double*
             for (int u = 0; u < 3; ++u) {
                 const int cc = c + 64 * u;
                 if (cc < len) {
-                    const double av = a[cc];
+                    const double av = (double)a[cc];
 #pragma unroll
                     for (int q = 0; q < R; ++q) s[u][q] += av * rs[cc * R + q];
                 }

@@ -152,7 +152,8 @@ struct dgmg_solver {
     std::vector<DevLevel> lv;
     // coarse
     int64_t nc_dofs = 0;
-    double* Ainv = nullptr;
+    double* Ainv = nullptr;     // dense coarse inverse (FP64 solvers)
+    float* Ainv32 = nullptr;    // the same rounded to FP32 (mixed solvers' FP32 V-cycle)
     // outer PCG work
     double *r = nullptr, *z = nullptr, *zold = nullptr, *pv = nullptr, *q = nullptr, *bwork = nullptr;
     double *tmp64a = nullptr, *tmp64b = nullptr;
@@ -204,6 +205,16 @@ struct dgmg_solver {
         allocs.push_back(p);
         dev_bytes += (int64_t)(count * sizeof(T));
         return (T*)p;
+    }
+    // releases a dalloc'ed block of `bytes` before the solver ends
+    void dfree(void* p, size_t bytes) {
+        for (size_t k = 0; k < allocs.size(); ++k)
+            if (allocs[k] == p) {
+                allocs.erase(allocs.begin() + (ptrdiff_t)k);
+                mem.release(p);
+                dev_bytes -= (int64_t)bytes;
+                return;
+            }
     }
     template <typename T>
     T* upload(const std::vector<T>& h) {
@@ -428,10 +439,16 @@ static void coarse_solve(dgmg_solver* s, const T* rc, T* xc, hipStream_t st) {
     const int n = (int)s->nc_dofs;
     ProfScope ps(s, PK_COARSE, s->L - 1, st);
     const int rows_per_wg = kWG / 64;   // one row per wave
+    // the FP32 V-cycle of a mixed solver reads the inverse rounded to FP32
+    using TA = T;
+    const TA* A;
+    if constexpr (sizeof(T) == 4) A = s->Ainv32;
+    else A = s->Ainv;
+    if (!A) fail(DGMG_EINVAL, "the coarse inverse of this precision is not held by the solver");
     if constexpr (R == 1)
-        klaunch(ps, k_coarse_solve<T, T>, (n + rows_per_wg - 1) / rows_per_wg, kWG, st, n, s->Ainv, rc, xc);
+        klaunch(ps, k_coarse_solve<T, T, TA>, (n + rows_per_wg - 1) / rows_per_wg, kWG, st, n, A, rc, xc);
     else
-        klaunch(ps, k_coarse_solve_m<T, T, R>, (n + rows_per_wg - 1) / rows_per_wg, kWG, st, n, s->Ainv, rc, xc);
+        klaunch(ps, k_coarse_solve_m<T, T, R, TA>, (n + rows_per_wg - 1) / rows_per_wg, kWG, st, n, A, rc, xc);
 }
 
 // A roctx range (host timeline of rocprofv3's marker trace) for the scope's
@@ -1735,6 +1752,17 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     if (mg->device_setup) {
         for (int l = 0; l < s->L; ++l) upload_level(s, l);
         s->Ainv = coarse_on_device ? device_spd_inverse(s, Ac, s->nc_dofs) : s->upload(Ac);
+        if (s->prec == DGMG_PREC_MIXED) {
+            // the FP32 V-cycle streams the inverse rounded to FP32 (half the
+            // bytes of the GEMV; the sums stay in FP64); the FP64 copy goes
+            const int64_t nn = s->nc_dofs * s->nc_dofs;
+            s->Ainv32 = s->dalloc<float>((size_t)nn);
+            k_cast<double, float><<<blocks_for(nn), kWG>>>(nn, s->Ainv, nullptr, s->Ainv32);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipDeviceSynchronize());
+            s->dfree(s->Ainv, (size_t)nn * sizeof(double));
+            s->Ainv = nullptr;
+        }
         const int64_t N = s->N, R = s->max_rhs;
         s->r = s->dalloc<double>(N * R);
         s->z = s->dalloc<double>(N * R);
