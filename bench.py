@@ -52,7 +52,7 @@ def _stats(v):
 
 def cheb_step_bytes(info, prec_bytes, nrhs=1):
     """Algorithmic bytes of one fused Chebyshev step on level 0: every face
-    block once and every cell block once (the axis layout: its upper
+    block once (its nonzero part in the sparse-face form) and every cell block once (the axis layout: its upper
     triangle, the block being symmetric; matrix-free: the packed
     conductivity of every cell instead), the adjacency lists, and the
     vector streams of every column (gather d, x r/w, r r/w, new d) plus
@@ -63,7 +63,7 @@ def cheb_step_bytes(info, prec_bytes, nrhs=1):
     if info.get("fine_layout") == "matrix_free":
         d = info["dim"]
         return n * (d * (d + 1) // 2) * prec_bytes + 2 * d * 4 * n + (6 * nrhs + 1) * prec_bytes * N
-    blocks = (n * cell_block_values(info) + nf * b * b) * prec_bytes
+    blocks = (n * cell_block_values(info) + nf * face_block_values(info)) * prec_bytes
     adjacency = 4 * (n + 1) + 2 * 2 * 4 * nf
     vectors = (6 * nrhs + 1) * prec_bytes * N
     return blocks + adjacency + vectors
@@ -76,6 +76,18 @@ def cell_block_values(info):
     the tile layout."""
     b = info["b"]
     return b * (b + 1) // 2 if info.get("fine_layout") == "axis_ell" else b * b
+
+
+def face_block_values(info):
+    """Values a level-0 face block needs: b^2, or on a nodal fine level in
+    the sparse-face form the entries whose row or column node lies on the
+    face (nF = b / q of each, q nodes per axis): 2 nF b - nF^2."""
+    b, d = info["b"], info["dim"]
+    if not info.get("sparse_faces"):
+        return b * b
+    q = round(b ** (1.0 / d))
+    nf_ = b // q
+    return 2 * nf_ * b - nf_ * nf_
 
 
 def level0_working_set(info, prec_bytes, nrhs=1):
@@ -91,7 +103,7 @@ def level0_working_set(info, prec_bytes, nrhs=1):
         d = info["dim"]
         ops = n * (d * (d + 1) // 2) * prec_bytes + 2 * d * 4 * n
     else:
-        ops = (n * cell_block_values(info) + nf * b * b) * prec_bytes + 4 * (n + 1) + 2 * 2 * 4 * nf
+        ops = (n * cell_block_values(info) + nf * face_block_values(info)) * prec_bytes + 4 * (n + 1) + 2 * 2 * 4 * nf
     return ops + (6 * nrhs + 1) * prec_bytes * N
 
 

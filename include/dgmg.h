@@ -176,7 +176,10 @@ enum { DGMG_PREC_FP64 = 0, DGMG_PREC_MIXED = 1 };
  * upper faces along each axis; lower faces are read transposed from the
  * neighbour), TILE_ELL stores each face block twice, oriented for both
  * cells, as on the agglomerated levels; AUTO takes MATRIX_FREE for p >= 2 on
- * meshes of identical boxes with max_rhs <= 1, AXIS_ELL otherwise.
+ * meshes of identical boxes with max_rhs <= 1, AXIS_ELL otherwise.  With
+ * max_rhs <= 1, AXIS_ELL stores nodal face blocks in sparse form (see
+ * dgmg_solver_info.sparse_faces); AXIS_ELL_DENSE keeps every face block
+ * whole.
  * MATRIX_FREE (meshes of identical
  * axis-aligned boxes only, single-column calls only; DGMG_EUNSUPPORTED
  * otherwise) stores no fine-level operator: the cell, face and mass terms
@@ -213,7 +216,7 @@ typedef struct {
 enum { DGMG_JACOBI_POINT = 0, DGMG_JACOBI_CELL_BLOCK = 1 };
 
 enum { DGMG_LAYOUT_AUTO = 0, DGMG_LAYOUT_TILE_ELL = 1, DGMG_LAYOUT_AXIS_ELL = 2,
-       DGMG_LAYOUT_MATRIX_FREE = 3 };
+       DGMG_LAYOUT_MATRIX_FREE = 3, DGMG_LAYOUT_AXIS_ELL_DENSE = 4 };
 
 /* Number of columns of the multi-right-hand-side calls. */
 enum { DGMG_MULTI_RHS = 8 };
@@ -257,6 +260,13 @@ typedef struct {
      * neighbour count within runs of tiles (a tile-to-cell map, kept when it
      * saves at least 3% of the padded slots), 0 for the identity order */
     int32_t level_grouped[DGMG_MAX_LEVELS];
+    /* 1 when the fine level's axis-ELL face blocks are stored in sparse form:
+     * on a nodal fine level (Lagrange basis on Gauss-Lobatto nodes) entry
+     * (i, j) of a face block vanishes unless node i or node j lies on the
+     * face (section 3, face terms of a_h), and only the rest is stored.
+     * Single-column solvers use it whenever every fine face block has that
+     * pattern, unless fine_layout = AXIS_ELL_DENSE was asked for. */
+    int32_t sparse_faces;
 } dgmg_solver_info;
 int dgmg_get_info(const dgmg_solver* s, dgmg_solver_info* info);
 

@@ -86,7 +86,8 @@ class SolverInfo(C.Structure):
                 ("fine_layout", C.c_int32),
                 ("level_layout", C.c_int32 * MAX_LEVELS),
                 ("prolong_types", C.c_int32 * MAX_LEVELS),
-                ("level_grouped", C.c_int32 * MAX_LEVELS)]
+                ("level_grouped", C.c_int32 * MAX_LEVELS),
+                ("sparse_faces", C.c_int32)]
 
 
 class PCGOpts(C.Structure):

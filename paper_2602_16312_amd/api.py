@@ -13,7 +13,7 @@ from . import _ffi as F
 MODELS = {"fhn": 0, "ap": 1, "bo": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 TOL_MODES = {"rel_r0": 0, "rel_b": 1, "abs": 2}
-LAYOUTS = {"auto": 0, "tile_ell": 1, "axis_ell": 2, "matrix_free": 3}
+LAYOUTS = {"auto": 0, "tile_ell": 1, "axis_ell": 2, "matrix_free": 3, "axis_ell_dense": 4}
 JACOBI = {"point": 0, "cell_block": 1}
 
 
@@ -165,7 +165,8 @@ class Solver:
                     fine_layout=_LAYOUT_NAMES.get(i.fine_layout, "none"),
                     level_layout=[_LAYOUT_NAMES.get(v, "none") for v in i.level_layout[:L]],
                     prolong_types=list(i.prolong_types[:L]),
-                    level_grouped=[bool(v) for v in i.level_grouped[:L]])
+                    level_grouped=[bool(v) for v in i.level_grouped[:L]],
+                    sparse_faces=bool(i.sparse_faces))
 
     def export_level(self, level, blocks=True):
         """Host copies of a level's FP64 operator and transfer blocks

@@ -100,6 +100,30 @@ struct Tile {
 constexpr int ax_cell_planes(int b) { return b / 2 + 1; }
 constexpr int ax_tile_planes(int b, int d) { return ax_cell_planes(b) + d * b; }
 
+// Sparse face blocks of a nodal fine level (section 3: the face terms of a_h
+// test and trial traces, and a Q_p Lagrange function on Gauss-Lobatto nodes
+// has a nonzero trace on a face only if its node lies on that face).  Entry
+// (i, j) of the block A[c, up_a(c)] therefore vanishes unless node i lies on
+// the upper a-face of c or node j on the lower a-face of the neighbour: with
+// q nodes per axis, nF = b / q of the b rows and columns.  Per axis the
+// block is stored as nF full planes (the columns j on the lower face, by
+// tangential index) and b - nF sparse planes (the other columns, ordered by
+// (tangential index, coordinate - 1); each holds only the nF rows on the
+// upper face: TC nF values, by cell slot then the row's tangential index).
+__host__ __device__ constexpr int ax_nodes_1d(int b, int d) { return d == 2 ? (b == 4 ? 2 : b == 9 ? 3 : b == 16 ? 4 : 5) : (b == 8 ? 2 : b == 27 ? 3 : 4); }
+// coordinate of node j along axis a, and its index among the nodes of a face normal to a
+__host__ __device__ constexpr int node_coord(int j, int a, int q) { return a == 0 ? j % q : a == 1 ? (j / q) % q : j / (q * q); }
+__host__ __device__ constexpr int node_tan(int j, int a, int q) {
+    return a == 0 ? (j / q) % q + q * (j / (q * q)) : a == 1 ? j % q + q * (j / (q * q)) : j % (q * q);
+}
+// values per axis and per tile of the sparse-face axis layout (tiles of tc cells)
+constexpr int64_t ax_sparse_axis_values(int b, int d, int tc) {
+    return (int64_t)(b / ax_nodes_1d(b, d)) * tc * b + (int64_t)(b - b / ax_nodes_1d(b, d)) * tc * (b / ax_nodes_1d(b, d));
+}
+constexpr int64_t ax_sparse_tile_values(int b, int d, int tc) {
+    return (int64_t)ax_cell_planes(b) * tc * b + d * ax_sparse_axis_values(b, d, tc);
+}
+
 // Slots whose loads are issued together before any of them is accumulated
 // (bounded so that G*B values stay in registers): all five slots of a 2D
 // quad cell for B <= 9, fewer for larger blocks.
@@ -200,16 +224,20 @@ __device__ __forceinline__ T ell_row_apply(const LevelArgs<T>& L, int tile, int 
 // groups as above, the cell block from its b/2 + 1 symmetric planes (the
 // cell's own vector values in the matching cyclic order), then each lower
 // face as the transposed column of the neighbour's stored block.
-template <typename T, int B, bool VB, bool WW>
+// SF: sparse face blocks (see ax_sparse_tile_values).
+template <typename T, int B, bool VB, bool WW, bool SF = false>
 __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int cell, int ri, int i,
                                           const T* __restrict__ va, const T* __restrict__ vb) {
     constexpr int TC = Tile<T, B>::TC, TR = Tile<T, B>::TR, D = dim_of<B>();
     constexpr int P0 = ax_cell_planes(B), TP = ax_tile_planes(B, D);
+    constexpr int Q = ax_nodes_1d(B, D), NFN = B / Q, SP = TC * NFN;
+    constexpr int64_t AXS = ax_sparse_axis_values(B, D, TC);
+    constexpr int64_t TSTRIDE = SF ? ax_sparse_tile_values(B, D, TC) : (int64_t)TP * TR;
     constexpr int G = slot_group<B>() < D ? slot_group<B>() : D;
     // cell-block planes per load group (FP64: fewer, to keep 8 waves per SIMD)
     constexpr int KG = B > 27 ? 8 : (sizeof(T) == 8 ? 3 : P0);
     const int base = ((int)threadIdx.x & 63) - i;   // lane of the cell's row 0 (whole-wave cells)
-    const T* __restrict__ A = L.vals + (size_t)tile * TP * TR + ri;
+    const T* __restrict__ A = L.vals + (size_t)tile * TSTRIDE + ri;
     T acc = 0;
     // cell block: plane k holds A[i][i+k] at row i.  Row i takes it times
     // x[i+k]; the symmetric entry A[i][i-k] is the plane's value at row i-k,
@@ -262,9 +290,24 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int c
         for (int q = 0; q < G; ++q) nbq[q] = L.up[(size_t)min(g + q, D - 1) * L.n + cell];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            const T* As = A + (size_t)(P0 + min(g + q, D - 1) * B) * TR;
+            if constexpr (SF) {
+                // full planes at the thread's row; sparse planes only on
+                // the rows of the upper face, at (cell slot, tangential index)
+                const int ax = min(g + q, D - 1);
+                const T* As = A + (size_t)P0 * TR + (size_t)ax * AXS;
+                const T* Ss = As - ri + (size_t)NFN * TR + (size_t)(ri - i) / B * NFN + node_tan(i, ax, Q);
+                const bool on_up = node_coord(i, ax, Q) == Q - 1;
 #pragma unroll
-            for (int j = 0; j < B; ++j) a[q][j] = As[(size_t)j * TR];
+                for (int j = 0; j < B; ++j) {
+                    const int cj = node_coord(j, ax, Q), tj = node_tan(j, ax, Q);
+                    if (cj == 0) a[q][j] = As[(size_t)tj * TR];
+                    else a[q][j] = on_up ? Ss[(size_t)(tj * (Q - 1) + cj - 1) * SP] : T(0);
+                }
+            } else {
+                const T* As = A + (size_t)(P0 + min(g + q, D - 1) * B) * TR;
+#pragma unroll
+                for (int j = 0; j < B; ++j) a[q][j] = As[(size_t)j * TR];
+            }
         }
         if constexpr (WW) {
             T xq[G];
@@ -288,10 +331,27 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int c
         const int c0 = L.lo[(size_t)ax * L.n + cell];
         if (c0 >= 0) {
             const int t0 = c0 / TC, l0 = c0 - t0 * TC;
-            const T* At = L.vals + ((size_t)t0 * TP + P0 + ax * B + i) * TR + (size_t)l0 * B;
             T a[B], v[B];
+            if constexpr (SF) {
+                // column i of the neighbour's block: a full plane when node i
+                // lies on the lower face, else the upper-face rows only
+                const T* As = L.vals + (size_t)t0 * TSTRIDE + (size_t)P0 * TR + (size_t)ax * AXS;
+                const int ci = node_coord(i, ax, Q), ti = node_tan(i, ax, Q);
+                if (ci == 0) {
+                    const T* At = As + (size_t)ti * TR + (size_t)l0 * B;
 #pragma unroll
-            for (int r = 0; r < B; ++r) a[r] = At[r];
+                    for (int r = 0; r < B; ++r) a[r] = At[r];
+                } else {
+                    const T* At = As + (size_t)NFN * TR + (size_t)(ti * (Q - 1) + ci - 1) * SP + (size_t)l0 * NFN;
+#pragma unroll
+                    for (int r = 0; r < B; ++r)
+                        a[r] = node_coord(r, ax, Q) == Q - 1 ? At[node_tan(r, ax, Q)] : T(0);
+                }
+            } else {
+                const T* At = L.vals + ((size_t)t0 * TP + P0 + ax * B + i) * TR + (size_t)l0 * B;
+#pragma unroll
+                for (int r = 0; r < B; ++r) a[r] = At[r];
+            }
             if constexpr (WW)
                 share_segment<T, B>(gather_own<T, B, VB>(va, vb, c0, i), base, v);
             else
@@ -308,8 +368,9 @@ __device__ __forceinline__ T mf_row_apply(const LevelArgs<T>& L, int lc, int cel
                                           const T* __restrict__ va, const T* __restrict__ vb,
                                           T** lds_free);
 
-// Operator layouts of a level: tile-ELL, axis-ELL, matrix-free boxes.
-enum { LY_TILE = 0, LY_AXIS = 1, LY_MF = 2 };
+// Operator layouts of a level: tile-ELL, axis-ELL, matrix-free boxes,
+// axis-ELL with sparse face blocks (nodal fine levels, single column).
+enum { LY_TILE = 0, LY_AXIS = 1, LY_MF = 2, LY_AXS = 3 };
 
 // (A (va + vb)) at the thread's row for layout LY.  The matrix-free product
 // synchronises the workgroup, so every thread calls this; rows of inactive
@@ -327,8 +388,8 @@ __device__ __forceinline__ T row_apply(const LevelArgs<T>& L, int tile, int lc, 
         // a cell's lanes are all active or all inactive, so the shuffles of
         // an active cell read active lanes only
         if (!active) return T(0);
-        if constexpr (LY == LY_AXIS)
-            return ax_row_apply<T, B, VB, whole_wave_cells<B>()>(L, tile, cell, ri, i, va, vb);
+        if constexpr (LY == LY_AXIS || LY == LY_AXS)
+            return ax_row_apply<T, B, VB, whole_wave_cells<B>(), LY == LY_AXS>(L, tile, cell, ri, i, va, vb);
         else
             return ell_row_apply<T, B, VB, whole_wave_cells<B>()>(L, tile, lc, ri, i, va, vb);
     }

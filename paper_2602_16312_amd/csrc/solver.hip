@@ -50,11 +50,12 @@ void set_last_error(const std::string& m) { g_last_error = m; }
             fail(DGMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
     } while (0)
 
-// level layout: LYV (LY_TILE, LY_AXIS, LY_MF) and AXV (axis-ELL) as constants
+// level layout: LYV (LY_TILE, LY_AXIS, LY_MF, LY_AXS) and AXV (axis-ELL) as constants
 #define DISPATCH_LY(lyval, ...)                                                        \
     switch (lyval) {                                                                   \
         case LY_TILE: { constexpr int LYV = LY_TILE; constexpr bool AXV = false; __VA_ARGS__; } break; \
         case LY_AXIS: { constexpr int LYV = LY_AXIS; constexpr bool AXV = true; __VA_ARGS__; } break;  \
+        case LY_AXS: { constexpr int LYV = LY_AXS; constexpr bool AXV = true; __VA_ARGS__; } break;    \
         default: { constexpr int LYV = LY_MF; constexpr bool AXV = false; __VA_ARGS__; } break;        \
     }
 
@@ -107,6 +108,7 @@ struct DevLevel {
     int64_t N = 0;
     int32_t *slot_ptr = nullptr, *snb = nullptr;          // tile-ELL structure
     bool ax = false;                                       // axis-ELL layout instead
+    bool sf = false;                                       // axis-ELL with sparse face blocks
     bool mf = false;                                       // matrix-free boxes (fine level)
     MfConst<double> mf64{};
     MfConst<float> mf32{};
@@ -266,7 +268,7 @@ template <>
 LevelArgs<float> largs<float>(const DevLevel& L) {
     return {L.vals32, L.slot_ptr, L.snb, L.dinv32, L.n, L.up, L.lo, L.mf32, L.cmap};
 }
-static int level_ly(const DevLevel& L) { return L.mf ? LY_MF : (L.ax ? LY_AXIS : LY_TILE); }
+static int level_ly(const DevLevel& L) { return L.mf ? LY_MF : (L.ax ? (L.sf ? LY_AXS : LY_AXIS) : LY_TILE); }
 template <typename T>
 static const T* Pof(const DevLevel& L);
 template <>
@@ -341,6 +343,8 @@ static void launch_apply(dgmg_solver* s, const DevLevel& L, const T* va, T* y, c
         if constexpr (R == 1) {
             DISPATCH_B(s->b, klaunch(ps, k_apply<T, BV, LYV>, tiles_for<T, BV>(L), kWG, st, largs<T>(L), va, y, w,
                                                                                         partial));
+        } else if constexpr (LYV == LY_AXS) {
+            fail(DGMG_EUNSUPPORTED, "sparse face blocks have no multi-column kernels");
         } else if constexpr (LYV == LY_MF) {
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
@@ -371,6 +375,8 @@ static void launch_residual(dgmg_solver* s, const DevLevel& L, const T* va, cons
                 DISPATCH_B(s->b, klaunch(ps, k_residual<T, BV, false, LYV>, tiles_for<T, BV>(L), kWG, st,
                                      largs<T>(L), va, vb, rhs, r, d, c1, xout, partial, P, rp, ptype, bj));
             }
+        } else if constexpr (LYV == LY_AXS) {
+            fail(DGMG_EUNSUPPORTED, "sparse face blocks have no multi-column kernels");
         } else if constexpr (LYV == LY_MF) {
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
@@ -414,6 +420,8 @@ static void launch_step(dgmg_solver* s, const DevLevel& L, const T* d, T* x, T* 
                 DISPATCH_B(s->b, klaunch(ps, k_cheb_step<T, BV, LYV>, tiles_for<T, BV>(L), kWG, st, largs<T>(L), d,
                                          x, r, dn, cd, cr, assign, last, bj));
             }
+        } else if constexpr (LYV == LY_AXS) {
+            fail(DGMG_EUNSUPPORTED, "sparse face blocks have no multi-column kernels");
         } else if constexpr (LYV == LY_MF) {
             fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
         } else {
@@ -927,8 +935,31 @@ static TileEll build_tile_ell(const BlockOp& A, int window = 0) {
 struct AxisEll {
     std::vector<int32_t> up, lo;
     std::vector<double> vals;
+    bool sparse = false;   // face blocks in the sparse-face form (kernels.hpp)
 };
-static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, int d, bool with_vals) {
+// Whether every face block vanishes outside the rows of the lower cell's
+// upper face and the columns of the upper cell's lower face (exact zeros).
+static bool faces_are_nodal(const BlockOp& A, const std::vector<int64_t>& upface, int d) {
+    const int b = A.b, q = ax_nodes_1d(b, d);
+    if (q < 2 || std::pow(q, d) != b) return false;
+    const int64_t n = A.n;
+    bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+    for (int64_t c = 0; c < n; ++c)
+        for (int a = 0; a < d; ++a) {
+            const int64_t f = upface[(size_t)a * n + c];
+            if (f < 0) continue;
+            const double* F = &A.fblk[(size_t)f * b * b];
+            for (int i = 0; i < b; ++i)
+                for (int j = 0; j < b; ++j)
+                    if (node_coord(i, a, q) != q - 1 && node_coord(j, a, q) != 0 && F[(size_t)i * b + j] != 0.0)
+                        ok = false;
+        }
+    return ok;
+}
+// sparse: store the face blocks in the sparse-face form when they are nodal
+static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, int d, bool with_vals,
+                              bool sparse = false) {
     const int b = A.b, TC = kWG / b, TR = TC * b, P0 = ax_cell_planes(b), TP = ax_tile_planes(b, d);
     const int64_t n = A.n, ntiles = (n + TC - 1) / TC;
     if ((int64_t)axis.size() != A.nf) fail(DGMG_EINVAL, "face axis list does not match the operator");
@@ -949,25 +980,44 @@ static AxisEll build_axis_ell(const BlockOp& A, const std::vector<int>& axis, in
         upface[(size_t)a * n + p] = f;
     }
     if (!with_vals) return E;
+    E.sparse = sparse && faces_are_nodal(A, upface, d);
     // per tile: the cell blocks' symmetric planes (plane k, row (cell, i):
-    // entry [i][(i + k) mod b]), then b planes per upper face (plane j, row
-    // (cell, i): entry [i][j])
-    E.vals.assign((size_t)ntiles * TP * TR, 0.0);
+    // entry [i][(i + k) mod b]), then per upper face either b planes
+    // (plane j, row (cell, i): entry [i][j]) or the sparse-face form
+    const int q = ax_nodes_1d(b, d), nF = b / q;
+    const int64_t TS = E.sparse ? ax_sparse_tile_values(b, d, TC) : (int64_t)TP * TR;
+    const int64_t AXS = ax_sparse_axis_values(b, d, TC);
+    E.vals.assign((size_t)(ntiles * TS), 0.0);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
-        const int64_t t = c / TC;
-        const size_t row0 = (size_t)(c - t * TC) * b;
+        const int64_t t = c / TC, lc = c - t * TC;
+        const size_t row0 = (size_t)lc * b;
         const double* D = &A.diag[(size_t)c * b * b];
         for (int k = 0; k < P0; ++k)
             for (int i = 0; i < b; ++i)
-                E.vals[((size_t)t * TP + k) * TR + row0 + i] = D[(size_t)i * b + (i + k) % b];
+                E.vals[(size_t)(t * TS) + (size_t)k * TR + row0 + i] = D[(size_t)i * b + (i + k) % b];
         for (int a = 0; a < d; ++a) {
             const int64_t f = upface[(size_t)a * n + c];
             if (f < 0) continue;
             const double* F = &A.fblk[(size_t)f * b * b];
-            for (int j = 0; j < b; ++j)
-                for (int i = 0; i < b; ++i)
-                    E.vals[((size_t)t * TP + P0 + (size_t)a * b + j) * TR + row0 + i] = F[(size_t)i * b + j];
+            if (E.sparse) {
+                const size_t ab = (size_t)(t * TS) + (size_t)P0 * TR + (size_t)(a * AXS);
+                for (int j = 0; j < b; ++j) {
+                    const int cj = node_coord(j, a, q), tj = node_tan(j, a, q);
+                    if (cj == 0) {
+                        for (int i = 0; i < b; ++i) E.vals[ab + (size_t)tj * TR + row0 + i] = F[(size_t)i * b + j];
+                    } else {
+                        const size_t sp = ab + (size_t)nF * TR + (size_t)(tj * (q - 1) + cj - 1) * TC * nF;
+                        for (int i = 0; i < b; ++i)
+                            if (node_coord(i, a, q) == q - 1)
+                                E.vals[sp + (size_t)lc * nF + node_tan(i, a, q)] = F[(size_t)i * b + j];
+                    }
+                }
+            } else {
+                for (int j = 0; j < b; ++j)
+                    for (int i = 0; i < b; ++i)
+                        E.vals[(size_t)(t * TS) + (size_t)(P0 + a * b + j) * TR + row0 + i] = F[(size_t)i * b + j];
+            }
         }
     }
     return E;
@@ -1230,8 +1280,12 @@ static void upload_level(dgmg_solver* s, int l) {
             L.mf32 = mf_constants<float>(s, re, s->upload(convert<float>(s->mf_D)));
         }
     } else if (ax || axc) {
-        AxisEll E = axc ? std::move(Ec) : build_axis_ell(A, s->axis0, s->dim, true);
+        // single-column solvers store nodal fine face blocks in sparse form
+        // (the multi-column kernels read whole blocks)
+        const bool sparse = !axc && s->max_rhs <= 1 && s->fine_layout != DGMG_LAYOUT_AXIS_ELL_DENSE;
+        AxisEll E = axc ? std::move(Ec) : build_axis_ell(A, s->axis0, s->dim, true, sparse);
         L.ax = true;
+        L.sf = E.sparse;
         L.up = s->upload(E.up);
         L.lo = s->upload(E.lo);
         L.vals64 = s->upload(E.vals);
@@ -1597,7 +1651,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
         fail(DGMG_EINVAL, "max_rhs must be 0, 1 or DGMG_MULTI_RHS");
     s->max_rhs = mg->max_rhs > 1 ? mg->max_rhs : 1;
     s->mfma = mg->mfma ? 1 : 0;
-    if (mg->fine_layout < DGMG_LAYOUT_AUTO || mg->fine_layout > DGMG_LAYOUT_MATRIX_FREE)
+    if (mg->fine_layout < DGMG_LAYOUT_AUTO || mg->fine_layout > DGMG_LAYOUT_AXIS_ELL_DENSE)
         fail(DGMG_EINVAL, "unknown fine_layout");
     if (mg->fine_layout == DGMG_LAYOUT_MATRIX_FREE && mg->max_rhs > 1)
         fail(DGMG_EUNSUPPORTED, "the matrix-free fine level has no multi-column kernels");
@@ -1819,6 +1873,7 @@ int dgmg_setup_levels(const dgmg_hierarchy* h, const dgmg_disc* disc, const dgmg
     s->info.fine_layout = s->info.level_layout[0];
     for (int l = 0; l < s->L; ++l) s->info.prolong_types[l] = s->on_device ? s->lv[l].ntypes : 0;
     for (int l = 0; l < s->L; ++l) s->info.level_grouped[l] = s->on_device && s->lv[l].cmap ? 1 : 0;
+    s->info.sparse_faces = s->on_device && s->L > 0 && s->lv[0].sf ? 1 : 0;
     *out = guard.release();
     return DGMG_OK;
     API_END
