@@ -313,9 +313,12 @@ struct ProfScope {
 template <typename... KA, typename... A>
 static void klaunch(const ProfScope& ps, void (*k)(KA...), dim3 grid, dim3 block, hipStream_t st,
                     A&&... a) {
-    hipEvent_t e0 = ps.on ? ps.s->prof_ev[ps.idx].first : nullptr;
-    hipEvent_t e1 = ps.on ? ps.s->prof_ev[ps.idx].second : nullptr;
-    hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, static_cast<KA>(a)...);
+    if (!ps.on) {
+        hipLaunchKernelGGL(k, grid, block, 0, st, static_cast<KA>(a)...);
+        return;
+    }
+    hipExtLaunchKernelGGL(k, grid, block, 0, st, ps.s->prof_ev[ps.idx].first, ps.s->prof_ev[ps.idx].second, 0,
+                          static_cast<KA>(a)...);
 }
 enum { PK_CHEB_STEP = 0, PK_RESIDUAL = 1, PK_APPLY = 2, PK_RESTRICT = 3, PK_PROLONG = 4,
        PK_COARSE = 5 };
