@@ -483,7 +483,7 @@ def measure(workload, pr, args, steps, warmup, nrhs):
     b_ = info["b"]
     achieved = alg / in_run_s / 1e9
     if nrhs == 1:
-        kname = f"k_cheb_step<float,{b_},{info['fine_layout']}> (level 0)"
+        kname = f"k_cheb_step<float,{b_},{info['fine_layout']}{', sparse faces' if info.get('sparse_faces') else ''}> (level 0)"
     elif mfma:
         kname = f"k_cheb_step_mfma8<{info['fine_layout']}> (level 0, 8 columns, v_mfma_f32_4x4x1f32)"
     else:
