@@ -9,8 +9,8 @@ import scipy.sparse.linalg as spla
 
 from workloads import make_problem
 from workloads.meshes import structured_mesh
-from oracle.assemble import assemble, mass_blocks, system_matrix, unpack_sym
-from oracle.basis import tensor_basis, tensor_rule, cell_geometry
+from oracle.assemble import assemble, interior_faces, mass_blocks, system_matrix, unpack_sym
+from oracle.basis import multi_index, tensor_basis, tensor_rule, cell_geometry
 from oracle.hierarchy import fine_nodes_level0
 
 CASES = [("c1", 6), ("c2", 6), ("c3", 3)]
@@ -148,3 +148,27 @@ def test_manufactured_solution_rates(p, jit):
         errs.append(_l2_error(pr, U, fn))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] > p + 1 - 0.15, (rates, errs)
+
+
+@pytest.mark.parametrize("name,kw", [("c1", dict(n=5)), ("c2", dict(n=5)), ("c2", dict(n=4, p=3)),
+                                     ("c3", dict(n=3)), ("c3", dict(n=3, p=1))])
+def test_face_blocks_vanish_off_the_face_nodes(name, kw):
+    # Section 3: every face term of a_h has the trace of the test or of the
+    # trial function as a factor, and a Lagrange function on Gauss-Lobatto
+    # nodes has a zero trace on a face unless its node lies on that face.  So
+    # the block A[plus, minus] of an interior face (plus sees it at xi_a = 1,
+    # minus at xi_a = 0) is exactly zero outside the rows of plus's face nodes
+    # and the columns of minus's face nodes; the rest carries the coupling.
+    pr = _prob(name, **kw)
+    _, A = assemble(pr)
+    A = A.tocsr()
+    d, p = pr["xyz"].shape[1], pr["p"]
+    b = (p + 1) ** d
+    mi = multi_index(p, d)
+    plus, minus, axis = interior_faces(pr["cell_vtx"], d)
+    assert len(plus) > 0
+    for K, Nb, a in zip(plus, minus, axis):
+        blk = A[K * b:(K + 1) * b, Nb * b:(Nb + 1) * b].toarray()
+        allowed = (mi[:, a] == p)[:, None] | (mi[:, a] == 0)[None, :]
+        assert np.all(blk[~allowed] == 0.0)
+        assert np.count_nonzero(blk[allowed]) > 0.5 * allowed.sum()
