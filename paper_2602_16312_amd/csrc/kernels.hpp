@@ -238,6 +238,10 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int c
     constexpr int KG = B > 27 ? 8 : (sizeof(T) == 8 ? 3 : P0);
     const int base = ((int)threadIdx.x & 63) - i;   // lane of the cell's row 0 (whole-wave cells)
     const T* __restrict__ A = L.vals + (size_t)tile * TSTRIDE + ri;
+    // lower neighbours first: their blocks and values are the longest chain
+    int lo_nb[D];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) lo_nb[ax] = L.lo[(size_t)ax * L.n + cell];
     T acc = 0;
     // cell block: plane k holds A[i][i+k] at row i.  Row i takes it times
     // x[i+k]; the symmetric entry A[i][i-k] is the plane's value at row i-k,
@@ -328,7 +332,7 @@ __device__ __forceinline__ T ax_row_apply(const LevelArgs<T>& L, int tile, int c
     }
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-        const int c0 = L.lo[(size_t)ax * L.n + cell];
+        const int c0 = lo_nb[ax];
         if (c0 >= 0) {
             const int t0 = c0 / TC, l0 = c0 - t0 * TC;
             T a[B], v[B];
