@@ -544,17 +544,27 @@ __global__ __launch_bounds__(kWG) void k_cheb_step(LevelArgs<T> L, const T* __re
                                                    int last, const T* __restrict__ bj) {
     DGMG_TILE_THREAD_M(T, B, LY == LY_TILE, DGMG_TILE_WW(B, LY))
     T* lds_free = nullptr;
+    // FP32: the row's own operands are requested before the product, so that
+    // their loads overlap its memory chain (FP64 keeps its register count;
+    // for 3D Q1 blocks the three registers would cost a wave per SIMD)
+    constexpr bool EARLY = sizeof(T) == 4 && B != 8;
+    T r0 = 0, x0 = 0, di = 0;
+    if (EARLY && active) {
+        r0 = r[t];
+        if (!assign) x0 = x[t];
+        if constexpr (!BJ) di = L.dinv[t];
+    }
     const T a = row_apply<T, B, false, LY>(L, tile, lc, cell, ri, ti, active, d, nullptr,
                                            BJ ? &lds_free : nullptr);
     T rr = 0;
-    if (active) rr = r[t] - a;
+    if (active) rr = (EARLY ? r0 : r[t]) - a;
     // the block term stages the workgroup's residuals in LDS (all threads)
     T zb = 0;
     if constexpr (BJ) zb = block_jacobi_row<T, B, LY>(bj, rr, lc, cell, ri, ti, active, lds_free);
     if (!active) return;
     const T dt = d[t];
-    const T x1 = assign ? dt : x[t] + dt;
-    const T dnew = cd * dt + cr * (BJ ? zb : L.dinv[t] * rr);
+    const T x1 = assign ? dt : (EARLY ? x0 : x[t]) + dt;
+    const T dnew = cd * dt + cr * (BJ ? zb : (EARLY ? di : L.dinv[t]) * rr);
     if (last) {
         x[t] = x1 + dnew;
     } else {
